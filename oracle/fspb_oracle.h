@@ -1,0 +1,131 @@
+/*
+ * fspb_oracle.h -- plain FP64 CPU oracle of the finite-size pencil beam dose
+ * method with 3D density correction (DC-FSPB).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library.  It
+ * is not part of the product path: only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it.  It shares no code, header,
+ * table or constant with the GPU library.
+ *
+ * What it computes (Gu et al., "GPU-based finite-size pencil beam algorithm
+ * with 3D-density correction"):
+ *   smoothed density      Section 2.1 and Algorithm A1 step 1
+ *   beamlet frame, theta  Eq. 2 definitions and Algorithm A1 step 3
+ *   ray trace, tables     Algorithm A1 steps 4-6, uniform sampling of Sec. 2.2
+ *   pair dose D_i(r)      Eqs. 2-4 and the density corrections of Sec. 2.1,
+ *                         inside the 5 cm ROI cylinder of Algorithm A1
+ *   dose superposition    Eq. 1
+ *   adjoint g = D^T w     (transpose of Eq. 1; not in the paper)
+ *
+ * Every value is computed in double precision, brute force over every voxel
+ * and every beamlet, in a fixed summation order.  Parity status of each
+ * function is listed at its declaration.
+ */
+#ifndef FSPB_ORACLE_H
+#define FSPB_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double start, step;   /* value i sits at start + i*step */
+    int n;
+    const float* v;       /* host array, read only */
+} orc_table;
+
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;    /* cm */
+    double ox, oy, oz;    /* centre of voxel (0,0,0), cm */
+    const float* rho;     /* [nz][ny][nx], g/cm^3 relative to water */
+} orc_grid;
+
+typedef struct {
+    double gantry, couch; /* rad */
+    double iso[3];        /* cm */
+    double sad;           /* cm */
+    int nbx, nby;
+    double wx, wy;        /* beamlet full width at the isocentre plane */
+    double cx, cy;        /* beamlet grid centre offset at the isocentre plane */
+} orc_beam;
+
+typedef struct {
+    orc_table A;          /* row-major [n_theta][A.n] over radiological depth */
+    int n_theta;
+    double theta_step;    /* theta rows start at 0 */
+    orc_table u1x, u1y, u2x, u2y, w1, w2;   /* vs geometric depth t */
+    orc_table fu1, fu2, fw1, fw2, b1, b2;   /* vs density */
+} orc_tables;
+
+typedef struct {
+    double roi_radius, rho_surface, smooth_sigma, rho_min, rho_max, sample_step;
+    int dc_enabled;
+} orc_options;
+
+/* Ambiguity tolerances: a pair whose ROI or depth test lies this close to
+ * its boundary may be decided either way by a lower-precision implementation. */
+#define ORC_TOL_ROI_REL 1e-4   /* |xp^2+yp^2 - R^2| <= tol * R^2 */
+#define ORC_TOL_T       1e-4   /* |t| <= tol (cm) */
+
+typedef struct orc_ctx orc_ctx;
+
+/* Builds frames and ray-trace tables for every beamlet.  Copies nothing: the
+ * grid and tables must outlive the context.  Returns NULL on bad input. */
+orc_ctx* orc_create(const orc_grid* g, int n_beams, const orc_beam* beams,
+                    const orc_tables* tab, const orc_options* opt);
+void orc_destroy(orc_ctx* c);
+int  orc_n_beamlets(const orc_ctx* c);
+
+/* Eq. 4 penumbra profile p(x, u, x0).  Pinned by quadrature of a box of
+ * half-width x0 against the Laplace density (u/2) exp(-u|x|). */
+double orc_p(double x, double u, double x0);
+
+/* Beamlet frame: out[0..2] source, [3..5] direction, [6..8] lateral x axis,
+ * [9..11] lateral y axis, [12] theta, [13] x0, [14] y0, [15] SAD. */
+void orc_frame(const orc_ctx* c, int i, double out[16]);
+
+/* Ray-trace results of beamlet i.  info[0] hit (1/0), [1] s_in, [2] s_out,
+ * [3] s_entry, [4] k_entry, [5] K (table length), [6] s_exit,
+ * [7] min |rho_k - rho_surface| over samples up to the entry (ambiguity
+ * margin of the entry decision), [8] sample step d, [9] n_samples.
+ * Copies min(K, maxK) table entries to T, W1, W2 when they are non-NULL.
+ * Returns K. */
+int orc_trace(const orc_ctx* c, int i, double info[10], double* T,
+              double* W1, double* W2, int maxK);
+
+/* Smoothed density at one voxel (direct, non-separable 3D sum). */
+double orc_smoothed_at(const orc_ctx* c, long vox);
+/* Smoothed density of the whole grid into out[n_vox]. */
+void orc_smooth_all(const orc_ctx* c, double* out);
+/* Truncation radius (voxels) of the smoothing kernel along each axis. */
+void orc_smooth_radius(const orc_ctx* c, int r[3]);
+
+/* Unit-fluence dose of beamlet i at voxel vox (Eq. 2).  flags (if non-NULL)
+ * gets bit 0 = pair counted (in ROI and t >= 0 and beamlet hits),
+ * bit 1 = ambiguous (close to the ROI or depth boundary).  The returned value
+ * is the would-be contribution for an ambiguous pair even when it is not
+ * counted. */
+double orc_pair(const orc_ctx* c, long vox, int i, int* flags);
+
+/* Dose (Eq. 1) at n voxels listed in vox (or every voxel when vox is NULL, in
+ * which case n must equal the grid size).  amb[k] gets the ambiguity
+ * allowance sum |f_i D_i(r)| over ambiguous pairs; pairs[k] the number of
+ * counted pairs with f_i != 0.  amb and pairs may be NULL. */
+void orc_dose(const orc_ctx* c, const float* fluence, long n, const long* vox,
+              double* dose, double* amb, long long* pairs);
+
+/* Adjoint g_i = sum_r w(r) D_i(r) for the n beamlets listed (all beamlets
+ * when list is NULL and n equals the beamlet count), with allowance
+ * amb_i = sum |w(r) D_i(r)| over ambiguous pairs.  amb may be NULL. */
+void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list,
+                 double* g, double* amb);
+
+/* Number of counted pairs (all beamlets, regardless of fluence) per listed
+ * voxel; vox may be NULL for the whole grid. */
+void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
