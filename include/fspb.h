@@ -1,0 +1,220 @@
+/*
+ * fspb.h -- C ABI of the MI355X (gfx950) finite-size pencil beam dose engine
+ * with 3D density correction (DC-FSPB).
+ *
+ * The method (Gu, Jelen, Li, Jia, Jiang, "GPU-based finite-size pencil beam
+ * algorithm with 3D-density correction for radiotherapy dose calculation"):
+ *   D(r)   = sum_i f_i D_i(r)                                          (Eq. 1)
+ *   D_i(r) = F(x, y, omega, u_x, u_y, x0, y0) A(t_eq, theta) (SAD/|r_a|)^2 (Eq. 2)
+ *   F      = sum_{c=1,2} omega_c p(x, u_cx, x0) p(y, u_cy, y0)         (Eq. 3)
+ *   p      = the exponential penumbra profile of Eq. 4
+ * with the lateral/weight density corrections of Section 2.1, evaluated for
+ * every (voxel, beamlet) pair inside a 5 cm cylinder around the beamlet axis
+ * (Algorithm A1), using per-beamlet radiological-depth and weight-drift
+ * tables sampled uniformly along the axis (Section 2.2).
+ *
+ * Conventions
+ *   Units: cm, radians, g/cm^3 relative to water; dose in arbitrary units
+ *   (fluence x table units).
+ *   Voxel grids: float32, [nz][ny][nx] with x fastest; voxel (i,j,k) has its
+ *   centre at (ox + i dx, oy + j dy, oz + k dz).
+ *   Beams: gantry rotates about z; at gantry 0 the source sits at
+ *   iso - SAD*(0,1,0) so the beam travels +y; the couch angle rotates the
+ *   beam about y.  Beamlet (n, m) of a beam (row n along the beam's y axis,
+ *   column m along its x axis) is centred at
+ *   ((m-(nbx-1)/2) wx + cx, (n-(nby-1)/2) wy + cy) in the isocentre plane.
+ *   Fluence order: beam-major, then row n, then column m.
+ *   "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *   null stream).
+ *
+ * Memory ownership
+ *   Pointers marked "device" must point to device memory of the current HIP
+ *   device; pointers marked "host" to host memory.  The library never frees
+ *   caller memory.  A geometry handle owns its own device buffers.
+ *
+ * Errors
+ *   Every int-returning entry point returns FSPB_OK (0) or a negative code;
+ *   fspb_last_error() gives a description of the last failure on the calling
+ *   thread.  On error, output arguments are left untouched (and *out is set
+ *   to NULL for fspb_create_geometry).
+ *
+ * Concurrency
+ *   A handle may be used from one stream at a time.  Distinct handles are
+ *   independent.
+ */
+#ifndef FSPB_H
+#define FSPB_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSPB_OK             0
+#define FSPB_E_ARG         -1   /* invalid argument or inconsistent sizes */
+#define FSPB_E_HIP         -2   /* a HIP runtime call failed */
+#define FSPB_E_NOMEM       -3   /* device or host allocation failed */
+#define FSPB_E_STATE       -4   /* operation not valid for this handle */
+#define FSPB_E_UNSUPPORTED -5   /* no usable gfx950 device */
+
+typedef struct fspb_geometry fspb_geometry;
+
+/* CT density grid (Algorithm A2 step 1 input).  density: device, read only,
+ * n = nx*ny*nz floats; only read during fspb_create_geometry. */
+typedef struct {
+    int nx, ny, nz;
+    float dx, dy, dz;
+    float ox, oy, oz;
+    const float* density;
+} fspb_ct;
+
+/* One beam: gantry/couch angles, isocentre, source-axis distance (Eq. 2) and
+ * its beamlet grid.  wx, wy are the beamlet full widths at the isocentre
+ * plane; the half widths are the x0, y0 of Eq. 4. */
+typedef struct {
+    float gantry, couch;
+    float iso[3];
+    float sad;
+    int nbx, nby;
+    float wx, wy;
+    float cx, cy;
+} fspb_beam;
+
+/* Uniformly sampled table: v[i] (host) is the value at start + i*step.
+ * Lookups interpolate linearly and hold the end values outside the range. */
+typedef struct {
+    float start, step;
+    int n;
+    const float* v;
+} fspb_table1d;
+
+/* Commissioned model parameters (Section 2.1).
+ *   A        2-D table [n_theta][A.n]: row r is A(t_eq, r*theta_step) over
+ *            radiological depth on A's grid; looked up bilinearly.
+ *   u1x..w2  water parameters vs geometric depth t; all six must share one
+ *            grid (start, step, n).
+ *   fu1,fu2  penumbra widening factors vs density: u1 = fu1(rho) u1^w,
+ *            u2 = fu2(rho_hat) u2^w.
+ *   fw1,fw2  weight factors vs smoothed density.
+ *   b1,b2    weight drift per cm vs density:
+ *            omega_c = fw_c(rho_hat) (omega_c^w(t) + int_0^t b_c(rho) dt').
+ * All host pointers; copied during fspb_create_geometry. */
+typedef struct {
+    fspb_table1d A;
+    int n_theta;
+    float theta_step;
+    fspb_table1d u1x, u1y, u2x, u2y, w1, w2;
+    fspb_table1d fu1, fu2, fw1, fw2, b1, b2;
+} fspb_tables;
+
+/* Options.  Zero-initialised fields take the defaults in brackets. */
+typedef struct {
+    float roi_radius;    /* ROI cylinder radius [5 cm] (Algorithm A1 footnote) */
+    float rho_surface;   /* body-surface density threshold [0.5] */
+    float smooth_sigma;  /* Gaussian width of the smoothed density [0.5 cm] */
+    float rho_min;       /* commissioned density range [0.1] */
+    float rho_max;       /*                            [2.0] */
+    float sample_step;   /* ray sampling step [min(dx,dy,dz)/2] (Section 2.2) */
+    int dc_enabled;      /* 1: 3D density correction, 0: plain FSPB (A1 without step 11) */
+    int flags;           /* reserved, must be 0 */
+} fspb_options;
+
+typedef struct {
+    int n_beams, n_beamlets;
+    int nx, ny, nz;
+    long long n_vox;
+    int k_stride;          /* samples reserved per beamlet depth table */
+    int k_max;             /* longest depth table actually used */
+    int n_hit;             /* beamlets whose axis enters the body */
+    int n_entry_ambiguous; /* beamlets whose entrance sample lies within 1e-9 of rho_surface */
+    int smooth_radius[3];  /* Gaussian truncation radius in voxels */
+    float sample_step;
+    int dc_enabled;
+    long long device_bytes;
+} fspb_info;
+
+/* Per-beamlet geometry and tables, for inspection and tests. */
+typedef struct {
+    int hit;               /* 1 if the axis enters the body */
+    int k_entry;           /* entrance sample index from the grid-box entry */
+    int n_samples;         /* samples from the box entry to the end of the table */
+    int K;                 /* depth-table length (samples from the entrance) */
+    double s_in;           /* box entry distance from the source */
+    double s_entry;        /* entrance distance from the source */
+    double theta;          /* angle to the beam's central axis */
+    double src[3], dir[3], ex[3], ey[3];
+    double entry_margin;   /* min |rho_k - rho_surface| over samples up to the entrance */
+} fspb_beamlet_info;
+
+/* Builds the per-plan geometry on the device (Algorithm A2 steps 2-5):
+ * smoothed density and per-voxel correction factors (DC only), beamlet
+ * frames and angles, entrance points, and radiological-depth and
+ * weight-drift tables.  Synchronises the stream before returning, so the
+ * caller may free ct->density afterwards.
+ *   ct      host struct; ct->density device.
+ *   beams   host array [n_beams].
+ *   tables  host struct with host arrays (copied).
+ *   opts    host struct or NULL for the defaults.
+ *   out     receives the handle (NULL on error).
+ * Errors: FSPB_E_ARG for empty or inconsistent inputs (non-positive sizes,
+ * source inside the grid box, depth tables on different grids, nonzero
+ * flags), FSPB_E_NOMEM, FSPB_E_HIP, FSPB_E_UNSUPPORTED. */
+int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
+                         const fspb_tables* tables, const fspb_options* opts,
+                         void* stream, fspb_geometry** out);
+
+/* Dose superposition (Eq. 1 over Eqs. 2-4, Algorithm A2 step 6).
+ *   fluence  device [n_beamlets]; beamlets with f_i == 0 are skipped.
+ *   dose     device [n_vox], overwritten (every voxel is written once).
+ * Asynchronous on stream.  Uses the density correction iff it is enabled on
+ * the handle (see fspb_set_dc). */
+int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream);
+
+/* Adjoint of fspb_forward: grad_i = sum_r voxel_weight(r) D_i(r) for every
+ * beamlet, including those with zero fluence.  For L = sum w (D - D0)^2 pass
+ * voxel_weight = 2 w (D - D0) to get dL/df.  Deterministic (fixed reduction
+ * order, no atomics).
+ *   voxel_weight  device [n_vox].
+ *   grad          device [n_beamlets], overwritten.
+ * Asynchronous on stream. */
+int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream);
+
+/* Number of evaluated pairs: voxel-beamlet pairs inside the ROI with t >= 0
+ * for beamlets that enter the body; with fluence non-NULL, only beamlets with
+ * f_i != 0 (the pairs fspb_forward evaluates).
+ *   fluence  device [n_beamlets] or NULL.
+ *   counts   device int [n_vox] or NULL; per-voxel counts.
+ *   total    host; receives the sum.  The call synchronises the stream. */
+int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
+                     unsigned long long* total, void* stream);
+
+/* Switches the forward/adjoint between the density-corrected model (1) and
+ * plain FSPB (0).  Enabling DC on a handle created with dc_enabled = 0
+ * returns FSPB_E_STATE. */
+int fspb_set_dc(fspb_geometry* g, int enabled);
+
+/* Plan summary (host struct). */
+int fspb_geometry_info(const fspb_geometry* g, fspb_info* info);
+
+/* Copies the smoothed density (device [n_vox]) of a DC handle. */
+int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream);
+
+/* Copies beamlet i's geometry (host struct) and up to max_k entries of its
+ * depth tables T (radiological depth), W1, W2 (weight drift) into host
+ * arrays (each may be NULL).  Synchronous. */
+int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info,
+                 float* T, float* W1, float* W2, int max_k);
+
+/* Frees the handle and its device buffers.  NULL-safe.  Waits for work
+ * queued on the handle's buffers to finish. */
+void fspb_destroy(fspb_geometry* g);
+
+/* Static description of an error code. */
+const char* fspb_error_string(int code);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* fspb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSPB_H */

@@ -1,0 +1,120 @@
+"""ctypes binding of libfspb.so (the C ABI in include/fspb.h).
+
+Argument marshalling only: every step of the dose computation runs in the
+library's HIP kernels.  Importing this module fails loudly when the library
+has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = Path(os.environ.get("FSPB_LIBRARY", PKG / "libfspb.so"))
+
+FSPB_OK = 0
+FSPB_E_ARG = -1
+FSPB_E_HIP = -2
+FSPB_E_NOMEM = -3
+FSPB_E_STATE = -4
+FSPB_E_UNSUPPORTED = -5
+
+
+class fspb_ct(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_float), ("dy", C.c_float), ("dz", C.c_float),
+                ("ox", C.c_float), ("oy", C.c_float), ("oz", C.c_float),
+                ("density", C.c_void_p)]
+
+
+class fspb_beam(C.Structure):
+    _fields_ = [("gantry", C.c_float), ("couch", C.c_float), ("iso", C.c_float * 3),
+                ("sad", C.c_float), ("nbx", C.c_int), ("nby", C.c_int),
+                ("wx", C.c_float), ("wy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class fspb_table1d(C.Structure):
+    _fields_ = [("start", C.c_float), ("step", C.c_float), ("n", C.c_int),
+                ("v", C.POINTER(C.c_float))]
+
+
+class fspb_tables(C.Structure):
+    _fields_ = [("A", fspb_table1d), ("n_theta", C.c_int), ("theta_step", C.c_float)] + [
+        (n, fspb_table1d) for n in ("u1x", "u1y", "u2x", "u2y", "w1", "w2",
+                                    "fu1", "fu2", "fw1", "fw2", "b1", "b2")]
+
+
+class fspb_options(C.Structure):
+    _fields_ = [("roi_radius", C.c_float), ("rho_surface", C.c_float),
+                ("smooth_sigma", C.c_float), ("rho_min", C.c_float), ("rho_max", C.c_float),
+                ("sample_step", C.c_float), ("dc_enabled", C.c_int), ("flags", C.c_int)]
+
+
+class fspb_info(C.Structure):
+    _fields_ = [("n_beams", C.c_int), ("n_beamlets", C.c_int), ("nx", C.c_int),
+                ("ny", C.c_int), ("nz", C.c_int), ("n_vox", C.c_longlong),
+                ("k_stride", C.c_int), ("k_max", C.c_int), ("n_hit", C.c_int),
+                ("n_entry_ambiguous", C.c_int), ("smooth_radius", C.c_int * 3),
+                ("sample_step", C.c_float), ("dc_enabled", C.c_int),
+                ("device_bytes", C.c_longlong)]
+
+
+class fspb_beamlet_info(C.Structure):
+    _fields_ = [("hit", C.c_int), ("k_entry", C.c_int), ("n_samples", C.c_int), ("K", C.c_int),
+                ("s_in", C.c_double), ("s_entry", C.c_double), ("theta", C.c_double),
+                ("src", C.c_double * 3), ("dir", C.c_double * 3), ("ex", C.c_double * 3),
+                ("ey", C.c_double * 3), ("entry_margin", C.c_double)]
+
+
+# name -> (restype, argtypes); the list of every symbol include/fspb.h declares
+SIGNATURES = {
+    "fspb_create_geometry": (C.c_int, [C.POINTER(fspb_ct), C.c_int, C.POINTER(fspb_beam),
+                                       C.POINTER(fspb_tables), C.POINTER(fspb_options),
+                                       C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fspb_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_count_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_ulonglong), C.c_void_p]),
+    "fspb_set_dc": (C.c_int, [C.c_void_p, C.c_int]),
+    "fspb_geometry_info": (C.c_int, [C.c_void_p, C.POINTER(fspb_info)]),
+    "fspb_smoothed_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_beamlet": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(fspb_beamlet_info),
+                               C.POINTER(C.c_float), C.POINTER(C.c_float),
+                               C.POINTER(C.c_float), C.c_int]),
+    "fspb_destroy": (None, [C.c_void_p]),
+    "fspb_error_string": (C.c_char_p, [C.c_int]),
+    "fspb_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads libfspb.so; raises if it is missing (build it with
+    ``python -m paper_1103_1164_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} not found: build the HIP library first "
+                              "(python -m paper_1103_1164_amd.build)")
+        L = C.CDLL(str(LIB_PATH))
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class FspbError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = load()
+        msg = L.fspb_last_error().decode() or L.fspb_error_string(code).decode()
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+def check(code: int, where: str) -> None:
+    if code != FSPB_OK:
+        raise FspbError(code, where)

@@ -1,0 +1,306 @@
+// dose.hip -- the dose superposition (Eq. 1 over Eqs. 2-4; Algorithm A2
+// kernel 5), its transpose, and the evaluated-pair count, for gfx950.
+//
+// Forward: voxel-major.  A wavefront owns a 4x4x4 brick of voxels (one per
+// lane).  For each beam it projects its voxels onto the isocentre plane,
+// reduces the projections across the wave, and visits only the rectangle of
+// beamlets whose 5 cm ROI cylinder can reach the brick.  Beamlet descriptors
+// and fluences are wave-uniform (scalar loads); every lane then tests its own
+// voxel exactly and evaluates the pair in FP32.  Each voxel is written once:
+// no atomics, and the result does not depend on scheduling.
+//
+// Adjoint: beamlet-major.  A workgroup owns one beamlet.  It walks the grid
+// row by row (rows along x); for each row it solves for the x-interval that
+// can lie inside the ROI past the entrance, compacts the intervals of 256 rows
+// with a block scan, and spreads the voxels of those intervals over its lanes.
+// Partial sums are reduced in a fixed order, so the gradient is deterministic.
+#include "kernels.h"
+#include "pair.h"
+
+#include <float.h>
+
+namespace fspb {
+
+__device__ __forceinline__ float wave_min(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+__device__ __forceinline__ float wave_sum(float x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Voxel centre relative to P0; identical in every kernel so that forward,
+// adjoint and count take the same pair decisions.
+__device__ __forceinline__ void voxel_q(const PlanConst& P, int i, int j, int k, float& qx,
+                                        float& qy, float& qz) {
+    qx = fmaf((float)i, P.dx, P.qx0);
+    qy = fmaf((float)j, P.dy, P.qy0);
+    qz = fmaf((float)k, P.dz, P.qz0);
+}
+
+// Depth below the entrance and lateral offsets of a voxel for one beamlet,
+// and the pair test of Algorithm A1 step 8 (inside the ROI cylinder, t >= 0).
+__device__ __forceinline__ bool pair_coords(const BeamletDesc& d, const PlanConst& P, float qx,
+                                            float qy, float qz, float& t, float& xp, float& yp) {
+    t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
+    xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
+    yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
+    return (t >= 0.0f) && (fmaf(xp, xp, yp * yp) <= P.R2);
+}
+
+// ---------------------------------------------------------------------------
+template <bool DC, bool COUNT>
+__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const float* __restrict__ fluence,
+                                                    float* __restrict__ dose,
+                                                    int* __restrict__ counts) {
+    const PlanConst& P = a.P;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so
+    // give each XCD one contiguous run of bricks (a z-slab) to keep its L2
+    // working set (the beamlet tables of a band of beamlet rows) small.
+    const int per = P.n_blocks >> 3;
+    const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int brick = blk * 4 + wid;
+    const int n_bricks = P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
+    if (brick >= n_bricks) return;
+    const int bx = brick % P.n_bricks_x;
+    const int by = (brick / P.n_bricks_x) % P.n_bricks_y;
+    const int bz = brick / (P.n_bricks_x * P.n_bricks_y);
+    const int i = bx * 4 + (lane & 3), j = by * 4 + ((lane >> 2) & 3), k = bz * 4 + (lane >> 4);
+    const bool valid = (i < P.nx) && (j < P.ny) && (k < P.nz);
+    const long v = ((long)k * P.ny + j) * P.nx + i;
+    float qx, qy, qz;
+    voxel_q(P, i, j, k, qx, qy, qz);
+    float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    if (DC && valid) fac = a.fac[v];
+
+    float acc = 0.0f;
+    int cnt = 0;
+    for (int b = 0; b < P.n_beams; ++b) {
+        const BeamDesc& B = a.beams[b];
+        // isocentre-plane projection of the brick's voxels
+        float vx = qx - B.src[0], vy = qy - B.src[1], vz = qz - B.src[2];
+        float z = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
+        float X = fmaf(vx, B.ex[0], fmaf(vy, B.ex[1], vz * B.ex[2]));
+        float Y = fmaf(vx, B.ey[0], fmaf(vy, B.ey[1], vz * B.ey[2]));
+        float s = B.sad / z;
+        float pa = X * s, pb = Y * s;
+        float amin = wave_min(valid ? pa : FLT_MAX), amax = wave_max(valid ? pa : -FLT_MAX);
+        float bmin = wave_min(valid ? pb : FLT_MAX), bmax = wave_max(valid ? pb : -FLT_MAX);
+        float zmin = wave_min(valid ? z : FLT_MAX);
+        // A voxel inside beamlet (n,m)'s ROI lies within R / cos(theta) of its
+        // axis in the plane normal to the central axis; scaled to the
+        // isocentre plane that is at most pad_scale / z.
+        float pad = B.pad_scale / zmin * 1.0001f + 1e-3f;
+        float fm0 = fmaxf((amin - pad - B.a0) / B.wx, -1.0f);
+        float fm1 = fminf((amax + pad - B.a0) / B.wx, (float)B.nbx);
+        float fn0 = fmaxf((bmin - pad - B.b0) / B.wy, -1.0f);
+        float fn1 = fminf((bmax + pad - B.b0) / B.wy, (float)B.nby);
+        const int m_lo = uniform(max((int)ceilf(fm0), 0));
+        const int m_hi = uniform(min((int)floorf(fm1), B.nbx - 1));
+        const int n_lo = uniform(max((int)ceilf(fn0), 0));
+        const int n_hi = uniform(min((int)floorf(fn1), B.nby - 1));
+        const int first = uniform(B.first), nbx = uniform(B.nbx);
+        float accb = 0.0f;
+        for (int n = n_lo; n <= n_hi; ++n) {
+            for (int m = m_lo; m <= m_hi; ++m) {
+                const int ib = first + n * nbx + m;
+                const float fi = fluence ? fluence[ib] : 1.0f;
+                if (fi == 0.0f) continue;
+                const BeamletDesc& d = a.bl[ib];
+                if (!d.hit) continue;
+                float t, xp, yp;
+                bool act = valid && pair_coords(d, P, qx, qy, qz, t, xp, yp);
+                if (COUNT) {
+                    cnt += act ? 1 : 0;
+                    continue;
+                }
+                if (!__any(act)) continue;
+                if (act)
+                    accb = fmaf(fi, pair_dose<DC>(t, xp, yp, d, fac, P, a.dtab, a.atab, a.tT, a.tW),
+                                accb);
+            }
+        }
+        acc += accb;
+    }
+    if (valid) {
+        if (COUNT)
+            counts[v] = cnt;
+        else
+            dose[v] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
+    for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <bool DC>
+__global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, const float* __restrict__ w,
+                                                    float* __restrict__ grad) {
+    __shared__ int s_off[256];
+    __shared__ int s_lo[256];
+    __shared__ int s_wsum[4];
+    __shared__ float s_red[4];
+    const PlanConst& P = a.P;
+    const int ib = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const BeamletDesc& d = a.bl[ib];
+    float acc = 0.0f;
+    if (d.hit) {
+        // along a grid row (fixed j,k) the lateral offsets and the depth are
+        // affine in i: xp = xp0 + i a1, yp = yp0 + i a2, t = t0 + i a3
+        const double a1 = (double)P.dx * d.ex[0], a2 = (double)P.dx * d.ey[0],
+                     a3 = (double)P.dx * d.d[0];
+        const double A = a1 * a1 + a2 * a2;
+        const double R2s = (double)P.R2 * (1.0 + 1e-4);
+        const double t_slack = 1e-3;
+        const int n_rows = P.ny * P.nz;
+        for (int r0 = 0; r0 < n_rows; r0 += 256) {
+            const int row = r0 + tid;
+            int lo = 0, len = 0;
+            if (row < n_rows) {
+                const int j = row % P.ny, k = row / P.ny;
+                float qx, qy, qz;
+                voxel_q(P, 0, j, k, qx, qy, qz);
+                double xp0 = (double)qx * d.ex[0] + (double)qy * d.ex[1] + (double)qz * d.ex[2] + d.c_x;
+                double yp0 = (double)qx * d.ey[0] + (double)qy * d.ey[1] + (double)qz * d.ey[2] + d.c_y;
+                double t0 = (double)qx * d.d[0] + (double)qy * d.d[1] + (double)qz * d.d[2] + d.c_t;
+                double flo = -1.0, fhi = (double)P.nx;
+                bool empty = false;
+                double C = xp0 * xp0 + yp0 * yp0 - R2s;
+                if (A < 1e-20) {
+                    empty = C > 0.0;
+                } else {
+                    double B = 2.0 * (xp0 * a1 + yp0 * a2);
+                    double disc = B * B - 4.0 * A * C;
+                    if (disc < 0.0) {
+                        empty = true;
+                    } else {
+                        double sq = sqrt(disc);
+                        flo = fmax(flo, (-B - sq) / (2.0 * A) - 1.0);
+                        fhi = fmin(fhi, (-B + sq) / (2.0 * A) + 1.0);
+                    }
+                }
+                if (a3 > 0.0) flo = fmax(flo, (-t_slack - t0) / a3 - 1.0);
+                else if (a3 < 0.0) fhi = fmin(fhi, (-t_slack - t0) / a3 + 1.0);
+                else if (t0 < -t_slack) empty = true;
+                if (!empty && flo <= fhi) {
+                    int ilo = max((int)floor(fmax(flo, -1.0)), 0);
+                    int ihi = min((int)ceil(fmin(fhi, (double)P.nx)), P.nx - 1);
+                    if (ihi >= ilo) {
+                        lo = ilo;
+                        len = ihi - ilo + 1;
+                    }
+                }
+            }
+            // block exclusive scan of the interval lengths
+            int incl = wave_incl_scan_int(len, lane);
+            if (lane == kWave - 1) s_wsum[wid] = incl;
+            __syncthreads();
+            int base = 0, total = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (q < wid) base += s_wsum[q];
+                total += s_wsum[q];
+            }
+            s_off[tid] = base + incl - len;
+            s_lo[tid] = lo;
+            __syncthreads();
+            for (int e = tid; e < total; e += 256) {
+                // the last row whose interval starts at or before item e
+                int rlo = 0, rhi = 255;
+                while (rlo < rhi) {
+                    int mid = (rlo + rhi + 1) >> 1;
+                    if (s_off[mid] <= e) rlo = mid;
+                    else rhi = mid - 1;
+                }
+                const int rr = r0 + rlo;
+                const int i = s_lo[rlo] + (e - s_off[rlo]);
+                const int j = rr % P.ny, k = rr / P.ny;
+                float qx, qy, qz;
+                voxel_q(P, i, j, k, qx, qy, qz);
+                float t, xp, yp;
+                if (pair_coords(d, P, qx, qy, qz, t, xp, yp)) {
+                    const long v = ((long)k * P.ny + j) * P.nx + i;
+                    float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+                    if (DC) fac = a.fac[v];
+                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, d, fac, P, a.dtab, a.atab, a.tT, a.tW),
+                               acc);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) s_red[wid] = acc;
+    __syncthreads();
+    if (tid == 0) grad[ib] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sum_counts_partial(const int* __restrict__ c, long n,
+                                                          unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long s[256];
+    unsigned long long acc = 0;
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256)
+        acc += (unsigned long long)c[q];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void sum_counts_final(const unsigned long long* __restrict__ part, int n,
+                                 unsigned long long* __restrict__ total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long acc = 0;
+        for (int q = 0; q < n; ++q) acc += part[q];
+        *total = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+void launch_forward(const DoseArgs& a, bool dc, const float* fluence, float* dose, hipStream_t s) {
+    dim3 grid(a.P.n_blocks), block(256);
+    if (dc)
+        hipLaunchKernelGGL((dose_forward<true, false>), grid, block, 0, s, a, fluence, dose, (int*)nullptr);
+    else
+        hipLaunchKernelGGL((dose_forward<false, false>), grid, block, 0, s, a, fluence, dose, (int*)nullptr);
+}
+
+void launch_count(const DoseArgs& a, const float* fluence, int* counts, hipStream_t s) {
+    hipLaunchKernelGGL((dose_forward<false, true>), dim3(a.P.n_blocks), dim3(256), 0, s, a,
+                       fluence, (float*)nullptr, counts);
+}
+
+void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
+                    hipStream_t s) {
+    if (dc)
+        hipLaunchKernelGGL((dose_adjoint<true>), dim3(n_beamlets), dim3(256), 0, s, a, w, grad);
+    else
+        hipLaunchKernelGGL((dose_adjoint<false>), dim3(n_beamlets), dim3(256), 0, s, a, w, grad);
+}
+
+void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,
+                       unsigned long long* total, hipStream_t s) {
+    hipLaunchKernelGGL(sum_counts_partial, dim3(n_partial), dim3(256), 0, s, counts, n, partial);
+    hipLaunchKernelGGL(sum_counts_final, dim3(1), dim3(64), 0, s, (const unsigned long long*)partial,
+                       n_partial, total);
+}
+
+}  // namespace fspb

@@ -1,0 +1,656 @@
+// fspb_api.hip -- host side of libfspb: the C ABI of include/fspb.h.
+//
+// Responsibilities: argument validation (pure host, before any HIP call),
+// device buffers owned by the geometry handle, packing of the commissioned
+// tables into the layouts the kernels read, and kernel launches.  All of the
+// method's per-voxel and per-beamlet arithmetic runs in the kernels.
+#include "fspb.h"
+#include "kernels.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+using namespace fspb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FSPB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// Test hook: FSPB_TEST_FAIL_ALLOC=n makes the n-th device allocation after the
+// variable was set (or changed) fail, to exercise the out-of-memory paths.
+int g_alloc_count = 0;
+std::string g_alloc_env;
+
+int dev_alloc(void** p, size_t bytes, size_t* total) {
+    const char* inj = getenv("FSPB_TEST_FAIL_ALLOC");
+    std::string cur = inj ? inj : "";
+    if (cur != g_alloc_env) {
+        g_alloc_env = cur;
+        g_alloc_count = 0;
+    }
+    ++g_alloc_count;
+    if (inj && atoi(inj) == g_alloc_count) {
+        *p = nullptr;
+        return fail(FSPB_E_NOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+    }
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(FSPB_E_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    *total += bytes;
+    return FSPB_OK;
+}
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+int check_table(const fspb_table1d& t, const char* name) {
+    if (t.n < 1 || !t.v) return fail(FSPB_E_ARG, "table %s: needs n >= 1 and values", name);
+    if (!isfinite(t.start) || (t.n > 1 && !finite_pos(t.step)))
+        return fail(FSPB_E_ARG, "table %s: start must be finite and step > 0", name);
+    return FSPB_OK;
+}
+
+}  // namespace
+
+struct fspb_geometry {
+    int device = 0;
+    PlanConst P{};
+    DensTabs dens{};
+    int n_beams = 0, n_beamlets = 0, k_stride = 0;
+    int dc_created = 0, dc_enabled = 0;
+    int smooth_r[3] = {0, 0, 0};
+    float sample_step = 0.0f;
+    size_t device_bytes = 0;
+    // device buffers
+    float* rhohat = nullptr;
+    float4* fac = nullptr;
+    BeamDesc* beams = nullptr;
+    BeamIn* beam_in = nullptr;
+    Frame64* frames = nullptr;
+    BeamletDesc* desc = nullptr;
+    TraceInfo* tinfo = nullptr;
+    float4* dtab = nullptr;
+    float4* atab = nullptr;
+    float* denstab = nullptr;
+    float2* tT = nullptr;
+    float4* tW = nullptr;
+    float* w3 = nullptr;
+    int* counts = nullptr;
+    unsigned long long* partial = nullptr;
+    unsigned long long* total = nullptr;
+    // host copies
+    std::vector<BeamletDesc> h_desc;
+    std::vector<Frame64> h_frames;
+    std::vector<TraceInfo> h_info;
+    int k_max = 0, n_hit = 0, n_amb = 0;
+
+    DoseArgs args() const {
+        DoseArgs a;
+        a.P = P;
+        a.P.dc = dc_enabled;
+        a.beams = beams;
+        a.bl = desc;
+        a.fac = fac;
+        a.dtab = dtab;
+        a.atab = atab;
+        a.tT = tT;
+        a.tW = tW;
+        return a;
+    }
+
+    void release() {
+        void* bufs[] = {rhohat, fac, beams, beam_in, frames, desc, tinfo, dtab, atab,
+                        denstab, tT, tW, w3, counts, partial, total};
+        for (void* b : bufs)
+            if (b) (void)hipFree(b);
+    }
+};
+
+namespace {
+
+int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_tables* t,
+             const fspb_options* o) {
+    if (!ct || !beams || !t) return fail(FSPB_E_ARG, "ct, beams and tables must be non-NULL");
+    if (ct->nx < 1 || ct->ny < 1 || ct->nz < 1)
+        return fail(FSPB_E_ARG, "grid size %dx%dx%d must be positive", ct->nx, ct->ny, ct->nz);
+    if (!finite_pos(ct->dx) || !finite_pos(ct->dy) || !finite_pos(ct->dz))
+        return fail(FSPB_E_ARG, "voxel sizes must be positive");
+    if (!isfinite(ct->ox) || !isfinite(ct->oy) || !isfinite(ct->oz))
+        return fail(FSPB_E_ARG, "grid origin must be finite");
+    if (!ct->density) return fail(FSPB_E_ARG, "ct->density is NULL");
+    long long nv = (long long)ct->nx * ct->ny * ct->nz;
+    if (nv > (1LL << 31) - 1) return fail(FSPB_E_ARG, "grid of %lld voxels exceeds 2^31-1", nv);
+    if (n_beams < 1) return fail(FSPB_E_ARG, "n_beams must be >= 1");
+    long long nbl = 0;
+    for (int b = 0; b < n_beams; ++b) {
+        const fspb_beam& B = beams[b];
+        if (B.nbx < 1 || B.nby < 1) return fail(FSPB_E_ARG, "beam %d: empty beamlet grid", b);
+        if (!finite_pos(B.wx) || !finite_pos(B.wy) || !finite_pos(B.sad))
+            return fail(FSPB_E_ARG, "beam %d: beamlet widths and SAD must be positive", b);
+        if (!isfinite(B.gantry) || !isfinite(B.couch) || !isfinite(B.cx) || !isfinite(B.cy) ||
+            !isfinite(B.iso[0]) || !isfinite(B.iso[1]) || !isfinite(B.iso[2]))
+            return fail(FSPB_E_ARG, "beam %d: angles, offsets and isocentre must be finite", b);
+        nbl += (long long)B.nbx * B.nby;
+    }
+    if (nbl > (1 << 24)) return fail(FSPB_E_ARG, "too many beamlets (%lld)", nbl);
+    const fspb_table1d* all[] = {&t->A, &t->u1x, &t->u1y, &t->u2x, &t->u2y, &t->w1, &t->w2,
+                                 &t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
+    const char* names[] = {"A", "u1x", "u1y", "u2x", "u2y", "w1", "w2",
+                           "fu1", "fu2", "fw1", "fw2", "b1", "b2"};
+    for (int q = 0; q < 13; ++q) {
+        int rc = check_table(*all[q], names[q]);
+        if (rc) return rc;
+    }
+    if (t->n_theta < 1 || (t->n_theta > 1 && !finite_pos(t->theta_step)))
+        return fail(FSPB_E_ARG, "A table: n_theta >= 1 and theta_step > 0 required");
+    const fspb_table1d* dts[] = {&t->u1y, &t->u2x, &t->u2y, &t->w1, &t->w2};
+    for (const fspb_table1d* d : dts)
+        if (d->start != t->u1x.start || d->n != t->u1x.n || (d->n > 1 && d->step != t->u1x.step))
+            return fail(FSPB_E_ARG, "the water tables u1x..w2 must share one depth grid");
+    if (o) {
+        if (o->flags != 0) return fail(FSPB_E_ARG, "options.flags must be 0");
+        if (o->dc_enabled != 0 && o->dc_enabled != 1)
+            return fail(FSPB_E_ARG, "options.dc_enabled must be 0 or 1");
+        if (o->roi_radius < 0 || o->smooth_sigma < 0 || o->sample_step < 0 ||
+            !isfinite(o->roi_radius) || !isfinite(o->smooth_sigma) || !isfinite(o->sample_step) ||
+            !isfinite(o->rho_surface) || !isfinite(o->rho_min) || !isfinite(o->rho_max))
+            return fail(FSPB_E_ARG, "options must be finite and non-negative");
+        if ((o->rho_min != 0 || o->rho_max != 0) && !(o->rho_min < o->rho_max))
+            return fail(FSPB_E_ARG, "options: rho_min must be below rho_max");
+    }
+    // every voxel must lie in front of every source (positive depth along the
+    // central axis), so that the isocentre-plane projection is defined
+    double lo[3] = {ct->ox - 0.5 * ct->dx, ct->oy - 0.5 * ct->dy, ct->oz - 0.5 * ct->dz};
+    double hi[3] = {ct->ox + (ct->nx - 0.5) * ct->dx, ct->oy + (ct->ny - 0.5) * ct->dy,
+                    ct->oz + (ct->nz - 0.5) * ct->dz};
+    for (int b = 0; b < n_beams; ++b) {
+        const fspb_beam& B = beams[b];
+        double phi = B.gantry, psi = B.couch;
+        double c0[3] = {-sin(phi), cos(phi), 0.0};
+        double cax[3] = {cos(psi) * c0[0] + sin(psi) * c0[2], c0[1], -sin(psi) * c0[0] + cos(psi) * c0[2]};
+        double src[3];
+        for (int q = 0; q < 3; ++q) src[q] = B.iso[q] - (double)B.sad * cax[q];
+        for (int c = 0; c < 8; ++c) {
+            double p[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+            double z = (p[0] - src[0]) * cax[0] + (p[1] - src[1]) * cax[1] + (p[2] - src[2]) * cax[2];
+            if (!(z > 1e-3))
+                return fail(FSPB_E_ARG, "beam %d: the grid must lie entirely in front of the source", b);
+        }
+    }
+    return FSPB_OK;
+}
+
+int check_device(int* dev) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
+    }
+    HIP_TRY(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
+                    prop.gcnArchName);
+    return FSPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fspb_error_string(int code) {
+    switch (code) {
+        case FSPB_OK: return "success";
+        case FSPB_E_ARG: return "invalid argument";
+        case FSPB_E_HIP: return "HIP runtime error";
+        case FSPB_E_NOMEM: return "out of memory";
+        case FSPB_E_STATE: return "invalid state for this handle";
+        case FSPB_E_UNSUPPORTED: return "unsupported device";
+        default: return "unknown error";
+    }
+}
+
+const char* fspb_last_error(void) { return g_last_error.c_str(); }
+
+static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
+                       const fspb_tables* t, const fspb_options* opts, hipStream_t s,
+                       fspb_geometry* G) {
+    fspb_options o;
+    if (opts) {
+        o = *opts;
+    } else {
+        memset(&o, 0, sizeof o);
+        o.dc_enabled = 1;
+    }
+    if (o.roi_radius == 0) o.roi_radius = 5.0f;
+    if (o.rho_surface == 0) o.rho_surface = 0.5f;
+    if (o.smooth_sigma == 0) o.smooth_sigma = 0.5f;
+    if (o.rho_min == 0 && o.rho_max == 0) {
+        o.rho_min = 0.1f;
+        o.rho_max = 2.0f;
+    }
+    const double dmin = std::min(std::min((double)ct->dx, (double)ct->dy), (double)ct->dz);
+    double step = o.sample_step > 0 ? (double)o.sample_step : 0.5 * dmin;
+    G->sample_step = (float)step;
+
+    const int nx = ct->nx, ny = ct->ny, nz = ct->nz;
+    const long nv = (long)nx * ny * nz;
+    G->n_beams = n_beams;
+    G->dc_created = G->dc_enabled = o.dc_enabled;
+    int nbl = 0;
+    for (int b = 0; b < n_beams; ++b) nbl += beams[b].nbx * beams[b].nby;
+    G->n_beamlets = nbl;
+
+    // plan reference point: grid centre
+    double P0[3] = {ct->ox + 0.5 * (nx - 1) * ct->dx, ct->oy + 0.5 * (ny - 1) * ct->dy,
+                    ct->oz + 0.5 * (nz - 1) * ct->dz};
+    double L[3] = {nx * (double)ct->dx, ny * (double)ct->dy, nz * (double)ct->dz};
+    double diag = sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+    G->k_stride = (int)floor(diag / step) + 3;
+    if ((long long)G->k_stride * nbl > (1LL << 31) - 1)
+        return fail(FSPB_E_ARG, "depth tables of %d x %d samples exceed 2^31-1", nbl, G->k_stride);
+
+    PlanConst& P = G->P;
+    P.nx = nx;
+    P.ny = ny;
+    P.nz = nz;
+    P.n_beams = n_beams;
+    P.dx = ct->dx;
+    P.dy = ct->dy;
+    P.dz = ct->dz;
+    P.R2 = o.roi_radius * o.roi_radius;
+    P.qx0 = (float)(ct->ox - P0[0]);
+    P.qy0 = (float)(ct->oy - P0[1]);
+    P.qz0 = (float)(ct->oz - P0[2]);
+    P.inv_d = (float)(1.0 / step);
+    P.dt_start = t->u1x.start;
+    P.dt_inv = t->u1x.n > 1 ? (float)(1.0 / t->u1x.step) : 0.0f;
+    P.dt_n = t->u1x.n;
+    P.at_start = t->A.start;
+    P.at_inv = t->A.n > 1 ? (float)(1.0 / t->A.step) : 0.0f;
+    P.at_n = t->A.n;
+    P.a_cols = std::max(t->n_theta - 1, 1);
+    P.dc = o.dc_enabled;
+    P.n_bricks_x = (nx + 3) / 4;
+    P.n_bricks_y = (ny + 3) / 4;
+    P.n_bricks_z = (nz + 3) / 4;
+    long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
+    long blocks = (n_bricks + 3) / 4;
+    P.n_blocks = (int)((blocks + 7) / 8 * 8);
+
+    // ---- host-side table packing -------------------------------------------
+    const int dn = t->u1x.n;
+    std::vector<float4> dtab(3 * (size_t)dn);
+    const fspb_table1d* U[4] = {&t->u1x, &t->u1y, &t->u2x, &t->u2y};
+    auto at = [](const fspb_table1d& tb, int i) { return (double)tb.v[std::min(i, tb.n - 1)]; };
+    for (int j = 0; j < dn; ++j) {
+        float u[4], du[4];
+        for (int q = 0; q < 4; ++q) {
+            u[q] = (float)(at(*U[q], j) * 1.4426950408889634);
+            du[q] = (float)((at(*U[q], j + 1) - at(*U[q], j)) * 1.4426950408889634);
+        }
+        dtab[3 * j + 0] = make_float4(u[0], u[1], u[2], u[3]);
+        dtab[3 * j + 1] = make_float4(du[0], du[1], du[2], du[3]);
+        dtab[3 * j + 2] = make_float4(t->w1.v[j], t->w2.v[j], (float)(at(t->w1, j + 1) - at(t->w1, j)),
+                                      (float)(at(t->w2, j + 1) - at(t->w2, j)));
+    }
+    const int an = t->A.n, nth = t->n_theta, ac = P.a_cols;
+    std::vector<float4> atab((size_t)an * ac);
+    auto A = [&](int r, int j) {
+        return (double)t->A.v[(size_t)std::min(r, nth - 1) * an + std::min(j, an - 1)];
+    };
+    for (int j = 0; j < an; ++j)
+        for (int r = 0; r < ac; ++r)
+            atab[(size_t)j * ac + r] = make_float4((float)A(r, j), (float)A(r + 1, j),
+                                                   (float)(A(r, j + 1) - A(r, j)),
+                                                   (float)(A(r + 1, j + 1) - A(r + 1, j)));
+    const fspb_table1d* D[6] = {&t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
+    DTab* DT[6] = {&G->dens.fu1, &G->dens.fu2, &G->dens.fw1, &G->dens.fw2, &G->dens.b1, &G->dens.b2};
+    std::vector<float> dens;
+    for (int q = 0; q < 6; ++q) {
+        DT[q]->start = D[q]->start;
+        DT[q]->step = D[q]->n > 1 ? D[q]->step : 1.0f;
+        DT[q]->inv_step = D[q]->n > 1 ? (float)(1.0 / D[q]->step) : 0.0f;
+        DT[q]->n = D[q]->n;
+        DT[q]->off = (int)dens.size();
+        dens.insert(dens.end(), D[q]->v, D[q]->v + D[q]->n);
+    }
+    G->dens.rho_min = o.rho_min;
+    G->dens.rho_max = o.rho_max;
+
+    // beams: FP64 inputs of the setup kernel and FP32 culling descriptors
+    std::vector<BeamIn> bin(n_beams);
+    std::vector<BeamDesc> bd(n_beams);
+    int first = 0;
+    for (int b = 0; b < n_beams; ++b) {
+        const fspb_beam& B = beams[b];
+        BeamIn& I = bin[b];
+        I.gantry = B.gantry;
+        I.couch = B.couch;
+        for (int q = 0; q < 3; ++q) I.iso[q] = B.iso[q];
+        I.sad = B.sad;
+        I.wx = B.wx;
+        I.wy = B.wy;
+        I.cx = B.cx;
+        I.cy = B.cy;
+        I.nbx = B.nbx;
+        I.nby = B.nby;
+        I.first = first;
+        double phi = B.gantry, psi = B.couch, cp = cos(psi), sp = sin(psi);
+        double c0[3] = {-sin(phi), cos(phi), 0.0}, e0[3] = {cos(phi), sin(phi), 0.0};
+        double cax[3] = {cp * c0[0] + sp * c0[2], c0[1], -sp * c0[0] + cp * c0[2]};
+        double ex[3] = {cp * e0[0] + sp * e0[2], e0[1], -sp * e0[0] + cp * e0[2]};
+        double ey[3] = {sp, 0.0, cp};
+        BeamDesc& Q = bd[b];
+        for (int q = 0; q < 3; ++q) {
+            Q.src[q] = (float)(B.iso[q] - (double)B.sad * cax[q] - P0[q]);
+            Q.cax[q] = (float)cax[q];
+            Q.ex[q] = (float)ex[q];
+            Q.ey[q] = (float)ey[q];
+        }
+        Q.sad = B.sad;
+        Q.a0 = (float)(-0.5 * (B.nbx - 1) * B.wx + B.cx);
+        Q.b0 = (float)(-0.5 * (B.nby - 1) * B.wy + B.cy);
+        Q.wx = B.wx;
+        Q.wy = B.wy;
+        Q.nbx = B.nbx;
+        Q.nby = B.nby;
+        Q.first = first;
+        double am = 0.5 * (B.nbx - 1) * B.wx + fabs((double)B.cx);
+        double bm = 0.5 * (B.nby - 1) * B.wy + fabs((double)B.cy);
+        Q.pad_scale = (float)(o.roi_radius * sqrt((double)B.sad * B.sad + am * am + bm * bm));
+        first += B.nbx * B.nby;
+    }
+
+    // smoothing weights (normalised 1-D Gaussians per axis)
+    const double del[3] = {ct->dx, ct->dy, ct->dz};
+    std::vector<float> w3;
+    for (int a = 0; a < 3; ++a) {
+        double sg = o.smooth_sigma;
+        int r = sg > 0 ? (int)ceil(3.0 * sg / del[a] - 1e-6) : 0;
+        if (r > 64) return fail(FSPB_E_ARG, "smoothing radius %d voxels is too large", r);
+        G->smooth_r[a] = r;
+        std::vector<double> g(2 * r + 1);
+        double sum = 0;
+        for (int q = -r; q <= r; ++q) {
+            double x = q * del[a];
+            g[q + r] = sg > 0 ? exp(-x * x / (2.0 * sg * sg)) : 1.0;
+            sum += g[q + r];
+        }
+        for (double v : g) w3.push_back((float)(v / sum));
+    }
+
+    // ---- device buffers ----------------------------------------------------
+    size_t& tot = G->device_bytes;
+    int rc;
+#define ALLOC(ptr, bytes)                                                   \
+    if ((rc = dev_alloc((void**)&(ptr), (bytes), &tot)) != FSPB_OK) return rc;
+    ALLOC(G->beams, sizeof(BeamDesc) * n_beams);
+    ALLOC(G->beam_in, sizeof(BeamIn) * n_beams);
+    ALLOC(G->frames, sizeof(Frame64) * nbl);
+    ALLOC(G->desc, sizeof(BeamletDesc) * nbl);
+    ALLOC(G->tinfo, sizeof(TraceInfo) * nbl);
+    ALLOC(G->dtab, sizeof(float4) * dtab.size());
+    ALLOC(G->atab, sizeof(float4) * atab.size());
+    ALLOC(G->denstab, sizeof(float) * dens.size());
+    ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
+    if (o.dc_enabled) {
+        ALLOC(G->tW, sizeof(float4) * (size_t)nbl * G->k_stride);
+        ALLOC(G->rhohat, sizeof(float) * nv);
+        ALLOC(G->fac, sizeof(float4) * nv);
+        ALLOC(G->w3, sizeof(float) * w3.size());
+    }
+#undef ALLOC
+    HIP_TRY(hipMemcpyAsync(G->beams, bd.data(), sizeof(BeamDesc) * n_beams, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(G->beam_in, bin.data(), sizeof(BeamIn) * n_beams, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(G->dtab, dtab.data(), sizeof(float4) * dtab.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(G->atab, atab.data(), sizeof(float4) * atab.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(G->denstab, dens.data(), sizeof(float) * dens.size(), hipMemcpyHostToDevice, s));
+
+    // ---- kernels 1-4 ---------------------------------------------------------
+    if (o.dc_enabled) {
+        HIP_TRY(hipMemcpyAsync(G->w3, w3.data(), sizeof(float) * w3.size(), hipMemcpyHostToDevice, s));
+        float *tmp0 = nullptr, *tmp1 = nullptr;
+        size_t scratch = 0;
+        if ((rc = dev_alloc((void**)&tmp0, sizeof(float) * nv, &scratch)) != FSPB_OK) return rc;
+        if ((rc = dev_alloc((void**)&tmp1, sizeof(float) * nv, &scratch)) != FSPB_OK) {
+            (void)hipFree(tmp0);
+            return rc;
+        }
+        launch_smooth(ct->density, tmp0, tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3, G->smooth_r,
+                      G->denstab, G->dens, s);
+        hipError_t e = hipGetLastError();
+        hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipFree(tmp0);
+        (void)hipFree(tmp1);
+        if (e != hipSuccess) return fail(FSPB_E_HIP, "smoothing launch: %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(FSPB_E_HIP, "smoothing: %s", hipGetErrorString(e2));
+    }
+    double lo[3] = {ct->ox - 0.5 * ct->dx, ct->oy - 0.5 * ct->dy, ct->oz - 0.5 * ct->dz};
+    double hi[3] = {ct->ox + (nx - 0.5) * ct->dx, ct->oy + (ny - 0.5) * ct->dy,
+                    ct->oz + (nz - 0.5) * ct->dz};
+    launch_setup(G->beam_in, n_beams, nbl, lo, hi, step, G->frames, s);
+    HIP_TRY(hipGetLastError());
+    TraceGrid tg;
+    tg.o[0] = ct->ox;
+    tg.o[1] = ct->oy;
+    tg.o[2] = ct->oz;
+    tg.inv[0] = 1.0 / (double)ct->dx;
+    tg.inv[1] = 1.0 / (double)ct->dy;
+    tg.inv[2] = 1.0 / (double)ct->dz;
+    tg.n[0] = nx;
+    tg.n[1] = ny;
+    tg.n[2] = nz;
+    TraceParams tp;
+    tp.step = step;
+    tp.rho_surface = o.rho_surface;
+    tp.theta_step = t->n_theta > 1 ? (double)t->theta_step : 1.0;
+    for (int q = 0; q < 3; ++q) tp.p0[q] = P0[q];
+    tp.n_theta = t->n_theta;
+    tp.k_stride = G->k_stride;
+    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tW, G->desc,
+                 G->tinfo, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+
+    G->h_desc.resize(nbl);
+    G->h_frames.resize(nbl);
+    G->h_info.resize(nbl);
+    HIP_TRY(hipMemcpy(G->h_desc.data(), G->desc, sizeof(BeamletDesc) * nbl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(G->h_frames.data(), G->frames, sizeof(Frame64) * nbl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(G->h_info.data(), G->tinfo, sizeof(TraceInfo) * nbl, hipMemcpyDeviceToHost));
+    for (int i = 0; i < nbl; ++i) {
+        if (G->h_desc[i].hit) ++G->n_hit;
+        G->k_max = std::max(G->k_max, G->h_desc[i].K);
+        if (G->h_info[i].k_entry >= 0 && G->h_info[i].margin <= 1e-9) ++G->n_amb;
+        if (G->h_info[i].n_samples > G->k_stride)
+            return fail(FSPB_E_STATE, "internal: beamlet %d needs %d samples > %d", i,
+                        G->h_info[i].n_samples, G->k_stride);
+    }
+    return FSPB_OK;
+}
+
+int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
+                         const fspb_tables* tables, const fspb_options* opts, void* stream,
+                         fspb_geometry** out) {
+    if (!out) return fail(FSPB_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate(ct, n_beams, beams, tables, opts);
+    if (rc) return rc;
+    int dev = 0;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    fspb_geometry* G = new (std::nothrow) fspb_geometry();
+    if (!G) return fail(FSPB_E_NOMEM, "host allocation failed");
+    G->device = dev;
+    rc = create_impl(ct, n_beams, beams, tables, opts, (hipStream_t)stream, G);
+    if (rc) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        G->release();
+        delete G;
+        return rc;
+    }
+    *out = G;
+    g_last_error.clear();
+    return FSPB_OK;
+}
+
+int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream) {
+    if (!g || !fluence || !dose) return fail(FSPB_E_ARG, "forward: NULL argument");
+    launch_forward(g->args(), g->dc_enabled != 0, fluence, dose, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FSPB_OK;
+}
+
+int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream) {
+    if (!g || !voxel_weight || !grad) return fail(FSPB_E_ARG, "adjoint: NULL argument");
+    launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad,
+                   (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FSPB_OK;
+}
+
+int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
+                     unsigned long long* total, void* stream) {
+    if (!g || !total) return fail(FSPB_E_ARG, "count_pairs: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const long nv = (long)g->P.nx * g->P.ny * g->P.nz;
+    const int n_part = 256;
+    int rc;
+    if (!counts && !g->counts)
+        if ((rc = dev_alloc((void**)&g->counts, sizeof(int) * nv, &g->device_bytes)) != FSPB_OK) return rc;
+    if (!g->partial) {
+        if ((rc = dev_alloc((void**)&g->partial, sizeof(unsigned long long) * n_part, &g->device_bytes)) != FSPB_OK)
+            return rc;
+        if ((rc = dev_alloc((void**)&g->total, sizeof(unsigned long long), &g->device_bytes)) != FSPB_OK)
+            return rc;
+    }
+    int* c = counts ? counts : g->counts;
+    launch_count(g->args(), fluence, c, s);
+    HIP_TRY(hipGetLastError());
+    launch_sum_counts(c, nv, g->partial, n_part, g->total, s);
+    HIP_TRY(hipGetLastError());
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, g->total, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *total = h;
+    return FSPB_OK;
+}
+
+int fspb_set_dc(fspb_geometry* g, int enabled) {
+    if (!g) return fail(FSPB_E_ARG, "set_dc: NULL handle");
+    if (enabled != 0 && enabled != 1) return fail(FSPB_E_ARG, "set_dc: enabled must be 0 or 1");
+    if (enabled && !g->dc_created)
+        return fail(FSPB_E_STATE, "set_dc: handle was created without density correction");
+    g->dc_enabled = enabled;
+    return FSPB_OK;
+}
+
+int fspb_geometry_info(const fspb_geometry* g, fspb_info* info) {
+    if (!g || !info) return fail(FSPB_E_ARG, "geometry_info: NULL argument");
+    memset(info, 0, sizeof *info);
+    info->n_beams = g->n_beams;
+    info->n_beamlets = g->n_beamlets;
+    info->nx = g->P.nx;
+    info->ny = g->P.ny;
+    info->nz = g->P.nz;
+    info->n_vox = (long long)g->P.nx * g->P.ny * g->P.nz;
+    info->k_stride = g->k_stride;
+    info->k_max = g->k_max;
+    info->n_hit = g->n_hit;
+    info->n_entry_ambiguous = g->n_amb;
+    for (int a = 0; a < 3; ++a) info->smooth_radius[a] = g->smooth_r[a];
+    info->sample_step = g->sample_step;
+    info->dc_enabled = g->dc_enabled;
+    info->device_bytes = (long long)g->device_bytes;
+    return FSPB_OK;
+}
+
+int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream) {
+    if (!g || !out) return fail(FSPB_E_ARG, "smoothed_density: NULL argument");
+    if (!g->rhohat) return fail(FSPB_E_STATE, "smoothed_density: handle has no density correction");
+    const long nv = (long)g->P.nx * g->P.ny * g->P.nz;
+    HIP_TRY(hipMemcpyAsync(out, g->rhohat, sizeof(float) * nv, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return FSPB_OK;
+}
+
+int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* T, float* W1,
+                 float* W2, int max_k) {
+    if (!g) return fail(FSPB_E_ARG, "beamlet: NULL handle");
+    if (i < 0 || i >= g->n_beamlets) return fail(FSPB_E_ARG, "beamlet: index %d out of range", i);
+    const BeamletDesc& d = g->h_desc[i];
+    const Frame64& f = g->h_frames[i];
+    const TraceInfo& ti = g->h_info[i];
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->hit = d.hit;
+        info->k_entry = ti.k_entry;
+        info->n_samples = ti.n_samples;
+        info->K = d.K;
+        info->s_in = f.s_in;
+        info->s_entry = ti.s_entry;
+        info->theta = f.theta;
+        for (int q = 0; q < 3; ++q) {
+            info->src[q] = f.src[q];
+            info->dir[q] = f.d[q];
+            info->ex[q] = f.ex[q];
+            info->ey[q] = f.ey[q];
+        }
+        info->entry_margin = ti.margin;
+    }
+    int n = std::min(max_k, d.K);
+    if (n > 0 && (T || W1 || W2)) {
+        std::vector<float2> tt(n);
+        HIP_TRY(hipMemcpy(tt.data(), g->tT + d.tab_off, sizeof(float2) * n, hipMemcpyDeviceToHost));
+        if (T)
+            for (int j = 0; j < n; ++j) T[j] = tt[j].x;
+        if ((W1 || W2) && g->tW) {
+            std::vector<float4> tw(n);
+            HIP_TRY(hipMemcpy(tw.data(), g->tW + d.tab_off, sizeof(float4) * n, hipMemcpyDeviceToHost));
+            for (int j = 0; j < n; ++j) {
+                if (W1) W1[j] = tw[j].x;
+                if (W2) W2[j] = tw[j].z;
+            }
+        }
+    }
+    return FSPB_OK;
+}
+
+void fspb_destroy(fspb_geometry* g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    g->release();
+    delete g;
+}
+
+}  // extern "C"

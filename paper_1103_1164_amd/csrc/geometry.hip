@@ -1,0 +1,356 @@
+// geometry.hip -- per-plan geometry kernels for gfx950 (Algorithm A2 kernels 1-4):
+//   smooth_pass / smooth_last_factors  smoothed density and per-voxel correction
+//                                      factors (Section 2.1, A1 step 1)
+//   beamlet_setup                      beamlet frames and angles (A1 step 3)
+//   ray_trace                          entrance point and uniform-sampled
+//                                      radiological-depth / weight-drift tables
+//                                      (A1 steps 4-6, Section 2.2)
+#include "fspb_internal.h"
+#include "kernels.h"
+
+#include <math.h>
+
+namespace fspb {
+
+// ---------------------------------------------------------------------------
+// Kernel 1: separable Gaussian smoothing with clamp-to-edge borders.  The
+// normalised 3D cube-truncated Gaussian is the product of three normalised
+// 1D kernels, so three 1D passes give the same sums.  Each thread produces
+// one voxel; the 64 lanes of a wave read consecutive x, so every tap load is
+// coalesced whatever the pass axis.
+__global__ __launch_bounds__(256) void smooth_pass(const float* __restrict__ in,
+                                                   float* __restrict__ out, int nx, int ny,
+                                                   int nz, int axis,
+                                                   const float* __restrict__ w, int r) {
+    long n = (long)nx * ny * nz;
+    long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int i = (int)(v % nx);
+    int j = (int)((v / nx) % ny);
+    int k = (int)(v / ((long)nx * ny));
+    float acc = 0.0f;
+    if (axis == 0) {
+        const float* row = in + (v - i);
+        for (int d = -r; d <= r; ++d) acc = fmaf(w[d + r], row[min(max(i + d, 0), nx - 1)], acc);
+    } else if (axis == 1) {
+        const float* col = in + ((long)k * ny) * nx + i;
+        for (int d = -r; d <= r; ++d)
+            acc = fmaf(w[d + r], col[(long)min(max(j + d, 0), ny - 1) * nx], acc);
+    } else {
+        const float* col = in + (long)j * nx + i;
+        long plane = (long)nx * ny;
+        for (int d = -r; d <= r; ++d)
+            acc = fmaf(w[d + r], col[(long)min(max(k + d, 0), nz - 1) * plane], acc);
+    }
+    out[v] = acc;
+}
+
+// Last (z) pass fused with the per-voxel factors of Section 2.1:
+//   fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)),
+// densities clamped to the commissioned range.
+__global__ __launch_bounds__(256) void smooth_last_factors(
+    const float* __restrict__ in, const float* __restrict__ rho, float* __restrict__ rhohat,
+    float4* __restrict__ fac, int nx, int ny, int nz, const float* __restrict__ w, int r,
+    const float* __restrict__ tabs, DensTabs dt) {
+    long n = (long)nx * ny * nz;
+    long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int i = (int)(v % nx);
+    int j = (int)((v / nx) % ny);
+    int k = (int)(v / ((long)nx * ny));
+    const float* col = in + (long)j * nx + i;
+    long plane = (long)nx * ny;
+    float acc = 0.0f;
+    for (int d = -r; d <= r; ++d)
+        acc = fmaf(w[d + r], col[(long)min(max(k + d, 0), nz - 1) * plane], acc);
+    rhohat[v] = acc;
+    float rc = fminf(fmaxf(rho[v], dt.rho_min), dt.rho_max);
+    float hc = fminf(fmaxf(acc, dt.rho_min), dt.rho_max);
+    fac[v] = make_float4(dens_lookup(tabs, dt.fu1, rc), dens_lookup(tabs, dt.fu2, hc),
+                         dens_lookup(tabs, dt.fw1, hc), dens_lookup(tabs, dt.fw2, hc));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: beamlet frames in FP64, one thread per beamlet.
+// Beam (gantry phi, couch psi): central axis cax = Rc (-sin phi, cos phi, 0),
+// lateral axes ex = Rc (cos phi, sin phi, 0), ey = Rc (0, 0, 1), with Rc the
+// couch rotation about y; source = iso - SAD cax.  Beamlet (n, m) aims at the
+// isocentre-plane point iso + a ex + b ey; its own lateral axes are ex made
+// orthogonal to the beamlet direction and ey_i = ex_i x d_i; theta is the
+// angle to the central axis (Eq. 2 definitions).
+struct GridBox {
+    double lo[3], hi[3];
+    double step;  // ray sample step
+};
+
+__device__ inline double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ inline void rot_couch(double psi, const double* a, double* b) {
+    double c = cos(psi), s = sin(psi);
+    b[0] = c * a[0] + s * a[2];
+    b[1] = a[1];
+    b[2] = -s * a[0] + c * a[2];
+}
+
+__global__ __launch_bounds__(256) void beamlet_setup(const BeamIn* __restrict__ beams,
+                                                     int n_beams, int n_beamlets, GridBox box,
+                                                     Frame64* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_beamlets) return;
+    int b = 0;
+    while (b + 1 < n_beams && beams[b + 1].first <= i) ++b;
+    const BeamIn bm = beams[b];
+    int loc = i - bm.first;
+    int n = loc / bm.nbx, m = loc % bm.nbx;
+    double phi = bm.gantry;
+    double c0[3] = {-sin(phi), cos(phi), 0.0}, ex0[3] = {cos(phi), sin(phi), 0.0},
+           ey0[3] = {0.0, 0.0, 1.0};
+    double cax[3], ex[3], ey[3];
+    rot_couch(bm.couch, c0, cax);
+    rot_couch(bm.couch, ex0, ex);
+    rot_couch(bm.couch, ey0, ey);
+    Frame64 f;
+    for (int q = 0; q < 3; ++q) f.src[q] = bm.iso[q] - bm.sad * cax[q];
+    double a = (m - 0.5 * (bm.nbx - 1)) * bm.wx + bm.cx;
+    double bb = (n - 0.5 * (bm.nby - 1)) * bm.wy + bm.cy;
+    double d[3];
+    for (int q = 0; q < 3; ++q) d[q] = bm.sad * cax[q] + a * ex[q] + bb * ey[q];
+    double nd = sqrt(dot3(d, d));
+    for (int q = 0; q < 3; ++q) f.d[q] = d[q] / nd;
+    double pr = dot3(ex, f.d);
+    double e[3];
+    for (int q = 0; q < 3; ++q) e[q] = ex[q] - pr * f.d[q];
+    double ne = sqrt(dot3(e, e));
+    for (int q = 0; q < 3; ++q) f.ex[q] = e[q] / ne;
+    f.ey[0] = f.ex[1] * f.d[2] - f.ex[2] * f.d[1];
+    f.ey[1] = f.ex[2] * f.d[0] - f.ex[0] * f.d[2];
+    f.ey[2] = f.ex[0] * f.d[1] - f.ex[1] * f.d[0];
+    f.theta = atan(sqrt(a * a + bb * bb) / bm.sad);
+    f.beam = b;
+    f.sad = bm.sad;
+    f.x0 = 0.5 * bm.wx;
+    f.y0 = 0.5 * bm.wy;
+    // slab clip of the axis against the grid box
+    double s_in = -1e300, s_out = 1e300;
+    bool miss = false;
+    for (int q = 0; q < 3; ++q) {
+        if (f.d[q] == 0.0) {
+            if (f.src[q] < box.lo[q] || f.src[q] > box.hi[q]) miss = true;
+            continue;
+        }
+        double t1 = (box.lo[q] - f.src[q]) / f.d[q], t2 = (box.hi[q] - f.src[q]) / f.d[q];
+        s_in = fmax(s_in, fmin(t1, t2));
+        s_out = fmin(s_out, fmax(t1, t2));
+    }
+    s_in = fmax(s_in, 0.0);
+    f.s_in = s_in;
+    f.s_cover = 0.0;
+    f.n_samples = 0;
+    if (!miss && s_in < s_out) {
+        double cover = -1e300;
+        for (int c = 0; c < 8; ++c) {
+            double p[3] = {(c & 1) ? box.hi[0] : box.lo[0], (c & 2) ? box.hi[1] : box.lo[1],
+                           (c & 4) ? box.hi[2] : box.lo[2]};
+            double v[3] = {p[0] - f.src[0], p[1] - f.src[1], p[2] - f.src[2]};
+            cover = fmax(cover, dot3(v, f.d));
+        }
+        f.s_cover = cover;
+        // table runs past the deepest box point by one sample
+        f.n_samples = (int)floor((cover - s_in) / box.step) + 2;
+    }
+    out[i] = f;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels 3-4: one wavefront per beamlet, FP64.
+__device__ inline double trilinear64(const float* __restrict__ rho, const TraceGrid& g,
+                                     const double* p) {
+    double gx = (p[0] - g.o[0]) * g.inv[0], gy = (p[1] - g.o[1]) * g.inv[1],
+           gz = (p[2] - g.o[2]) * g.inv[2];
+    double fx0 = floor(gx), fy0 = floor(gy), fz0 = floor(gz);
+    int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+    double fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
+    int x0 = min(max(ix, 0), g.n[0] - 1), x1 = min(max(ix + 1, 0), g.n[0] - 1);
+    int y0 = min(max(iy, 0), g.n[1] - 1), y1 = min(max(iy + 1, 0), g.n[1] - 1);
+    int z0 = min(max(iz, 0), g.n[2] - 1), z1 = min(max(iz + 1, 0), g.n[2] - 1);
+    long sx = 1, sy = g.n[0], sz = (long)g.n[0] * g.n[1];
+    auto at = [&](int x, int y, int z) { return (double)rho[z * sz + y * sy + x * sx]; };
+    double c00 = at(x0, y0, z0) * (1 - fx) + at(x1, y0, z0) * fx;
+    double c10 = at(x0, y1, z0) * (1 - fx) + at(x1, y1, z0) * fx;
+    double c01 = at(x0, y0, z1) * (1 - fx) + at(x1, y0, z1) * fx;
+    double c11 = at(x0, y1, z1) * (1 - fx) + at(x1, y1, z1) * fx;
+    double c0 = c00 * (1 - fy) + c10 * fy;
+    double c1 = c01 * (1 - fy) + c11 * fy;
+    return c0 * (1 - fz) + c1 * fz;
+}
+
+__device__ inline double b_lookup64(const float* __restrict__ v, DTab t, double rho_c) {
+    double c = (rho_c - (double)t.start) / (double)t.step;
+    c = fmin(fmax(c, 0.0), (double)(t.n - 1));
+    int i = (int)floor(c);
+    i = max(min(i, t.n - 2), 0);
+    double f = (t.n > 1) ? c - i : 0.0;
+    double a = v[t.off + i], b = v[t.off + min(i + 1, t.n - 1)];
+    return (1.0 - f) * a + f * b;
+}
+
+__device__ inline double wave_incl_scan(double x, int lane) {
+    for (int o = 1; o < kWave; o <<= 1) {
+        double y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ inline double wave_min64(double x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+
+__global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ frames,
+                                                 int n_beamlets, const float* __restrict__ rho,
+                                                 TraceGrid g, TraceParams tp,
+                                                 const float* __restrict__ dtabs, DensTabs dt,
+                                                 float2* __restrict__ tT, float4* __restrict__ tW,
+                                                 BeamletDesc* __restrict__ desc,
+                                                 TraceInfo* __restrict__ info) {
+    int lane = threadIdx.x & (kWave - 1);
+    int ib = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (ib >= n_beamlets) return;  // wave-uniform exit
+    const Frame64 f = frames[ib];
+    const double d = tp.step;
+    auto sample = [&](int k) {
+        double s = f.s_in + k * d;
+        double p[3] = {f.src[0] + s * f.d[0], f.src[1] + s * f.d[1], f.src[2] + s * f.d[2]};
+        return trilinear64(rho, g, p);
+    };
+    const int N = min(f.n_samples, tp.k_stride);  // the host reserves k_stride >= n_samples
+    // entrance: first sample at or above the surface threshold (ballot)
+    int ke = -1;
+    double margin = 1e300;
+    for (int base = 0; base < N; base += kWave) {
+        int k = base + lane;
+        double r = (k < N) ? sample(k) : -1.0;
+        bool at_body = (k < N) && (r >= tp.rho_surface);
+        unsigned long long ball = __ballot(at_body);
+        double m = (k < N) ? fabs(r - tp.rho_surface) : 1e300;
+        if (ball) {
+            ke = base + __ffsll((long long)ball) - 1;
+            margin = fmin(margin, wave_min64(k <= ke ? m : 1e300));
+            break;
+        }
+        margin = fmin(margin, wave_min64(m));
+    }
+    BeamletDesc o = {};
+    TraceInfo ti = {};
+    ti.n_samples = N;
+    ti.k_entry = ke;
+    ti.margin = margin;
+    const double* P0 = tp.p0;
+    double v0[3] = {P0[0] - f.src[0], P0[1] - f.src[1], P0[2] - f.src[2]};
+    for (int q = 0; q < 3; ++q) {
+        o.d[q] = (float)f.d[q];
+        o.ex[q] = (float)f.ex[q];
+        o.ey[q] = (float)f.ey[q];
+    }
+    o.c_x = (float)(v0[0] * f.ex[0] + v0[1] * f.ex[1] + v0[2] * f.ex[2]);
+    o.c_y = (float)(v0[0] * f.ey[0] + v0[1] * f.ey[1] + v0[2] * f.ey[2]);
+    o.sad = (float)f.sad;
+    o.x0 = (float)f.x0;
+    o.y0 = (float)f.y0;
+    {
+        double c = f.theta / tp.theta_step;
+        c = fmin(fmax(c, 0.0), (double)(tp.n_theta - 1));
+        int r = (tp.n_theta > 1) ? min((int)floor(c), tp.n_theta - 2) : 0;
+        o.th_col = r;
+        o.th_frac = (tp.n_theta > 1) ? (float)(c - r) : 0.0f;
+    }
+    o.tab_off = ib * tp.k_stride;
+    if (ke < 0) {
+        o.hit = 0;
+        o.K = 0;
+        o.c_t = -1e30f;
+        if (lane == 0) {
+            desc[ib] = o;
+            info[ib] = ti;
+        }
+        return;
+    }
+    const int K = N - ke;
+    const double s_entry = f.s_in + ke * d;
+    o.hit = 1;
+    o.K = K;
+    o.s_entry = (float)s_entry;
+    o.c_t = (float)(v0[0] * f.d[0] + v0[1] * f.d[1] + v0[2] * f.d[2] - s_entry);
+    ti.s_entry = s_entry;
+
+    // tables: T_j = sum_{l<j} d (rho_l + rho_{l+1}) / 2 from the entrance,
+    // W_c likewise with b_c(clamped rho); exclusive wave scans in FP64.
+    double cT = 0.0, c1 = 0.0, c2 = 0.0;
+    for (int base = 0; base < K; base += kWave) {
+        int j = base + lane;
+        double r = (j < K) ? sample(ke + j) : 0.0;
+        double rn = __shfl_down(r, 1, kWave);
+        if (lane == kWave - 1) rn = (j + 1 < K) ? sample(ke + j + 1) : 0.0;
+        double rc = fmin(fmax(r, (double)dt.rho_min), (double)dt.rho_max);
+        double rcn = fmin(fmax(rn, (double)dt.rho_min), (double)dt.rho_max);
+        bool has_next = j + 1 < K;
+        double iT = has_next ? d * 0.5 * (r + rn) : 0.0;
+        double i1 = has_next ? d * 0.5 * (b_lookup64(dtabs, dt.b1, rc) + b_lookup64(dtabs, dt.b1, rcn)) : 0.0;
+        double i2 = has_next ? d * 0.5 * (b_lookup64(dtabs, dt.b2, rc) + b_lookup64(dtabs, dt.b2, rcn)) : 0.0;
+        double sT = wave_incl_scan(iT, lane), s1 = wave_incl_scan(i1, lane),
+               s2 = wave_incl_scan(i2, lane);
+        double T = cT + sT - iT, W1 = c1 + s1 - i1, W2 = c2 + s2 - i2;
+        if (j < K) {
+            tT[o.tab_off + j] = make_float2((float)T, (float)iT);
+            if (tW) tW[o.tab_off + j] = make_float4((float)W1, (float)i1, (float)W2, (float)i2);
+        }
+        cT += __shfl(sT, kWave - 1, kWave);
+        c1 += __shfl(s1, kWave - 1, kWave);
+        c2 += __shfl(s2, kWave - 1, kWave);
+    }
+    if (lane == 0) {
+        desc[ib] = o;
+        info[ib] = ti;
+    }
+}
+
+// ---------------------------------------------------------------------------
+void launch_smooth(const float* rho, float* tmp0, float* tmp1, float* rhohat, float4* fac,
+                   int nx, int ny, int nz, const float* w3, const int r[3],
+                   const float* dtabs, const DensTabs& dt, hipStream_t s) {
+    long n = (long)nx * ny * nz;
+    int blocks = (int)((n + 255) / 256);
+    const float* wx = w3;
+    const float* wy = w3 + (2 * r[0] + 1);
+    const float* wz = wy + (2 * r[1] + 1);
+    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, rho, tmp0, nx, ny, nz, 0, wx, r[0]);
+    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, (const float*)tmp0, tmp1, nx, ny, nz, 1, wy, r[1]);
+    hipLaunchKernelGGL(smooth_last_factors, dim3(blocks), dim3(256), 0, s, (const float*)tmp1, rho,
+                       rhohat, fac, nx, ny, nz, wz, r[2], dtabs, dt);
+}
+
+void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double lo[3],
+                  const double hi[3], double step, Frame64* out, hipStream_t s) {
+    GridBox box;
+    for (int q = 0; q < 3; ++q) {
+        box.lo[q] = lo[q];
+        box.hi[q] = hi[q];
+    }
+    box.step = step;
+    hipLaunchKernelGGL(beamlet_setup, dim3((n_beamlets + 255) / 256), dim3(256), 0, s, beams,
+                       n_beams, n_beamlets, box, out);
+}
+
+void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
+                  const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
+                  float4* tW, BeamletDesc* desc, TraceInfo* info, hipStream_t s) {
+    int waves_per_block = 4;
+    int blocks = (n_beamlets + waves_per_block - 1) / waves_per_block;
+    hipLaunchKernelGGL(ray_trace, dim3(blocks), dim3(waves_per_block * kWave), 0, s, frames,
+                       n_beamlets, rho, g, tp, dtabs, dt, tT, tW, desc, info);
+}
+
+}  // namespace fspb

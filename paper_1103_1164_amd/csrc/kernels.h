@@ -1,0 +1,59 @@
+// kernels.h -- launch wrappers of the gfx950 kernels (host-callable).
+#pragma once
+
+#include "fspb_internal.h"
+
+namespace fspb {
+
+// Beam parameters in FP64 for the beamlet-setup kernel.
+struct BeamIn {
+    double gantry, couch, iso[3], sad, wx, wy, cx, cy;
+    int nbx, nby, first, pad;
+};
+
+struct TraceGrid {
+    double o[3], inv[3];
+    int n[3];
+};
+
+struct TraceParams {
+    double step, rho_surface, theta_step;
+    double p0[3];
+    int n_theta, k_stride;
+};
+
+// Per-beamlet ray-trace results kept for inspection.
+struct TraceInfo {
+    int n_samples, k_entry;
+    double s_entry, margin;
+};
+
+void launch_smooth(const float* rho, float* tmp0, float* tmp1, float* rhohat, float4* fac,
+                   int nx, int ny, int nz, const float* w3, const int r[3],
+                   const float* dtabs, const DensTabs& dt, hipStream_t s);
+void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double lo[3],
+                  const double hi[3], double step, Frame64* out, hipStream_t s);
+void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
+                  const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
+                  float4* tW, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
+
+// Dose kernels (dose.hip).
+struct DoseArgs {
+    PlanConst P;
+    const BeamDesc* beams;
+    const BeamletDesc* bl;
+    const float4* fac;
+    const float4* dtab;
+    const float4* atab;
+    const float2* tT;
+    const float4* tW;
+};
+
+void launch_forward(const DoseArgs& a, bool dc, const float* fluence, float* dose, hipStream_t s);
+void launch_count(const DoseArgs& a, const float* fluence, int* counts, hipStream_t s);
+void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
+                    hipStream_t s);
+void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,
+                       unsigned long long* total, hipStream_t s);
+
+}  // namespace fspb

@@ -1,0 +1,97 @@
+// pair.h -- the per-(voxel, beamlet) dose of Eqs. 2-4 with the Section 2.1
+// density corrections, in FP32 VALU arithmetic for gfx950.
+//
+// Table layouts (built by the host, see fspb_api.hip):
+//   dtab[3*j + 0] = (u1x, u1y, u2x, u2y)(t_j) * log2(e)     water steepness
+//   dtab[3*j + 1] = slopes of the above to sample j+1
+//   dtab[3*j + 2] = (w1, w2, w1', w2')                      water weights + slopes
+//   atab[j*a_cols + r] = (A[r][j], A[r+1][j], A[r][j+1]-A[r][j], A[r+1][j+1]-A[r+1][j])
+//   tT[off + j] = (T_j, T_{j+1} - T_j)                       radiological depth
+//   tW[off + j] = (W1_j, W1_{j+1} - W1_j, W2_j, W2_{j+1} - W2_j)   weight drift
+#pragma once
+
+#include "fspb_internal.h"
+
+namespace fspb {
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Eq. 4 for a beamlet of half width x0:
+//   |x| >  x0:  sinh(u x0) e^{-u|x|}   = (e1 - e2) / 2
+//   |x| <= x0:  1 - cosh(u x) e^{-u x0} = 1 - (e1 + e2) / 2
+// with e1 = e^{-u | |x| - x0 |}, e2 = e^{-u (|x| + x0)}.  Both exponents are
+// non-positive, so nothing overflows.  ul = u * log2(e); dm = | |x| - x0 |,
+// dp = |x| + x0, outer = (|x| > x0).
+__device__ __forceinline__ float penumbra(float ul, float dm, float dp, bool outer) {
+    float e1 = fast_exp2(-ul * dm);
+    float e2 = fast_exp2(-ul * dp);
+    return outer ? 0.5f * (e1 - e2) : fmaf(-0.5f, e1 + e2, 1.0f);
+}
+
+// Unit-fluence dose D_i(r) (Eq. 2) of beamlet b at a voxel with depth t >= 0
+// below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
+// fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
+template <bool DC>
+__device__ __forceinline__ float pair_dose(float t, float xp, float yp, const BeamletDesc& b,
+                                           float4 fac, const PlanConst& P,
+                                           const float4* __restrict__ dtab,
+                                           const float4* __restrict__ atab,
+                                           const float2* __restrict__ tT,
+                                           const float4* __restrict__ tW) {
+    // magnification to the isocentre plane and inverse square (Eq. 2)
+    float k = b.sad * fast_rcp(t + b.s_entry);
+    float x = xp * k, y = yp * k;
+    float isq = k * k;
+
+    // per-beamlet radiological depth and weight drift at depth t (Section 2.2)
+    float c = fminf(t * P.inv_d, (float)(b.K - 1));
+    int j = max(min((int)c, b.K - 2), 0);
+    float f = c - (float)j;
+    float2 te = tT[b.tab_off + j];
+    float teq = fmaf(f, te.y, te.x);
+
+    // A(t_eq, theta): bilinear, theta column fixed per beamlet
+    float ca = (teq - P.at_start) * P.at_inv;
+    ca = fminf(fmaxf(ca, 0.0f), (float)(P.at_n - 1));
+    int ja = max(min((int)ca, P.at_n - 2), 0);
+    float fa = ca - (float)ja;
+    float4 ae = atab[ja * P.a_cols + b.th_col];
+    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
+    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+
+    // water parameters at geometric depth t
+    float cd = (t - P.dt_start) * P.dt_inv;
+    cd = fminf(fmaxf(cd, 0.0f), (float)(P.dt_n - 1));
+    int jd = max(min((int)cd, P.dt_n - 2), 0);
+    float fd = cd - (float)jd;
+    float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
+    float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
+    float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
+    float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
+
+    if (DC) {
+        // Section 2.1: u1 by local density, u2 and weights by smoothed
+        // density, weights drift with the passing history W_c(t).
+        float4 we = tW[b.tab_off + j];
+        float W1 = fmaf(f, we.y, we.x), W2 = fmaf(f, we.w, we.z);
+        u1x *= fac.x;
+        u1y *= fac.x;
+        u2x *= fac.y;
+        u2y *= fac.y;
+        w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
+        w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
+    }
+
+    // Eq. 3 with the Eq. 4 profiles
+    float ax = fabsf(x), ay = fabsf(y);
+    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
+    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
+    bool ox = ax > b.x0, oy = ay > b.y0;
+    float p1 = penumbra(u1x, dmx, dpx, ox) * penumbra(u1y, dmy, dpy, oy);
+    float p2 = penumbra(u2x, dmx, dpx, ox) * penumbra(u2y, dmy, dpy, oy);
+    float F = fmaf(w1, p1, w2 * p2);
+    return F * A * isq;
+}
+
+}  // namespace fspb

@@ -1,0 +1,320 @@
+"""GPU parity of libfspb against the FP64 oracle (run on an MI355X).
+
+Every comparison calls the C ABI through the thin ctypes binding; the
+oracle runs independently on the host from the same seeded inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import fspb_synth as S
+from gpu_helpers import REL_TOL, assert_dose_parity, geometry, gpu_dose, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1103_1164_amd as M
+    M.load()
+    yield
+
+
+# ---------------------------------------------------------------------------
+# Config 1: the whole grid, DC and plain
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dc", [1, 0])
+def test_c1_full_grid(oracle_mod, dc):
+    plan = S.plan_c1()
+    say(f"c1 dc={dc}")
+    orc = oracle_mod.Oracle(plan, dc_enabled=dc)
+    d_orc, amb, pc = orc.dose()
+    geo = geometry(plan, dc)
+    d_gpu = gpu_dose(geo, plan.fluence)
+    rel = assert_dose_parity(d_gpu, d_orc, amb, what=f"c1 dc={dc}")
+    say(f"c1 dc={dc}: max |err|/max D = {rel:.2e}, pairs {int(pc.sum())}")
+    n_gpu = geo.count_pairs(torch.as_tensor(plan.fluence, device="cuda"))
+    assert abs(n_gpu - int(pc.sum())) <= int((amb > 0).sum())
+
+
+def test_c1_intermediates(oracle_mod):
+    plan = S.plan_c1()
+    orc = oracle_mod.Oracle(plan)
+    geo = geometry(plan, 1)
+    info = geo.info()
+    assert info["n_beamlets"] == 100 and info["n_hit"] == 100
+    assert info["n_entry_ambiguous"] == 0
+    assert info["smooth_radius"] == orc.smooth_radius()
+    rh = geo.smoothed_density().cpu().numpy()
+    ro = orc.smoothed()
+    assert np.max(np.abs(rh - ro)) < 2e-6
+    for i in range(orc.n_beamlets):
+        g, o = geo.beamlet(i), orc.trace(i)
+        f = orc.frame(i)
+        assert g["hit"] == o["hit"] and g["k_entry"] == o["k_entry"] and g["K"] == o["K"]
+        assert abs(g["s_entry"] - o["s_entry"]) < 1e-9
+        assert np.allclose(g["d"], f["d"], atol=1e-12) and np.allclose(g["ex"], f["ex"], atol=1e-12)
+        assert np.allclose(g["ey"], f["ey"], atol=1e-12) and abs(g["theta"] - f["theta"]) < 1e-12
+        assert np.max(np.abs(g["T"] - o["T"])) <= 2e-6 * max(1.0, o["T"].max())
+        assert np.max(np.abs(g["W1"] - o["W1"])) < 1e-7 and np.max(np.abs(g["W2"] - o["W2"])) < 1e-7
+
+
+def test_c1_pair_counts_per_voxel(oracle_mod):
+    plan = S.plan_c1()
+    orc = oracle_mod.Oracle(plan)
+    counts_o = orc.pair_counts()
+    _, amb, _ = orc.dose(np.ones(100, np.float32))
+    geo = geometry(plan, 1)
+    tot, counts_g = geo.count_pairs(None, per_voxel=True)
+    counts_g = counts_g.cpu().numpy()
+    clear = amb == 0
+    assert np.array_equal(counts_g[clear], counts_o[clear])
+    assert abs(tot - int(counts_o.sum())) <= int((~clear).sum()) * 2
+
+
+# ---------------------------------------------------------------------------
+# Small plans with ragged sizes and every geometry option
+# ---------------------------------------------------------------------------
+def _ragged_plans():
+    rng = np.random.default_rng(21)
+    out = []
+    # heterogeneous noise phantom, two beams, rectangular beamlets, offsets
+    n = (23, 19, 13)
+    rho = rng.uniform(0.05, 2.3, size=(n[2], n[1], n[0])).astype(np.float32)
+    out.append(S.plan_small(n=n, density=rho, seed=1, name="noise2", beams=[
+        S.Beam(gantry=0.3, nbx=5, nby=3, wx=0.4, wy=0.6, cx=0.2, cy=-0.1),
+        S.Beam(gantry=3.9, nbx=4, nby=4, wx=0.5, wy=0.5)]))
+    # body in air (entrance inside the grid), anisotropic voxels, couch rotation
+    n, sp = (30, 26, 17), (0.3, 0.25, 0.4)
+
+    def body(Z, Y, X):
+        r = (X / 3.2) ** 2 + (Y / 2.6) ** 2 + (Z / 3.0) ** 2
+        return np.where(r <= 1.0, 1.0 + 0.3 * np.sin(2 * X) * np.cos(Y), 0.001)
+    out.append(S.plan_small(n=n, spacing=sp, density=body, seed=2, name="body_couch", beams=[
+        S.Beam(gantry=1.2, couch=0.35, nbx=6, nby=5, wx=0.5, wy=0.5, iso=(0.2, -0.3, 0.1)),
+        S.Beam(gantry=5.0, couch=-0.2, sad=80.0, nbx=3, nby=7, wx=0.7, wy=0.3)]))
+    # single beamlet, beam along x, 1-voxel-thick grid
+    out.append(S.plan_small(n=(25, 9, 1), density=1.1, seed=3, name="thin",
+                            beams=[S.Beam(gantry=math.pi / 2, nbx=1, nby=1, wx=1.0, wy=1.0)]))
+    return out
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("dc", [1, 0])
+def test_ragged_plans_full_grid(oracle_mod, k, dc):
+    plan = _ragged_plans()[k]
+    say(f"ragged {plan.name} dc={dc}")
+    orc = oracle_mod.Oracle(plan, dc_enabled=dc)
+    d_orc, amb, pc = orc.dose()
+    geo = geometry(plan, dc)
+    d_gpu = gpu_dose(geo, plan.fluence)
+    assert d_orc.max() > 0
+    assert_dose_parity(d_gpu, d_orc, amb, what=plan.name)
+    assert geo.info()["n_entry_ambiguous"] == 0
+
+
+# ---------------------------------------------------------------------------
+# Full-size configs 2 and 3, on sampled voxels and beamlets
+# ---------------------------------------------------------------------------
+def _sample_voxels(shape, d_gpu, n, seed):
+    rng = np.random.default_rng(seed)
+    nv = int(np.prod(shape))
+    rand = rng.choice(nv, size=n, replace=False)
+    hot = np.argsort(d_gpu.reshape(-1))[-n // 4:]          # highest-dose voxels
+    hot = rng.choice(hot, size=min(len(hot), n // 4), replace=False)
+    return np.unique(np.concatenate([rand, hot]))
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_full_size_forward_sampled(oracle_mod, cfg):
+    plan = S.plan_c2() if cfg == "c2" else S.plan_c3()
+    say(f"{cfg}: geometry")
+    geo = geometry(plan, 1)
+    d_gpu = gpu_dose(geo, plan.fluence)
+    info = geo.info()
+    assert info["n_entry_ambiguous"] == 0 and info["n_hit"] == plan.n_beamlets
+    vox = _sample_voxels(plan.shape, d_gpu, 3000, seed=7)
+    say(f"{cfg}: oracle at {vox.size} voxels")
+    orc = oracle_mod.Oracle(plan)
+    d_o, amb, pc = orc.dose(vox=vox)
+    # the scale is the oracle maximum over the sample, which includes the
+    # hottest GPU voxels
+    rel = assert_dose_parity(d_gpu.reshape(-1)[vox], d_o, amb, what=cfg)
+    say(f"{cfg}: max |err|/max D = {rel:.2e}")
+    assert np.all(np.isfinite(d_gpu)) and d_gpu.min() >= 0.0
+    # evaluated-pair counts at the sampled voxels
+    tot, cnt = geo.count_pairs(torch.as_tensor(plan.fluence, device="cuda"), per_voxel=True)
+    cnt = cnt.cpu().numpy().reshape(-1)[vox]
+    clear = amb == 0
+    assert np.array_equal(cnt[clear], pc[clear])
+
+
+def test_c3_adjoint_sampled_and_fd(oracle_mod):
+    plan = S.plan_c3()
+    geo = geometry(plan, 1)
+    nb = plan.n_beamlets
+    w, u = S.c3_objective(3, plan.n_vox)
+    wt = torch.as_tensor(w, device="cuda")
+    g = geo.adjoint(wt).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(g))
+    # sampled beamlets: two 4x2 blocks in beams 0 and 4 plus two field corners
+    pick = []
+    for beam, (n0, m0) in ((0, (13, 13)), (4, (10, 17))):
+        pick += [beam * 900 + (n0 + a) * 30 + (m0 + b) for a in range(2) for b in range(4)]
+    pick += [2 * 900 + 0, 7 * 900 + 899]
+    pick = np.array(pick)
+    say(f"c3 adjoint: oracle for {pick.size} beamlets")
+    orc = oracle_mod.Oracle(plan)
+    g_o, amb = orc.adjoint(w, pick)
+    scale = np.max(np.abs(g_o))
+    err = np.abs(g[pick] - g_o)
+    assert np.all(err <= REL_TOL * scale + amb), (err / scale).max()
+    say(f"c3 adjoint: max |err|/max g = {(err / scale).max():.2e}")
+
+    # quadratic objective: central differences of the GPU forward (h = 1e-3)
+    # against the adjoint of w' = 2 w (D - D0); the difference of L is summed
+    # in FP64 to avoid cancellation.
+    f = torch.as_tensor(plan.fluence, device="cuda")
+    D = geo.forward(f).reshape(-1)
+    D0 = torch.as_tensor(u, device="cuda") * D.max()
+    wq = (2.0 * wt * (D - D0)).contiguous()
+    gq = geo.adjoint(wq).double()
+    h = 1e-3
+    rng = np.random.default_rng(5)
+    for i in rng.choice(nb, size=8, replace=False):
+        fp, fm = f.clone(), f.clone()
+        fp[i] += h
+        fm[i] -= h
+        hh = (fp[i].double() - fm[i].double()) / 2
+        Dp, Dm = geo.forward(fp).reshape(-1).double(), geo.forward(fm).reshape(-1).double()
+        dL = torch.sum(wt.double() * (Dp - Dm) * (Dp + Dm - 2 * D0.double()))
+        fd = float(dL / (2 * hh))
+        assert abs(fd - float(gq[i])) <= 2e-3 * max(abs(float(gq[i])), 1e-3 * float(gq.abs().max()))
+
+
+# ---------------------------------------------------------------------------
+# Adjoint on a small plan: every beamlet against the oracle, dot-product test
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dc", [1, 0])
+def test_adjoint_full_small(oracle_mod, dc):
+    plan = _ragged_plans()[1]
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0, 1, plan.n_vox).astype(np.float32)
+    orc = oracle_mod.Oracle(plan, dc_enabled=dc)
+    g_o, amb = orc.adjoint(w)
+    geo = geometry(plan, dc)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy()
+    assert np.all(np.abs(g - g_o) <= REL_TOL * np.abs(g_o).max() + amb)
+    # <D f, w> = <f, D^T w> on the GPU
+    f = rng.uniform(0, 1, plan.n_beamlets).astype(np.float32)
+    D = gpu_dose(geo, f).reshape(-1)
+    lhs = float(D @ w.astype(np.float64))
+    rhs = float(f.astype(np.float64) @ g.astype(np.float64))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_autograd_function():
+    from paper_1103_1164_amd import FspbDose
+    plan = _ragged_plans()[0]
+    geo = geometry(plan, 1)
+    f = torch.as_tensor(plan.fluence, device="cuda").requires_grad_(True)
+    D = FspbDose.apply(f, geo)
+    w = torch.rand(D.shape, device="cuda")
+    loss = (w * D).sum()
+    loss.backward()
+    g = geo.adjoint(w.reshape(-1))
+    assert torch.equal(f.grad, g)
+
+
+# ---------------------------------------------------------------------------
+# Invariants through the GPU path
+# ---------------------------------------------------------------------------
+def test_gpu_invariants():
+    plan = _ragged_plans()[0]
+    geo = geometry(plan, 1)
+    rng = np.random.default_rng(8)
+    f = np.round(rng.uniform(0, 1, plan.n_beamlets) * 1024) / 1024
+    g = np.round(rng.uniform(0, 1, plan.n_beamlets) * 1024) / 1024
+    Df, Dg, Dfg = gpu_dose(geo, f), gpu_dose(geo, g), gpu_dose(geo, 2 * f + 0.5 * g)
+    assert np.max(np.abs(Dfg - (2 * Df + 0.5 * Dg))) < 2e-6 * Dfg.max()
+    # DC reduces to plain in water
+    water = S.plan_small(n=(27, 21, 15), density=1.0, seed=4,
+                         beams=[S.Beam(gantry=0.5, nbx=5, nby=4), S.Beam(gantry=3.0, nbx=3, nby=3)])
+    a = gpu_dose(geometry(water, 1), water.fluence)
+    b = gpu_dose(geometry(water, 0), water.fluence)
+    assert np.max(np.abs(a - b)) < 1e-6 * a.max()
+    # a DC handle switched to plain equals a plain handle
+    geo_w = geometry(water, 1)
+    geo_w.set_dc(False)
+    assert np.array_equal(gpu_dose(geo_w, water.fluence), b)
+    # inverse square along the central axis
+    tabs = S.constant_tables(A=1.0, u1=3.0, u2=1.2, w1=0.75, w2=0.25)
+    ax = S.plan_small(n=(9, 41, 9), density=1.0, tables=tabs, fluence=np.ones(1),
+                      beams=[S.Beam(gantry=0.0, nbx=1, nby=1)])
+    d = gpu_dose(geometry(ax, 1), ax.fluence)
+    y = ax.origin[1] + 0.25 * np.arange(41)
+    v = d[4, :, 4] * (y + 100.0) ** 2
+    assert np.max(np.abs(v / v.mean() - 1)) < 2e-6
+
+
+def test_determinism():
+    plan = S.plan_c2()
+    geo = geometry(plan, 1)
+    f = torch.as_tensor(plan.fluence, device="cuda")
+    a, b = geo.forward(f).clone(), geo.forward(f).clone()
+    assert torch.equal(a, b)
+    w = torch.rand(plan.n_vox, device="cuda")
+    assert torch.equal(geo.adjoint(w).clone(), geo.adjoint(w).clone())
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_edge_cases(oracle_mod):
+    # zero fluence: every voxel written with zero
+    plan = _ragged_plans()[0]
+    geo = geometry(plan, 1)
+    out = torch.full(plan.shape, 7.0, device="cuda")
+    geo.forward(torch.zeros(plan.n_beamlets, device="cuda"), out=out)
+    assert torch.count_nonzero(out) == 0
+    # a beamlet that misses the grid contributes nothing, others are unaffected
+    beams = [S.Beam(gantry=0.0, nbx=2, nby=1, wx=0.5, cx=0.0), S.Beam(gantry=0.0, nbx=1, nby=1, cx=60.0)]
+    p = S.plan_small(n=(12, 10, 6), density=1.0, beams=beams, fluence=np.ones(3), seed=0)
+    g = geometry(p, 1)
+    assert g.info()["n_hit"] == 2 and not g.beamlet(2)["hit"]
+    d_o, amb, _ = oracle_mod.Oracle(p).dose()
+    assert_dose_parity(gpu_dose(g, p.fluence), d_o, amb, what="miss")
+    # body entirely below the surface threshold: nothing enters
+    p2 = S.plan_small(n=(8, 8, 8), density=0.2, seed=0)
+    g2 = geometry(p2, 1)
+    assert g2.info()["n_hit"] == 0
+    assert gpu_dose(g2, p2.fluence).max() == 0.0
+    # 1x1x1 grid
+    p3 = S.plan_small(n=(1, 1, 1), density=1.0, beams=[S.Beam(gantry=0.7, nbx=2, nby=2)], seed=0)
+    d_o, amb, _ = oracle_mod.Oracle(p3).dose()
+    assert_dose_parity(gpu_dose(geometry(p3, 1), p3.fluence), d_o, amb, what="1x1x1")
+
+
+def test_errors_on_gpu():
+    from paper_1103_1164_amd import FspbError
+    import os
+    plan = _ragged_plans()[2]
+    geo = geometry(plan, 0)
+    with pytest.raises(FspbError):
+        geo.set_dc(True)             # created without density correction
+    with pytest.raises(FspbError):
+        geo.smoothed_density()
+    with pytest.raises(ValueError):
+        geo.forward(torch.ones(plan.n_beamlets + 1, device="cuda"))
+    # injected device allocation failure: clean error, no handle
+    os.environ["FSPB_TEST_FAIL_ALLOC"] = "3"
+    try:
+        with pytest.raises(FspbError) as e:
+            geometry(plan, 1)
+        assert e.value.code == -3
+    finally:
+        del os.environ["FSPB_TEST_FAIL_ALLOC"]
+    assert geometry(plan, 1).info()["n_hit"] == 1
