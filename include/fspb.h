@@ -204,9 +204,14 @@ int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream);
 int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info,
                  float* T, float* W1, float* W2, int max_k);
 
-/* Frees the handle and its device buffers.  NULL-safe.  Waits for work
- * queued on the handle's buffers to finish. */
+/* Frees the handle.  NULL-safe.  Waits for queued device work to finish,
+ * then returns the handle's device buffers to the library's per-device cache
+ * (reused by later fspb_create_geometry calls). */
 void fspb_destroy(fspb_geometry* g);
+
+/* Returns every cached device buffer to the HIP runtime.  Buffers of live
+ * handles are not affected. */
+int fspb_release_cached_memory(void);
 
 /* Static description of an error code. */
 const char* fspb_error_string(int code);

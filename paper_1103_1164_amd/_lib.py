@@ -83,6 +83,7 @@ SIGNATURES = {
                                C.POINTER(C.c_float), C.POINTER(C.c_float),
                                C.POINTER(C.c_float), C.c_int]),
     "fspb_destroy": (None, [C.c_void_p]),
+    "fspb_release_cached_memory": (C.c_int, []),
     "fspb_error_string": (C.c_char_p, [C.c_int]),
     "fspb_last_error": (C.c_char_p, []),
 }

@@ -2,12 +2,14 @@
 // kernel 5), its transpose, and the evaluated-pair count, for gfx950.
 //
 // Forward: voxel-major.  A wavefront owns a 4x4x4 brick of voxels (one per
-// lane).  For each beam it projects its voxels onto the isocentre plane,
-// reduces the projections across the wave, and visits only the rectangle of
-// beamlets whose 5 cm ROI cylinder can reach the brick.  Beamlet descriptors
-// and fluences are wave-uniform (scalar loads); every lane then tests its own
-// voxel exactly and evaluates the pair in FP32.  Each voxel is written once:
-// no atomics, and the result does not depend on scheduling.
+// lane).  For each beam it projects its voxels onto the isocentre plane and
+// reduces the projections across the wave to a rectangle of beamlets whose
+// 5 cm ROI cylinder can reach the brick.  The rectangle is filtered 64
+// beamlets at a time (one per lane) against the brick's bounding sphere and
+// the survivors are compacted; the wave then walks them with wave-uniform
+// beamlet descriptors (scalar loads), each lane testing its own voxel exactly
+// and evaluating the pair in FP32.  Each voxel is written once: no atomics,
+// and the result does not depend on scheduling.
 //
 // Adjoint: beamlet-major.  A workgroup owns one beamlet.  It walks the grid
 // row by row (rows along x); for each row it solves for the x-interval that
@@ -51,25 +53,30 @@ __device__ __forceinline__ bool pair_coords(const BeamletDesc& d, const PlanCons
     t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
     xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
     yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
-    return (t >= 0.0f) && (fmaf(xp, xp, yp * yp) <= P.R2);
+    return (t >= 0.0f) & (fmaf(xp, xp, yp * yp) <= P.R2);
 }
 
 // ---------------------------------------------------------------------------
-template <bool DC, bool COUNT>
-__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const float* __restrict__ fluence,
+// Forward kernel, three modes sharing the candidate search:
+//   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
+//   kCount  number of evaluated pairs per voxel
+//   kCost   number of candidate beamlets per brick (scheduling estimate)
+enum { kDose = 0, kCount = 1, kCost = 2 };
+
+template <bool DC, int MODE>
+__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __restrict__ order,
+                                                    const float* __restrict__ fluence,
                                                     float* __restrict__ dose,
-                                                    int* __restrict__ counts) {
+                                                    int* __restrict__ out_int) {
     const PlanConst& P = a.P;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so
-    // give each XCD one contiguous run of bricks (a z-slab) to keep its L2
-    // working set (the beamlet tables of a band of beamlet rows) small.
-    const int per = P.n_blocks >> 3;
-    const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int brick = blk * 4 + wid;
+    const int slot = blockIdx.x * 4 + threadIdx.x / kWave;
     const int n_bricks = P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
-    if (brick >= n_bricks) return;
+    if (slot >= n_bricks) return;
+    // bricks run in decreasing order of estimated work (longest first), so
+    // the expensive bricks near the isocentre start early and cheap ones fill
+    // the tail; consecutive slots are dealt round-robin to the 8 XCDs.
+    const int brick = order ? order[slot] : slot;
     const int bx = brick % P.n_bricks_x;
     const int by = (brick / P.n_bricks_x) % P.n_bricks_y;
     const int bz = brick / (P.n_bricks_x * P.n_bricks_y);
@@ -79,13 +86,22 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const float* __r
     float qx, qy, qz;
     voxel_q(P, i, j, k, qx, qy, qz);
     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-    if (DC && valid) fac = a.fac[v];
+    if (DC && MODE == kDose && valid) fac = a.fac[v];
+    // bounding sphere of the brick's 4x4x4 voxel centres
+    float cqx, cqy, cqz;
+    voxel_q(P, bx * 4, by * 4, bz * 4, cqx, cqy, cqz);
+    cqx += 1.5f * P.dx;
+    cqy += 1.5f * P.dy;
+    cqz += 1.5f * P.dz;
+    const float rb = 1.5f * sqrtf(P.dx * P.dx + P.dy * P.dy + P.dz * P.dz) * 1.0001f + 1e-3f;
+    const float Rc = sqrtf(P.R2) + rb;
+    const float Rc2 = Rc * Rc;
 
     float acc = 0.0f;
-    int cnt = 0;
+    int cnt = 0, cost = 0;
     for (int b = 0; b < P.n_beams; ++b) {
         const BeamDesc& B = a.beams[b];
-        // isocentre-plane projection of the brick's voxels
+        // rectangle of beamlets in the isocentre plane that can reach the brick
         float vx = qx - B.src[0], vy = qy - B.src[1], vz = qz - B.src[2];
         float z = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
         float X = fmaf(vx, B.ex[0], fmaf(vy, B.ex[1], vz * B.ex[2]));
@@ -108,31 +124,71 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const float* __r
         const int n_lo = uniform(max((int)ceilf(fn0), 0));
         const int n_hi = uniform(min((int)floorf(fn1), B.nby - 1));
         const int first = uniform(B.first), nbx = uniform(B.nbx);
+        const int nm = m_hi - m_lo + 1;
+        const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
         float accb = 0.0f;
-        for (int n = n_lo; n <= n_hi; ++n) {
-            for (int m = m_lo; m <= m_hi; ++m) {
-                const int ib = first + n * nbx + m;
-                const float fi = fluence ? fluence[ib] : 1.0f;
-                if (fi == 0.0f) continue;
-                const BeamletDesc& d = a.bl[ib];
-                if (!d.hit) continue;
+        for (int base = 0; base < total; base += kWave) {
+            // 64 candidates at once: one per lane, tested against the brick's
+            // bounding sphere with the beamlet's true axis
+            const int c = base + lane;
+            bool pass = false;
+            int ib = 0;
+            float fi = 1.0f;
+            if (c < total) {
+                ib = first + (n_lo + c / nm) * nbx + (m_lo + c % nm);
+                if (MODE == kDose || fluence) fi = fluence[ib];
+                if (fi != 0.0f) {
+                    const float4* dp = reinterpret_cast<const float4*>(a.bl + ib);
+                    const float4 r0 = dp[0], r1 = dp[1], r2 = dp[2];
+                    float tc = fmaf(cqx, r0.x, fmaf(cqy, r0.y, fmaf(cqz, r0.z, r0.w)));
+                    float xc = fmaf(cqx, r1.x, fmaf(cqy, r1.y, fmaf(cqz, r1.z, r1.w)));
+                    float yc = fmaf(cqx, r2.x, fmaf(cqy, r2.y, fmaf(cqz, r2.z, r2.w)));
+                    pass = (tc >= -rb) && (fmaf(xc, xc, yc * yc) <= Rc2);
+                }
+            }
+            const unsigned long long mask = __ballot(pass);
+            const int ncand = __popcll(mask);
+            if (MODE == kCost) {
+                cost += ncand;
+                continue;
+            }
+            if (ncand == 0) continue;
+            // compact: the r-th passing candidate moves to lane r
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+            const int dst = pass ? rank : ncand + (lane - rank);
+            const int pk_ib = __builtin_amdgcn_ds_permute(dst << 2, ib);
+            const int pk_f = __builtin_amdgcn_ds_permute(dst << 2, __float_as_int(fi));
+            // software pipeline: the next candidate's descriptor is fetched
+            // (scalar loads) while the current one is evaluated
+            BeamletDesc dn = a.bl[__builtin_amdgcn_readlane(pk_ib, 0)];
+            for (int e = 0; e < ncand; ++e) {
+                const BeamletDesc d = dn;
+                const float fe = __int_as_float(__builtin_amdgcn_readlane(pk_f, e));
+                dn = a.bl[__builtin_amdgcn_readlane(pk_ib, min(e + 1, ncand - 1))];
                 float t, xp, yp;
-                bool act = valid && pair_coords(d, P, qx, qy, qz, t, xp, yp);
-                if (COUNT) {
+                // evaluated on every lane (no short circuit) so that the whole
+                // descriptor is fetched in one scalar batch before the branch
+                const bool act = pair_coords(d, P, qx, qy, qz, t, xp, yp) & valid;
+                if (MODE == kCount) {
                     cnt += act ? 1 : 0;
                     continue;
                 }
+                const float kmag = magnification(t, d);
                 if (!__any(act)) continue;
                 if (act)
-                    accb = fmaf(fi, pair_dose<DC>(t, xp, yp, d, fac, P, a.dtab, a.atab, a.tT, a.tW),
+                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, a.dtab, a.atab, a.tT,
+                                                  a.tTW),
                                 accb);
             }
         }
         acc += accb;
     }
-    if (valid) {
-        if (COUNT)
-            counts[v] = cnt;
+    if (MODE == kCost) {
+        if (lane == 0) out_int[brick] = cost;
+    } else if (valid) {
+        if (MODE == kCount)
+            out_int[v] = cnt;
         else
             dose[v] = acc;
     }
@@ -236,7 +292,8 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, const float* __r
                     const long v = ((long)k * P.ny + j) * P.nx + i;
                     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                     if (DC) fac = a.fac[v];
-                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, d, fac, P, a.dtab, a.atab, a.tT, a.tW),
+                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P, a.dtab,
+                                                   a.atab, a.tT, a.tTW),
                                acc);
                 }
             }
@@ -275,17 +332,31 @@ __global__ void sum_counts_final(const unsigned long long* __restrict__ part, in
 }
 
 // ---------------------------------------------------------------------------
-void launch_forward(const DoseArgs& a, bool dc, const float* fluence, float* dose, hipStream_t s) {
-    dim3 grid(a.P.n_blocks), block(256);
-    if (dc)
-        hipLaunchKernelGGL((dose_forward<true, false>), grid, block, 0, s, a, fluence, dose, (int*)nullptr);
-    else
-        hipLaunchKernelGGL((dose_forward<false, false>), grid, block, 0, s, a, fluence, dose, (int*)nullptr);
+static int fwd_blocks(const PlanConst& P) {
+    long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
+    return (int)((n_bricks + 3) / 4);
 }
 
-void launch_count(const DoseArgs& a, const float* fluence, int* counts, hipStream_t s) {
-    hipLaunchKernelGGL((dose_forward<false, true>), dim3(a.P.n_blocks), dim3(256), 0, s, a,
-                       fluence, (float*)nullptr, counts);
+void launch_forward(const DoseArgs& a, bool dc, const int* order, const float* fluence,
+                    float* dose, hipStream_t s) {
+    dim3 grid(fwd_blocks(a.P)), block(256);
+    if (dc)
+        hipLaunchKernelGGL((dose_forward<true, kDose>), grid, block, 0, s, a, order, fluence, dose,
+                           (int*)nullptr);
+    else
+        hipLaunchKernelGGL((dose_forward<false, kDose>), grid, block, 0, s, a, order, fluence, dose,
+                           (int*)nullptr);
+}
+
+void launch_count(const DoseArgs& a, const int* order, const float* fluence, int* counts,
+                  hipStream_t s) {
+    hipLaunchKernelGGL((dose_forward<false, kCount>), dim3(fwd_blocks(a.P)), dim3(256), 0, s, a,
+                       order, fluence, (float*)nullptr, counts);
+}
+
+void launch_brick_cost(const DoseArgs& a, int* cost, hipStream_t s) {
+    hipLaunchKernelGGL((dose_forward<false, kCost>), dim3(fwd_blocks(a.P)), dim3(256), 0, s, a,
+                       (const int*)nullptr, (const float*)nullptr, (float*)nullptr, cost);
 }
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,

@@ -14,6 +14,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -40,32 +42,88 @@ int fail(int code, const char* fmt, ...) {
             return fail(FSPB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
+// Device memory comes from a per-device caching pool: blocks freed by
+// fspb_destroy are kept (by size class) and handed to the next geometry, so a
+// stream of plans does not pay hipMalloc/hipFree on every create.  Sizes are
+// rounded up to classes at most 1/8 above the request.
+struct Pool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;  // (device, class) -> blocks
+    size_t cached = 0;
+};
+
+Pool& pool() {
+    static Pool* p = new Pool();  // never destroyed: blocks may be returned during exit
+    return *p;
+}
+
+size_t size_class(size_t bytes) {
+    if (bytes <= 4096) return 4096;
+    size_t top = (size_t)1 << (63 - __builtin_clzll(bytes));
+    size_t q = std::max<size_t>(top / 8, 4096);
+    return (bytes + q - 1) / q * q;
+}
+
 // Test hook: FSPB_TEST_FAIL_ALLOC=n makes the n-th device allocation after the
 // variable was set (or changed) fail, to exercise the out-of-memory paths.
 int g_alloc_count = 0;
 std::string g_alloc_env;
 
-int dev_alloc(void** p, size_t bytes, size_t* total) {
+int pool_alloc(int dev, void** p, size_t bytes, size_t* cls_out) {
+    *p = nullptr;
     const char* inj = getenv("FSPB_TEST_FAIL_ALLOC");
-    std::string cur = inj ? inj : "";
-    if (cur != g_alloc_env) {
-        g_alloc_env = cur;
-        g_alloc_count = 0;
+    {
+        std::lock_guard<std::mutex> lk(pool().mu);
+        std::string cur = inj ? inj : "";
+        if (cur != g_alloc_env) {
+            g_alloc_env = cur;
+            g_alloc_count = 0;
+        }
+        ++g_alloc_count;
+        if (inj && atoi(inj) == g_alloc_count)
+            return fail(FSPB_E_NOMEM, "device allocation of %zu bytes failed (injected)", bytes);
     }
-    ++g_alloc_count;
-    if (inj && atoi(inj) == g_alloc_count) {
-        *p = nullptr;
-        return fail(FSPB_E_NOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+    const size_t cls = size_class(bytes);
+    *cls_out = cls;
+    {
+        std::lock_guard<std::mutex> lk(pool().mu);
+        auto it = pool().free_blocks.find({dev, cls});
+        if (it != pool().free_blocks.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            pool().cached -= cls;
+            return FSPB_OK;
+        }
     }
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = hipMalloc(p, cls);
     if (e != hipSuccess) {
-        *p = nullptr;
         (void)hipGetLastError();
-        return fail(FSPB_E_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        // give the cached blocks back to the runtime and try once more
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(pool().mu);
+            for (auto& kv : pool().free_blocks)
+                if (kv.first.first == dev) {
+                    drop.insert(drop.end(), kv.second.begin(), kv.second.end());
+                    kv.second.clear();
+                }
+        }
+        for (void* q : drop) (void)hipFree(q);
+        e = hipMalloc(p, cls);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return fail(FSPB_E_NOMEM, "hipMalloc of %zu bytes failed: %s", cls, hipGetErrorString(e));
+        }
     }
-    *total += bytes;
     return FSPB_OK;
+}
+
+void pool_free(int dev, void* p, size_t cls) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(pool().mu);
+    pool().free_blocks[{dev, cls}].push_back(p);
+    pool().cached += cls;
 }
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
@@ -100,9 +158,10 @@ struct fspb_geometry {
     float4* atab = nullptr;
     float* denstab = nullptr;
     float2* tT = nullptr;
-    float4* tW = nullptr;
+    float4* tTW = nullptr;    // DC only: interleaved depth + weight-drift records
     float* w3 = nullptr;
     int* counts = nullptr;
+    int* order = nullptr;      // bricks in decreasing order of estimated work
     unsigned long long* partial = nullptr;
     unsigned long long* total = nullptr;
     // host copies
@@ -110,6 +169,18 @@ struct fspb_geometry {
     std::vector<Frame64> h_frames;
     std::vector<TraceInfo> h_info;
     int k_max = 0, n_hit = 0, n_amb = 0;
+    bool host_ready = false;               // host copies are fetched on first use
+    std::vector<std::pair<void*, size_t>> blocks;   // pool blocks owned by the handle
+
+    int alloc(void** p, size_t bytes) {
+        size_t cls = 0;
+        int rc = pool_alloc(device, p, bytes, &cls);
+        if (rc == FSPB_OK) {
+            blocks.push_back({*p, cls});
+            device_bytes += cls;
+        }
+        return rc;
+    }
 
     DoseArgs args() const {
         DoseArgs a;
@@ -121,16 +192,16 @@ struct fspb_geometry {
         a.dtab = dtab;
         a.atab = atab;
         a.tT = tT;
-        a.tW = tW;
+        a.tTW = tTW;
         return a;
     }
 
     void release() {
-        void* bufs[] = {rhohat, fac, beams, beam_in, frames, desc, tinfo, dtab, atab,
-                        denstab, tT, tW, w3, counts, partial, total};
-        for (void* b : bufs)
-            if (b) (void)hipFree(b);
+        for (auto& b : blocks) pool_free(device, b.first, b.second);
+        blocks.clear();
     }
+
+    int fetch_host() const;
 };
 
 namespace {
@@ -225,6 +296,26 @@ int check_device(int* dev) {
 
 }  // namespace
 
+int fspb_geometry::fetch_host() const {
+    fspb_geometry* G = const_cast<fspb_geometry*>(this);
+    if (G->host_ready) return FSPB_OK;
+    const int nbl = n_beamlets;
+    G->h_desc.resize(nbl);
+    G->h_frames.resize(nbl);
+    G->h_info.resize(nbl);
+    HIP_TRY(hipMemcpy(G->h_desc.data(), desc, sizeof(BeamletDesc) * nbl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(G->h_frames.data(), frames, sizeof(Frame64) * nbl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(G->h_info.data(), tinfo, sizeof(TraceInfo) * nbl, hipMemcpyDeviceToHost));
+    G->n_hit = G->k_max = G->n_amb = 0;
+    for (int i = 0; i < nbl; ++i) {
+        if (G->h_desc[i].hit) ++G->n_hit;
+        G->k_max = std::max(G->k_max, G->h_desc[i].K);
+        if (G->h_info[i].k_entry >= 0 && G->h_info[i].margin <= 1e-9) ++G->n_amb;
+    }
+    G->host_ready = true;
+    return FSPB_OK;
+}
+
 extern "C" {
 
 const char* fspb_error_string(int code) {
@@ -303,9 +394,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     P.n_bricks_x = (nx + 3) / 4;
     P.n_bricks_y = (ny + 3) / 4;
     P.n_bricks_z = (nz + 3) / 4;
-    long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
-    long blocks = (n_bricks + 3) / 4;
-    P.n_blocks = (int)((blocks + 7) / 8 * 8);
+    const long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
 
     // ---- host-side table packing -------------------------------------------
     const int dn = t->u1x.n;
@@ -410,10 +499,9 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     }
 
     // ---- device buffers ----------------------------------------------------
-    size_t& tot = G->device_bytes;
     int rc;
 #define ALLOC(ptr, bytes)                                                   \
-    if ((rc = dev_alloc((void**)&(ptr), (bytes), &tot)) != FSPB_OK) return rc;
+    if ((rc = G->alloc((void**)&(ptr), (bytes))) != FSPB_OK) return rc;
     ALLOC(G->beams, sizeof(BeamDesc) * n_beams);
     ALLOC(G->beam_in, sizeof(BeamIn) * n_beams);
     ALLOC(G->frames, sizeof(Frame64) * nbl);
@@ -423,13 +511,13 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     ALLOC(G->atab, sizeof(float4) * atab.size());
     ALLOC(G->denstab, sizeof(float) * dens.size());
     ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
+    ALLOC(G->order, sizeof(int) * n_bricks);
     if (o.dc_enabled) {
-        ALLOC(G->tW, sizeof(float4) * (size_t)nbl * G->k_stride);
+        ALLOC(G->tTW, 2 * sizeof(float4) * (size_t)nbl * G->k_stride);
         ALLOC(G->rhohat, sizeof(float) * nv);
         ALLOC(G->fac, sizeof(float4) * nv);
         ALLOC(G->w3, sizeof(float) * w3.size());
     }
-#undef ALLOC
     HIP_TRY(hipMemcpyAsync(G->beams, bd.data(), sizeof(BeamDesc) * n_beams, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(G->beam_in, bin.data(), sizeof(BeamIn) * n_beams, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(G->dtab, dtab.data(), sizeof(float4) * dtab.size(), hipMemcpyHostToDevice, s));
@@ -439,21 +527,21 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     // ---- kernels 1-4 ---------------------------------------------------------
     if (o.dc_enabled) {
         HIP_TRY(hipMemcpyAsync(G->w3, w3.data(), sizeof(float) * w3.size(), hipMemcpyHostToDevice, s));
+        // the two intermediate passes use the (not yet written) depth-table
+        // buffer as scratch when it is large enough, else two pool blocks
         float *tmp0 = nullptr, *tmp1 = nullptr;
-        size_t scratch = 0;
-        if ((rc = dev_alloc((void**)&tmp0, sizeof(float) * nv, &scratch)) != FSPB_OK) return rc;
-        if ((rc = dev_alloc((void**)&tmp1, sizeof(float) * nv, &scratch)) != FSPB_OK) {
-            (void)hipFree(tmp0);
-            return rc;
+        const size_t tt_bytes = sizeof(float2) * (size_t)nbl * G->k_stride;
+        if (tt_bytes >= 2 * sizeof(float) * (size_t)nv) {
+            tmp0 = reinterpret_cast<float*>(G->tT);
+            tmp1 = tmp0 + nv;
+        } else {
+            ALLOC(tmp0, sizeof(float) * nv);
+            ALLOC(tmp1, sizeof(float) * nv);
         }
         launch_smooth(ct->density, tmp0, tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3, G->smooth_r,
                       G->denstab, G->dens, s);
-        hipError_t e = hipGetLastError();
-        hipError_t e2 = hipStreamSynchronize(s);
-        (void)hipFree(tmp0);
-        (void)hipFree(tmp1);
-        if (e != hipSuccess) return fail(FSPB_E_HIP, "smoothing launch: %s", hipGetErrorString(e));
-        if (e2 != hipSuccess) return fail(FSPB_E_HIP, "smoothing: %s", hipGetErrorString(e2));
+        HIP_TRY(hipGetLastError());
+#undef ALLOC
     }
     double lo[3] = {ct->ox - 0.5 * ct->dx, ct->oy - 0.5 * ct->dy, ct->oz - 0.5 * ct->dz};
     double hi[3] = {ct->ox + (nx - 0.5) * ct->dx, ct->oy + (ny - 0.5) * ct->dy,
@@ -477,24 +565,30 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     for (int q = 0; q < 3; ++q) tp.p0[q] = P0[q];
     tp.n_theta = t->n_theta;
     tp.k_stride = G->k_stride;
-    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tW, G->desc,
+    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->desc,
                  G->tinfo, s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(s));
 
-    G->h_desc.resize(nbl);
-    G->h_frames.resize(nbl);
-    G->h_info.resize(nbl);
-    HIP_TRY(hipMemcpy(G->h_desc.data(), G->desc, sizeof(BeamletDesc) * nbl, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(G->h_frames.data(), G->frames, sizeof(Frame64) * nbl, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(G->h_info.data(), G->tinfo, sizeof(TraceInfo) * nbl, hipMemcpyDeviceToHost));
-    for (int i = 0; i < nbl; ++i) {
-        if (G->h_desc[i].hit) ++G->n_hit;
-        G->k_max = std::max(G->k_max, G->h_desc[i].K);
-        if (G->h_info[i].k_entry >= 0 && G->h_info[i].margin <= 1e-9) ++G->n_amb;
-        if (G->h_info[i].n_samples > G->k_stride)
-            return fail(FSPB_E_STATE, "internal: beamlet %d needs %d samples > %d", i,
-                        G->h_info[i].n_samples, G->k_stride);
+    // schedule: estimated work per brick (candidate beamlets), longest first
+    // (counting sort on the integer cost, stable in brick index order)
+    {
+        launch_brick_cost(G->args(), G->order, s);
+        HIP_TRY(hipGetLastError());
+        std::vector<int> cost(n_bricks), idx(n_bricks);
+        HIP_TRY(hipMemcpyAsync(cost.data(), G->order, sizeof(int) * n_bricks, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int cap = 1 << 16;
+        std::vector<int> hist(cap + 1, 0);
+        for (long q = 0; q < n_bricks; ++q) ++hist[std::min(std::max(cost[q], 0), cap)];
+        int acc = 0;
+        for (int c = cap; c >= 0; --c) {
+            int h = hist[c];
+            hist[c] = acc;
+            acc += h;
+        }
+        for (long q = 0; q < n_bricks; ++q) idx[hist[std::min(std::max(cost[q], 0), cap)]++] = (int)q;
+        HIP_TRY(hipMemcpyAsync(G->order, idx.data(), sizeof(int) * n_bricks, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     return FSPB_OK;
 }
@@ -526,7 +620,7 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
 
 int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream) {
     if (!g || !fluence || !dose) return fail(FSPB_E_ARG, "forward: NULL argument");
-    launch_forward(g->args(), g->dc_enabled != 0, fluence, dose, (hipStream_t)stream);
+    launch_forward(g->args(), g->dc_enabled != 0, g->order, fluence, dose, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
@@ -547,15 +641,14 @@ int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
     const int n_part = 256;
     int rc;
     if (!counts && !g->counts)
-        if ((rc = dev_alloc((void**)&g->counts, sizeof(int) * nv, &g->device_bytes)) != FSPB_OK) return rc;
+        if ((rc = g->alloc((void**)&g->counts, sizeof(int) * nv)) != FSPB_OK) return rc;
     if (!g->partial) {
-        if ((rc = dev_alloc((void**)&g->partial, sizeof(unsigned long long) * n_part, &g->device_bytes)) != FSPB_OK)
+        if ((rc = g->alloc((void**)&g->partial, sizeof(unsigned long long) * n_part)) != FSPB_OK)
             return rc;
-        if ((rc = dev_alloc((void**)&g->total, sizeof(unsigned long long), &g->device_bytes)) != FSPB_OK)
-            return rc;
+        if ((rc = g->alloc((void**)&g->total, sizeof(unsigned long long))) != FSPB_OK) return rc;
     }
     int* c = counts ? counts : g->counts;
-    launch_count(g->args(), fluence, c, s);
+    launch_count(g->args(), g->order, fluence, c, s);
     HIP_TRY(hipGetLastError());
     launch_sum_counts(c, nv, g->partial, n_part, g->total, s);
     HIP_TRY(hipGetLastError());
@@ -577,6 +670,8 @@ int fspb_set_dc(fspb_geometry* g, int enabled) {
 
 int fspb_geometry_info(const fspb_geometry* g, fspb_info* info) {
     if (!g || !info) return fail(FSPB_E_ARG, "geometry_info: NULL argument");
+    int rc = g->fetch_host();
+    if (rc) return rc;
     memset(info, 0, sizeof *info);
     info->n_beams = g->n_beams;
     info->n_beamlets = g->n_beamlets;
@@ -608,6 +703,8 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
                  float* W2, int max_k) {
     if (!g) return fail(FSPB_E_ARG, "beamlet: NULL handle");
     if (i < 0 || i >= g->n_beamlets) return fail(FSPB_E_ARG, "beamlet: index %d out of range", i);
+    int rc = g->fetch_host();
+    if (rc) return rc;
     const BeamletDesc& d = g->h_desc[i];
     const Frame64& f = g->h_frames[i];
     const TraceInfo& ti = g->h_info[i];
@@ -634,12 +731,13 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
         HIP_TRY(hipMemcpy(tt.data(), g->tT + d.tab_off, sizeof(float2) * n, hipMemcpyDeviceToHost));
         if (T)
             for (int j = 0; j < n; ++j) T[j] = tt[j].x;
-        if ((W1 || W2) && g->tW) {
-            std::vector<float4> tw(n);
-            HIP_TRY(hipMemcpy(tw.data(), g->tW + d.tab_off, sizeof(float4) * n, hipMemcpyDeviceToHost));
+        if ((W1 || W2) && g->tTW) {
+            std::vector<float4> tw(2 * (size_t)n);
+            HIP_TRY(hipMemcpy(tw.data(), g->tTW + 2 * (size_t)d.tab_off, 2 * sizeof(float4) * n,
+                              hipMemcpyDeviceToHost));
             for (int j = 0; j < n; ++j) {
-                if (W1) W1[j] = tw[j].x;
-                if (W2) W2[j] = tw[j].z;
+                if (W1) W1[j] = tw[2 * j].z;
+                if (W2) W2[j] = tw[2 * j + 1].x;
             }
         }
     }
@@ -651,6 +749,20 @@ void fspb_destroy(fspb_geometry* g) {
     (void)hipDeviceSynchronize();
     g->release();
     delete g;
+}
+
+int fspb_release_cached_memory(void) {
+    std::vector<void*> drop;
+    {
+        std::lock_guard<std::mutex> lk(pool().mu);
+        for (auto& kv : pool().free_blocks) {
+            drop.insert(drop.end(), kv.second.begin(), kv.second.end());
+            kv.second.clear();
+        }
+        pool().cached = 0;
+    }
+    for (void* p : drop) HIP_TRY(hipFree(p));
+    return FSPB_OK;
 }
 
 }  // extern "C"

@@ -77,7 +77,7 @@ struct PlanConst {
     float inv_d;          // 1 / ray sample step
     float dt_start, dt_inv, at_start, at_inv;  // depth-table and A-table grids
     int dt_n, at_n, a_cols, dc;
-    int n_bricks_x, n_bricks_y, n_bricks_z, n_blocks;
+    int n_bricks_x, n_bricks_y, n_bricks_z, pad0;
 };
 
 // Density-table grid (host copy of start/step/n for the factor kernel and

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
                                                  int n_beamlets, const float* __restrict__ rho,
                                                  TraceGrid g, TraceParams tp,
                                                  const float* __restrict__ dtabs, DensTabs dt,
-                                                 float2* __restrict__ tT, float4* __restrict__ tW,
+                                                 float2* __restrict__ tT, float4* __restrict__ tTW,
                                                  BeamletDesc* __restrict__ desc,
                                                  TraceInfo* __restrict__ info) {
     int lane = threadIdx.x & (kWave - 1);
@@ -305,7 +305,10 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
         double T = cT + sT - iT, W1 = c1 + s1 - i1, W2 = c2 + s2 - i2;
         if (j < K) {
             tT[o.tab_off + j] = make_float2((float)T, (float)iT);
-            if (tW) tW[o.tab_off + j] = make_float4((float)W1, (float)i1, (float)W2, (float)i2);
+            if (tTW) {
+                tTW[2 * (o.tab_off + j)] = make_float4((float)T, (float)iT, (float)W1, (float)i1);
+                tTW[2 * (o.tab_off + j) + 1] = make_float4((float)W2, (float)i2, 0.0f, 0.0f);
+            }
         }
         cT += __shfl(sT, kWave - 1, kWave);
         c1 += __shfl(s1, kWave - 1, kWave);
@@ -346,11 +349,11 @@ void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double
 
 void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
                   const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
-                  float4* tW, BeamletDesc* desc, TraceInfo* info, hipStream_t s) {
+                  float4* tTW, BeamletDesc* desc, TraceInfo* info, hipStream_t s) {
     int waves_per_block = 4;
     int blocks = (n_beamlets + waves_per_block - 1) / waves_per_block;
     hipLaunchKernelGGL(ray_trace, dim3(blocks), dim3(waves_per_block * kWave), 0, s, frames,
-                       n_beamlets, rho, g, tp, dtabs, dt, tT, tW, desc, info);
+                       n_beamlets, rho, g, tp, dtabs, dt, tT, tTW, desc, info);
 }
 
 }  // namespace fspb

@@ -35,7 +35,7 @@ void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double
                   const double hi[3], double step, Frame64* out, hipStream_t s);
 void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
                   const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
-                  float4* tW, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
+                  float4* tTW, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
 
 // Dose kernels (dose.hip).
 struct DoseArgs {
@@ -46,11 +46,14 @@ struct DoseArgs {
     const float4* dtab;
     const float4* atab;
     const float2* tT;
-    const float4* tW;
+    const float4* tTW;
 };
 
-void launch_forward(const DoseArgs& a, bool dc, const float* fluence, float* dose, hipStream_t s);
-void launch_count(const DoseArgs& a, const float* fluence, int* counts, hipStream_t s);
+void launch_forward(const DoseArgs& a, bool dc, const int* order, const float* fluence,
+                    float* dose, hipStream_t s);
+void launch_count(const DoseArgs& a, const int* order, const float* fluence, int* counts,
+                  hipStream_t s);
+void launch_brick_cost(const DoseArgs& a, int* cost, hipStream_t s);
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     hipStream_t s);
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,

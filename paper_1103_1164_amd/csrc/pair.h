@@ -7,7 +7,9 @@
 //   dtab[3*j + 2] = (w1, w2, w1', w2')                      water weights + slopes
 //   atab[j*a_cols + r] = (A[r][j], A[r+1][j], A[r][j+1]-A[r][j], A[r+1][j+1]-A[r+1][j])
 //   tT[off + j] = (T_j, T_{j+1} - T_j)                       radiological depth
-//   tW[off + j] = (W1_j, W1_{j+1} - W1_j, W2_j, W2_{j+1} - W2_j)   weight drift
+//   tTW[2(off + j)]     = (T_j, T_{j+1} - T_j, W1_j, W1_{j+1} - W1_j)
+//   tTW[2(off + j) + 1] = (W2_j, W2_{j+1} - W2_j, 0, 0)      depth + weight drift,
+//                         one 32-byte record so both halves share a cache line
 #pragma once
 
 #include "fspb_internal.h"
@@ -23,33 +25,48 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // with e1 = e^{-u | |x| - x0 |}, e2 = e^{-u (|x| + x0)}.  Both exponents are
 // non-positive, so nothing overflows.  ul = u * log2(e); dm = | |x| - x0 |,
 // dp = |x| + x0, outer = (|x| > x0).
-__device__ __forceinline__ float penumbra(float ul, float dm, float dp, bool outer) {
+// Returns 2 p; the factors of 1/2 of both axes are applied once per pair.
+__device__ __forceinline__ float penumbra2(float ul, float dm, float dp, bool outer) {
     float e1 = fast_exp2(-ul * dm);
     float e2 = fast_exp2(-ul * dp);
-    return outer ? 0.5f * (e1 - e2) : fmaf(-0.5f, e1 + e2, 1.0f);
+    return outer ? e1 - e2 : 2.0f - (e1 + e2);
+}
+
+// SAD / |r_a| for a voxel at depth t below the beamlet's entrance.
+__device__ __forceinline__ float magnification(float t, const BeamletDesc& b) {
+    return b.sad * fast_rcp(t + b.s_entry);
 }
 
 // Unit-fluence dose D_i(r) (Eq. 2) of beamlet b at a voxel with depth t >= 0
 // below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
 // fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
+// k = SAD / |r_a| (see magnification()) is computed by the caller.
 template <bool DC>
-__device__ __forceinline__ float pair_dose(float t, float xp, float yp, const BeamletDesc& b,
-                                           float4 fac, const PlanConst& P,
+__device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
+                                           const BeamletDesc& b, float4 fac, const PlanConst& P,
                                            const float4* __restrict__ dtab,
                                            const float4* __restrict__ atab,
                                            const float2* __restrict__ tT,
-                                           const float4* __restrict__ tW) {
+                                           const float4* __restrict__ tTW) {
     // magnification to the isocentre plane and inverse square (Eq. 2)
-    float k = b.sad * fast_rcp(t + b.s_entry);
     float x = xp * k, y = yp * k;
-    float isq = k * k;
+    float isq = k * (0.25f * k);   // (SAD/|r_a|)^2 times the 1/4 of the two 2p factors
 
     // per-beamlet radiological depth and weight drift at depth t (Section 2.2)
     float c = fminf(t * P.inv_d, (float)(b.K - 1));
     int j = max(min((int)c, b.K - 2), 0);
     float f = c - (float)j;
-    float2 te = tT[b.tab_off + j];
-    float teq = fmaf(f, te.y, te.x);
+    float teq, W1 = 0.0f, W2 = 0.0f;
+    if (DC) {
+        const float4 r0 = tTW[2 * (b.tab_off + j)];
+        const float4 r1 = tTW[2 * (b.tab_off + j) + 1];
+        teq = fmaf(f, r0.y, r0.x);
+        W1 = fmaf(f, r0.w, r0.z);
+        W2 = fmaf(f, r1.y, r1.x);
+    } else {
+        const float2 te = tT[b.tab_off + j];
+        teq = fmaf(f, te.y, te.x);
+    }
 
     // A(t_eq, theta): bilinear, theta column fixed per beamlet
     float ca = (teq - P.at_start) * P.at_inv;
@@ -73,8 +90,6 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, const Be
     if (DC) {
         // Section 2.1: u1 by local density, u2 and weights by smoothed
         // density, weights drift with the passing history W_c(t).
-        float4 we = tW[b.tab_off + j];
-        float W1 = fmaf(f, we.y, we.x), W2 = fmaf(f, we.w, we.z);
         u1x *= fac.x;
         u1y *= fac.x;
         u2x *= fac.y;
@@ -88,8 +103,8 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, const Be
     float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
     float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
     bool ox = ax > b.x0, oy = ay > b.y0;
-    float p1 = penumbra(u1x, dmx, dpx, ox) * penumbra(u1y, dmy, dpy, oy);
-    float p2 = penumbra(u2x, dmx, dpx, ox) * penumbra(u2y, dmy, dpy, oy);
+    float p1 = penumbra2(u1x, dmx, dpx, ox) * penumbra2(u1y, dmy, dpy, oy);
+    float p2 = penumbra2(u2x, dmx, dpx, ox) * penumbra2(u2y, dmy, dpy, oy);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
