@@ -33,8 +33,8 @@ METRIC = "voxel·beamlet evals/s + ms/plan, plain DC-FSPB vs surrogate at ≤1% 
 # Algorithmic FP32 operations per evaluated pair (each add, multiply, divide,
 # exponential and comparison counts 1, an FMA counts 2); the breakdown is in
 # the design notes.  Plain FSPB skips the 14 density-correction operations.
-FLOPS_PER_PAIR_DC = 107
-FLOPS_PER_PAIR_PLAIN = 93
+FLOPS_PER_PAIR_DC = 109
+FLOPS_PER_PAIR_PLAIN = 95
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
 PEAK_HBM_GBS = 8000.0
 

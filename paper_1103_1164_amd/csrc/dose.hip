@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
                     continue;
                 }
                 const float kmag = magnification(t, d);
-                if (!__any(act)) continue;
+                // a candidate with no active lane skips the block (empty exec mask)
                 if (act)
                     accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, a.dtab, a.atab, a.tT,
                                                   a.tTW),
@@ -204,14 +204,20 @@ __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
 }
 
 template <bool DC>
-__global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, const float* __restrict__ w,
+__global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
+                                                    const float* __restrict__ w,
                                                     float* __restrict__ grad) {
     __shared__ int s_off[256];
     __shared__ int s_lo[256];
     __shared__ int s_wsum[4];
     __shared__ float s_red[4];
     const PlanConst& P = a.P;
-    const int ib = blockIdx.x;
+    // each XCD (workgroups are dealt round-robin to the 8 XCDs) takes a
+    // contiguous run of beamlets, whose ROI cylinders overlap, so that the
+    // voxel data they read is shared in that XCD's L2
+    const int per = (n_beamlets + 7) / 8;
+    const int ib = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (ib >= n_beamlets) return;  // whole workgroup
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const BeamletDesc& d = a.bl[ib];
     float acc = 0.0f;
@@ -274,14 +280,19 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, const float* __r
             s_off[tid] = base + incl - len;
             s_lo[tid] = lo;
             __syncthreads();
-            for (int e = tid; e < total; e += 256) {
-                // the last row whose interval starts at or before item e
+            for (int e0 = wid * kWave; e0 < total; e0 += 256) {
+                // a wave takes 64 consecutive items: the row of its first item
+                // is found once (same address on every lane), then each lane
+                // steps forward over the few rows its own item lies beyond
+                const int e = e0 + lane;
                 int rlo = 0, rhi = 255;
                 while (rlo < rhi) {
                     int mid = (rlo + rhi + 1) >> 1;
-                    if (s_off[mid] <= e) rlo = mid;
+                    if (s_off[mid] <= e0) rlo = mid;
                     else rhi = mid - 1;
                 }
+                while (rlo < 255 && s_off[rlo + 1] <= e) ++rlo;
+                if (e >= total) continue;
                 const int rr = r0 + rlo;
                 const int i = s_lo[rlo] + (e - s_off[rlo]);
                 const int j = rr % P.ny, k = rr / P.ny;
@@ -361,10 +372,11 @@ void launch_brick_cost(const DoseArgs& a, int* cost, hipStream_t s) {
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     hipStream_t s) {
+    dim3 grid(8 * ((n_beamlets + 7) / 8)), block(256);
     if (dc)
-        hipLaunchKernelGGL((dose_adjoint<true>), dim3(n_beamlets), dim3(256), 0, s, a, w, grad);
+        hipLaunchKernelGGL((dose_adjoint<true>), grid, block, 0, s, a, n_beamlets, w, grad);
     else
-        hipLaunchKernelGGL((dose_adjoint<false>), dim3(n_beamlets), dim3(256), 0, s, a, w, grad);
+        hipLaunchKernelGGL((dose_adjoint<false>), grid, block, 0, s, a, n_beamlets, w, grad);
 }
 
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,

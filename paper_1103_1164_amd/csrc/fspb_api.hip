@@ -383,11 +383,11 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     P.qy0 = (float)(ct->oy - P0[1]);
     P.qz0 = (float)(ct->oz - P0[2]);
     P.inv_d = (float)(1.0 / step);
-    P.dt_start = t->u1x.start;
     P.dt_inv = t->u1x.n > 1 ? (float)(1.0 / t->u1x.step) : 0.0f;
+    P.dt_off = t->u1x.n > 1 ? (float)(-(double)t->u1x.start / t->u1x.step) : 0.0f;
     P.dt_n = t->u1x.n;
-    P.at_start = t->A.start;
     P.at_inv = t->A.n > 1 ? (float)(1.0 / t->A.step) : 0.0f;
+    P.at_off = t->A.n > 1 ? (float)(-(double)t->A.start / t->A.step) : 0.0f;
     P.at_n = t->A.n;
     P.a_cols = std::max(t->n_theta - 1, 1);
     P.dc = o.dc_enabled;

@@ -75,7 +75,7 @@ struct PlanConst {
     float dx, dy, dz, R2;
     float qx0, qy0, qz0;  // centre of voxel (0,0,0) minus P0
     float inv_d;          // 1 / ray sample step
-    float dt_start, dt_inv, at_start, at_inv;  // depth-table and A-table grids
+    float dt_inv, dt_off, at_inv, at_off;  // table coordinate = value * inv + off
     int dt_n, at_n, a_cols, dc;
     int n_bricks_x, n_bricks_y, n_bricks_z, pad0;
 };

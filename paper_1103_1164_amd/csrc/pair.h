@@ -25,11 +25,17 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // with e1 = e^{-u | |x| - x0 |}, e2 = e^{-u (|x| + x0)}.  Both exponents are
 // non-positive, so nothing overflows.  ul = u * log2(e); dm = | |x| - x0 |,
 // dp = |x| + x0, outer = (|x| > x0).
-// Returns 2 p; the factors of 1/2 of both axes are applied once per pair.
-__device__ __forceinline__ float penumbra2(float ul, float dm, float dp, bool outer) {
+// Returns 2 p = sg e1 + (o2 - e2) with (sg, o2) = (1, 0) outside the box and
+// (-1, 2) inside; the factors 1/2 of both axes are applied once per pair.
+__device__ __forceinline__ float penumbra2(float ul, float dm, float dp, float sg, float o2) {
     float e1 = fast_exp2(-ul * dm);
     float e2 = fast_exp2(-ul * dp);
-    return outer ? e1 - e2 : 2.0f - (e1 + e2);
+    return fmaf(sg, e1, o2 - e2);
+}
+
+__device__ __forceinline__ float fract(float x) { return __builtin_amdgcn_fractf(x); }
+__device__ __forceinline__ float clampf(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
 // SAD / |r_a| for a voxel at depth t below the beamlet's entrance.
@@ -52,14 +58,26 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     float x = xp * k, y = yp * k;
     float isq = k * (0.25f * k);   // (SAD/|r_a|)^2 times the 1/4 of the two 2p factors
 
-    // per-beamlet radiological depth and weight drift at depth t (Section 2.2)
-    float c = fminf(t * P.inv_d, (float)(b.K - 1));
-    int j = max(min((int)c, b.K - 2), 0);
-    float f = c - (float)j;
+    // Every lookup below except A's depends on t only: issue those loads
+    // first so that they share one memory latency, then A's (which needs t_eq).
+    // Table coordinates are clamped to the table range; the last entry of
+    // each table has zero slope, so a coordinate clamped to the end reads the
+    // end value.
+    // water parameters at geometric depth t
+    const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
+    const int jd = (int)cd;
+    const float fd = fract(cd);
+    const float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
+
+    // per-beamlet radiological depth and weight drift at depth t (Section 2.2);
+    // t >= 0 and voxel centres never reach the last table interval
+    const float c = t * P.inv_d;
+    const int j = max(min((int)c, b.K - 2), 0);
+    const float f = fract(c);
     float teq, W1 = 0.0f, W2 = 0.0f;
     if (DC) {
         const float4 r0 = tTW[2 * (b.tab_off + j)];
-        const float4 r1 = tTW[2 * (b.tab_off + j) + 1];
+        const float2 r1 = *reinterpret_cast<const float2*>(&tTW[2 * (b.tab_off + j) + 1]);
         teq = fmaf(f, r0.y, r0.x);
         W1 = fmaf(f, r0.w, r0.z);
         W2 = fmaf(f, r1.y, r1.x);
@@ -69,20 +87,11 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     }
 
     // A(t_eq, theta): bilinear, theta column fixed per beamlet
-    float ca = (teq - P.at_start) * P.at_inv;
-    ca = fminf(fmaxf(ca, 0.0f), (float)(P.at_n - 1));
-    int ja = max(min((int)ca, P.at_n - 2), 0);
-    float fa = ca - (float)ja;
-    float4 ae = atab[ja * P.a_cols + b.th_col];
-    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
-    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+    const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
+    const int ja = (int)ca;
+    const float fa = fract(ca);
+    const float4 ae = atab[ja * P.a_cols + b.th_col];
 
-    // water parameters at geometric depth t
-    float cd = (t - P.dt_start) * P.dt_inv;
-    cd = fminf(fmaxf(cd, 0.0f), (float)(P.dt_n - 1));
-    int jd = max(min((int)cd, P.dt_n - 2), 0);
-    float fd = cd - (float)jd;
-    float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
     float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
     float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
     float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
@@ -98,13 +107,17 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
         w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
     }
 
+    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
+    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+
     // Eq. 3 with the Eq. 4 profiles
     float ax = fabsf(x), ay = fabsf(y);
     float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
     float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
-    bool ox = ax > b.x0, oy = ay > b.y0;
-    float p1 = penumbra2(u1x, dmx, dpx, ox) * penumbra2(u1y, dmy, dpy, oy);
-    float p2 = penumbra2(u2x, dmx, dpx, ox) * penumbra2(u2y, dmy, dpy, oy);
+    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
+    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
+    float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
