@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=600_000,
                     help="voxels in the CPU oracle sample")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 32-plan batched persistent launch (config 4)")
+    ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--forward-only", type=int, default=0,
                     help="profiling aid: only launch the forward kernel this many times")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -140,16 +143,13 @@ def main():
     geo.set_dc(False)
     plain_ms = time_loop(lambda: geo.forward(flu, out=dose), n_side)
     geo.set_dc(True)
+    make().close()
+    torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(n_side):
         make().close()
     torch.cuda.synchronize()
     geom_ms = (time.perf_counter() - t2) * 1e3 / n_side
-    t3 = time.perf_counter()
-    for _ in range(n_side):
-        make(0).close()
-    torch.cuda.synchronize()
-    geom_plain_ms = (time.perf_counter() - t3) * 1e3 / n_side
     # host<->device transfers of the CT in and the dose out (pinned host memory)
     h_ct = torch.empty(plan.shape, dtype=torch.float32, pin_memory=True)
     h_ct.copy_(torch.as_tensor(plan.density))
@@ -169,6 +169,10 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(plan, a.cpu_sample)
+    batch = None
+    if not a.no_batch:
+        del geo
+        batch = batch_c4(a.batch_replays)
 
     out = {
         "metric": METRIC,
@@ -198,13 +202,13 @@ def main():
         "plain_forward_evals_per_s": pairs_fwd / (plain_ms * 1e-3),
         "dc_over_plain_forward": round(fwd_loop_ms / plain_ms, 4),
         "geometry_ms": round(geom_ms, 4),
-        "geometry_plain_ms": round(geom_plain_ms, 4),
         "adjoint_ms": round(adj_ms, 4),
         "adjoint_evals_per_s": pairs_all / (adj_ms * 1e-3),
         "h2d_ct_ms": round(h2d_ms, 4),
         "d2h_dose_ms": round(d2h_ms, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch_c4": batch,
         "paper_context": "Tesla C1060, real H&N/lung IMRT plans (Table 4): median T_gpu "
                          "0.37 s DC (0.33 s plain), T_tr 0.20 s; different hardware and workload",
     }
@@ -216,6 +220,70 @@ def _opts(o, dc):
     o = copy.copy(o)
     o.dc_enabled = int(dc)
     return o
+
+
+def batch_c4(replays):
+    """Config 4: 32 plans of uneven size in one persistent launch, captured
+    with their density-dependent geometry (kernels 1-4 of every plan, then the
+    batched forward) in one HIP graph and replayed.  Reports plans/s over the
+    replays and the p50/p99 of per-plan completion times inside the persistent
+    launch (device wall clock, one sample per plan per replay)."""
+    import numpy as np
+    import torch
+
+    import fspb_synth as S
+    from paper_1103_1164_amd import Batch, Geometry
+    from paper_1103_1164_amd.autotune import tune
+
+    plans = S.plans_c4()
+    dev = torch.device("cuda:0")
+    dens = [torch.as_tensor(p.density, device=dev) for p in plans]
+    geos = [Geometry(d, p.spacing, p.origin, p.beams, p.tables, p.options)
+            for d, p in zip(dens, plans)]
+    fl = [torch.as_tensor(p.fluence, device=dev) for p in plans]
+    out = [torch.empty(p.shape, device=dev) for p in plans]
+    pairs = sum(g.count_pairs(f) for g, f in zip(geos, fl))
+    # tile shape from the autotuner on the median-size plan (cached per bucket)
+    mid = int(np.argsort([p.n_vox for p in plans])[len(plans) // 2])
+    t = tune(geos[mid], fl[mid])
+    s = torch.cuda.Stream()
+    res = {
+        "plans": len(plans), "voxels": int(sum(p.n_vox for p in plans)),
+        "beamlets": int(sum(p.n_beamlets for p in plans)), "pairs_forward": int(pairs),
+        "tile": {"shape": t["shape"], "dims": t["dims"], "waves_per_block": t["waves_per_block"]},
+        "note": "replay = density-dependent geometry of all 32 plans + one persistent "
+                "forward (one HIP graph); latencies are per-plan completion times inside "
+                "the persistent launch, one sample per plan per replay",
+    }
+    for policy in ("latency", "throughput"):
+        b = Batch(geos, shape=t["shape"], waves_per_block=t["waves_per_block"], policy=policy)
+        with torch.cuda.stream(s):
+            b.capture(fl, out, densities=dens, stream=s)
+            b.replay(stream=s)                      # warm-up
+        s.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(replays):
+            with torch.cuda.stream(s):
+                b.replay(stream=s)
+            ms, _ = b.latencies(stream=s)           # synchronises the stream
+            lat.extend(ms)
+        wall = (time.perf_counter() - t0) / replays
+        with torch.cuda.stream(s):
+            b.forward(fl, out, stream=s)            # the persistent forward alone
+        _, fwd_ms = b.latencies(stream=s)
+        lat = np.sort(np.asarray(lat))
+        res[policy] = {
+            "replay_ms": round(wall * 1e3, 3), "plans_per_s": round(len(plans) / wall, 2),
+            "evals_per_s": pairs / wall, "persistent_forward_ms": round(fwd_ms, 3),
+            "plan_latency_p50_ms": round(float(lat[len(lat) // 2]), 3),
+            "plan_latency_p99_ms": round(float(lat[min(len(lat) - 1, int(0.99 * len(lat)))]), 3),
+            "latency_samples": int(lat.size),
+        }
+        b.close()
+    for g in geos:
+        g.close()
+    return res
 
 
 def cpu_baseline(plan, n_sample):

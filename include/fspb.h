@@ -204,6 +204,90 @@ int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream);
 int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info,
                  float* T, float* W1, float* W2, int max_k);
 
+/* Re-runs the density-dependent part of fspb_create_geometry (smoothed
+ * density and correction factors, entrance points and depth tables) for a new
+ * CT of the same grid, beams and tables -- e.g. the next fraction of an
+ * adaptive session.  Asynchronous on stream with no allocation and no host
+ * synchronisation, so it can be captured in a HIP graph; density (device,
+ * [n_vox]) must stay valid until the work has run.  The brick schedule of the
+ * forward kernel is kept from the previous density. */
+int fspb_update_density(fspb_geometry* g, const float* density, void* stream);
+
+/* ---- forward-kernel tiling and autotuning -------------------------------
+ * The forward kernel assigns one 64-voxel brick to each wavefront.  Brick
+ * shapes (voxels along x, y, z) are listed by fspb_tile_shapes; a tile
+ * configuration is a shape index and 1, 2 or 4 waves per workgroup.  Results
+ * do not depend on the configuration (each voxel sums its pairs in the same
+ * order). */
+typedef struct {
+    int shape;            /* shape index */
+    int dims[3];          /* brick voxels along x, y, z */
+    int waves_per_block;
+    float ms;             /* median forward time */
+} fspb_tune_result;
+
+/* Number of brick shapes; writes dims[3*q .. 3*q+2] for q < max_shapes when
+ * dims is non-NULL (host). */
+int fspb_tile_shapes(int* dims, int max_shapes);
+
+/* Selects the tile configuration of a handle (recomputes its brick schedule
+ * when the shape changes; synchronises the stream then). */
+int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream);
+int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block);
+
+/* Times every tile configuration on this plan (reps timed forwards each,
+ * median) and keeps the fastest.  fluence: device [n_beamlets];
+ * dose_scratch: device [n_vox], overwritten.  results (host, up to
+ * max_results entries) and n_results may be NULL.  Synchronous. */
+int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, int reps,
+                  void* stream, fspb_tune_result* results, int max_results, int* n_results);
+
+/* ---- batches: many plans in one persistent launch -----------------------
+ * A batch schedules every brick of up to 64 plans (sharing the
+ * density-correction mode) over waves_per_cu x (number of CUs) persistent
+ * wavefronts.  The static schedule assigns bricks longest-first to the least
+ * loaded wavefront, so no atomics are needed.  Each wavefront records the wall
+ * clock after its last brick of every plan; fspb_batch_latencies turns those
+ * into per-plan completion times.  The geometries must outlive the batch. */
+typedef struct fspb_batch fspb_batch;
+
+#define FSPB_SCHEDULE_THROUGHPUT 0  /* one longest-first list over all plans */
+#define FSPB_SCHEDULE_LATENCY    1  /* plans by increasing work, bricks longest-first */
+
+/* geoms: host array [n] of handles.  shape / waves_per_block: tile
+ * configuration of the persistent kernel (plans are re-scheduled for that
+ * shape).  policy: FSPB_SCHEDULE_THROUGHPUT minimises the whole launch;
+ * FSPB_SCHEDULE_LATENCY lets small plans complete first.  Synchronises the
+ * stream. */
+int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_per_block,
+                      int waves_per_cu, int policy, void* stream, fspb_batch** out);
+
+/* One persistent launch: dose[p] (device [n_vox of plan p]) = forward of
+ * fluence[p] (device [n_beamlets of plan p]); both arrays are host arrays of
+ * n device pointers.  Asynchronous. */
+int fspb_batch_forward(fspb_batch* b, const float* const* fluence, float* const* dose, void* stream);
+
+/* Captures into a HIP graph owned by the batch: for each plan
+ * fspb_update_density(density[p]) when density is non-NULL (host array of n
+ * device pointers), then the batch forward.  stream must not be the null
+ * stream.  Replace any earlier capture. */
+int fspb_batch_capture(fspb_batch* b, const float* const* fluence, float* const* dose,
+                       const float* const* density, void* stream);
+
+/* Launches the captured graph on stream. */
+int fspb_batch_replay(fspb_batch* b, void* stream);
+
+/* After the last batch forward or replay on stream (the call synchronises
+ * it): plan_ms[p] (host, [n] or NULL) = time from the earliest wavefront start
+ * to plan p's last brick; total_ms = the whole launch.  Device wall clock. */
+int fspb_batch_latencies(const fspb_batch* b, double* plan_ms, double* total_ms, void* stream);
+
+/* Number of persistent wavefronts and scheduled bricks. */
+int fspb_batch_info(const fspb_batch* b, int* n_waves, long long* n_items);
+
+/* Frees the batch (not its geometries).  NULL-safe. */
+void fspb_batch_destroy(fspb_batch* b);
+
 /* Frees the handle.  NULL-safe.  Waits for queued device work to finish,
  * then returns the handle's device buffers to the library's per-device cache
  * (reused by later fspb_create_geometry calls). */

@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FspbError, check, load
 
-__all__ = ["Geometry", "FspbDose", "FspbError", "load"]
+__all__ = ["Geometry", "Batch", "FspbDose", "FspbError", "load"]
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -149,6 +149,47 @@ class Geometry:
               "fspb_count_pairs")
         return (int(tot.value), counts) if per_voxel else int(tot.value)
 
+    def update_density(self, density: torch.Tensor, stream=None) -> None:
+        """Re-runs the density-dependent geometry (smoothing, entrances, depth
+        tables) for a new CT of the same grid; asynchronous, graph-capturable.
+        The tensor must stay alive until the work has run."""
+        d = density
+        if not (isinstance(d, torch.Tensor) and d.is_cuda and d.dtype == torch.float32
+                and d.is_contiguous() and d.numel() == self.n_vox):
+            raise ValueError("density must be a contiguous float32 CUDA tensor of the grid's size")
+        check(load().fspb_update_density(self._handle(), C.c_void_p(d.data_ptr()), _stream(stream)),
+              "fspb_update_density")
+
+    @staticmethod
+    def tile_shapes():
+        L = load()
+        n = L.fspb_tile_shapes(None, 0)
+        dims = (C.c_int * (3 * n))()
+        L.fspb_tile_shapes(dims, n)
+        return [tuple(dims[3 * q:3 * q + 3]) for q in range(n)]
+
+    def set_tile(self, shape: int, waves_per_block: int, stream=None) -> None:
+        check(load().fspb_set_tile(self._handle(), int(shape), int(waves_per_block),
+                                   _stream(stream)), "fspb_set_tile")
+
+    def get_tile(self):
+        s, w = C.c_int(), C.c_int()
+        check(load().fspb_get_tile(self._handle(), C.byref(s), C.byref(w)), "fspb_get_tile")
+        return s.value, w.value
+
+    def autotune(self, fluence: torch.Tensor, reps: int = 3, stream=None):
+        """Times every tile configuration and keeps the fastest; returns the
+        timings as a list of dicts."""
+        f = _dev_f32(fluence, self.device)
+        scratch = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        res = (_lib.fspb_tune_result * 64)()
+        n = C.c_int(0)
+        check(load().fspb_autotune(self._handle(), C.c_void_p(f.data_ptr()),
+                                   C.c_void_p(scratch.data_ptr()), int(reps), _stream(stream),
+                                   res, 64, C.byref(n)), "fspb_autotune")
+        return [dict(shape=r.shape, dims=tuple(r.dims), waves_per_block=r.waves_per_block,
+                     ms=r.ms) for r in res[:n.value]]
+
     def set_dc(self, enabled: bool) -> None:
         check(load().fspb_set_dc(self._handle(), int(bool(enabled))), "fspb_set_dc")
 
@@ -181,6 +222,80 @@ class Geometry:
                   "fspb_beamlet")
             out.update(T=T, W1=W1, W2=W2)
         return out
+
+
+class Batch:
+    """Many plans in one persistent launch (static longest-first schedule),
+    with per-plan completion times and optional HIP-graph capture."""
+
+    def __init__(self, geometries, shape: int = 0, waves_per_block: int = 4,
+                 waves_per_cu: int = 32, policy: str = "latency", stream=None):
+        self.geometries = list(geometries)
+        n = len(self.geometries)
+        pol = {"throughput": _lib.FSPB_SCHEDULE_THROUGHPUT,
+               "latency": _lib.FSPB_SCHEDULE_LATENCY}[policy]
+        hs = (C.c_void_p * n)(*[g._handle() for g in self.geometries])
+        h = C.c_void_p()
+        check(load().fspb_batch_create(n, hs, int(shape), int(waves_per_block), int(waves_per_cu),
+                                       pol, _stream(stream), C.byref(h)), "fspb_batch_create")
+        self._h = h
+        self._keep = None
+
+    def _ptrs(self, tensors, n_expect, what):
+        if len(tensors) != len(self.geometries):
+            raise ValueError(f"need one {what} tensor per plan")
+        out = (C.c_void_p * len(tensors))()
+        for k, (t, g) in enumerate(zip(tensors, self.geometries)):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError(f"{what} {k} must be a contiguous float32 CUDA tensor")
+            if t.numel() != n_expect(g):
+                raise ValueError(f"{what} {k} has {t.numel()} values, expected {n_expect(g)}")
+            out[k] = t.data_ptr()
+        return out
+
+    def forward(self, fluences, doses, stream=None) -> None:
+        fp = self._ptrs(fluences, lambda g: g.n_beamlets, "fluence")
+        dp = self._ptrs(doses, lambda g: g.n_vox, "dose")
+        check(load().fspb_batch_forward(self._h, fp, dp, _stream(stream)), "fspb_batch_forward")
+
+    def capture(self, fluences, doses, densities=None, stream=None) -> None:
+        """Captures (density updates +) the batch forward into a HIP graph.
+        stream must not be the null stream; the tensors must outlive replays."""
+        fp = self._ptrs(fluences, lambda g: g.n_beamlets, "fluence")
+        dp = self._ptrs(doses, lambda g: g.n_vox, "dose")
+        rp = None
+        if densities is not None:
+            rp = self._ptrs(densities, lambda g: g.n_vox, "density")
+        self._keep = (list(fluences), list(doses), None if densities is None else list(densities))
+        check(load().fspb_batch_capture(self._h, fp, dp, rp, _stream(stream)), "fspb_batch_capture")
+
+    def replay(self, stream=None) -> None:
+        check(load().fspb_batch_replay(self._h, _stream(stream)), "fspb_batch_replay")
+
+    def latencies(self, stream=None):
+        """(per-plan completion times in ms, whole launch in ms) of the last run."""
+        n = len(self.geometries)
+        ms = (C.c_double * n)()
+        tot = C.c_double(0)
+        check(load().fspb_batch_latencies(self._h, ms, C.byref(tot), _stream(stream)),
+              "fspb_batch_latencies")
+        return list(ms), tot.value
+
+    def info(self):
+        w, it = C.c_int(), C.c_longlong()
+        check(load().fspb_batch_info(self._h, C.byref(w), C.byref(it)), "fspb_batch_info")
+        return dict(n_waves=w.value, n_items=it.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fspb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FspbDose(torch.autograd.Function):

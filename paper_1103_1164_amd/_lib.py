@@ -19,6 +19,8 @@ FSPB_E_HIP = -2
 FSPB_E_NOMEM = -3
 FSPB_E_STATE = -4
 FSPB_E_UNSUPPORTED = -5
+FSPB_SCHEDULE_THROUGHPUT = 0
+FSPB_SCHEDULE_LATENCY = 1
 
 
 class fspb_ct(C.Structure):
@@ -67,6 +69,11 @@ class fspb_beamlet_info(C.Structure):
                 ("ey", C.c_double * 3), ("entry_margin", C.c_double)]
 
 
+class fspb_tune_result(C.Structure):
+    _fields_ = [("shape", C.c_int), ("dims", C.c_int * 3), ("waves_per_block", C.c_int),
+                ("ms", C.c_float)]
+
+
 # name -> (restype, argtypes); the list of every symbol include/fspb.h declares
 SIGNATURES = {
     "fspb_create_geometry": (C.c_int, [C.POINTER(fspb_ct), C.c_int, C.POINTER(fspb_beam),
@@ -82,6 +89,23 @@ SIGNATURES = {
     "fspb_beamlet": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(fspb_beamlet_info),
                                C.POINTER(C.c_float), C.POINTER(C.c_float),
                                C.POINTER(C.c_float), C.c_int]),
+    "fspb_update_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.c_int]),
+    "fspb_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "fspb_get_tile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "fspb_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                C.POINTER(fspb_tune_result), C.c_int, C.POINTER(C.c_int)]),
+    "fspb_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int,
+                                    C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fspb_batch_forward": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.c_void_p]),
+    "fspb_batch_capture": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.c_void_p]),
+    "fspb_batch_replay": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fspb_batch_latencies": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.c_void_p]),
+    "fspb_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
+    "fspb_batch_destroy": (None, [C.c_void_p]),
     "fspb_destroy": (None, [C.c_void_p]),
     "fspb_release_cached_memory": (C.c_int, []),
     "fspb_error_string": (C.c_char_p, [C.c_int]),

@@ -21,6 +21,8 @@
 
 #include <float.h>
 
+#include <algorithm>
+
 namespace fspb {
 
 __device__ __forceinline__ float wave_min(float x) {
@@ -48,8 +50,9 @@ __device__ __forceinline__ void voxel_q(const PlanConst& P, int i, int j, int k,
 
 // Depth below the entrance and lateral offsets of a voxel for one beamlet,
 // and the pair test of Algorithm A1 step 8 (inside the ROI cylinder, t >= 0).
-__device__ __forceinline__ bool pair_coords(const BeamletDesc& d, const PlanConst& P, float qx,
-                                            float qy, float qz, float& t, float& xp, float& yp) {
+template <class BD>
+__device__ __forceinline__ bool pair_coords(const BD& d, const PlanConst& P, float qx, float qy,
+                                            float qz, float& t, float& xp, float& yp) {
     t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
     xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
     yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
@@ -57,50 +60,66 @@ __device__ __forceinline__ bool pair_coords(const BeamletDesc& d, const PlanCons
 }
 
 // ---------------------------------------------------------------------------
-// Forward kernel, three modes sharing the candidate search:
+// Forward pass over one brick, three modes sharing the candidate search:
 //   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
 //   kCount  number of evaluated pairs per voxel
 //   kCost   number of candidate beamlets per brick (scheduling estimate)
+// A brick is BX x BY x BZ = 64 voxels, one per lane.
 enum { kDose = 0, kCount = 1, kCost = 2 };
 
-template <bool DC, int MODE>
-__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __restrict__ order,
-                                                    const float* __restrict__ fluence,
-                                                    float* __restrict__ dose,
-                                                    int* __restrict__ out_int) {
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ int bricks_x(const PlanConst& P) { return (P.nx + BX - 1) / BX; }
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ int bricks_y(const PlanConst& P) { return (P.ny + BY - 1) / BY; }
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ int bricks_total(const PlanConst& P) {
+    return bricks_x<BX, BY, BZ>(P) * bricks_y<BX, BY, BZ>(P) * ((P.nz + BZ - 1) / BZ);
+}
+
+template <bool DC, int MODE, int BX, int BY, int BZ>
+__device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
+                                           const float* fluence_, float* dose_, int* out_int_) {
+    static_assert(BX * BY * BZ == kWave, "a brick holds one voxel per lane");
     const PlanConst& P = a.P;
+    const FSPB_CONST BeamDesc* __restrict__ beams = as_const(a.beams);
+    const FSPB_CONST BeamletDesc* __restrict__ bl = as_const(a.bl);
+    const FSPB_GLOBAL float4* __restrict__ bl4 = as_global(reinterpret_cast<const float4*>(a.bl));
+    const FSPB_GLOBAL float4* __restrict__ facs = as_global(a.fac);
+    const FSPB_GLOBAL float4* __restrict__ dtab = as_global(a.dtab);
+    const FSPB_GLOBAL float4* __restrict__ atab = as_global(a.atab);
+    const FSPB_GLOBAL float2* __restrict__ tT = as_global(a.tT);
+    const FSPB_GLOBAL float4* __restrict__ tTW = as_global(a.tTW);
+    const FSPB_GLOBAL float* __restrict__ fluence = as_global(fluence_);
+    FSPB_GLOBAL float* __restrict__ dose = as_global_rw(dose_);
+    FSPB_GLOBAL int* __restrict__ out_int = as_global_rw(out_int_);
     const int lane = threadIdx.x & (kWave - 1);
-    const int slot = blockIdx.x * 4 + threadIdx.x / kWave;
-    const int n_bricks = P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
-    if (slot >= n_bricks) return;
-    // bricks run in decreasing order of estimated work (longest first), so
-    // the expensive bricks near the isocentre start early and cheap ones fill
-    // the tail; consecutive slots are dealt round-robin to the 8 XCDs.
-    const int brick = order ? order[slot] : slot;
-    const int bx = brick % P.n_bricks_x;
-    const int by = (brick / P.n_bricks_x) % P.n_bricks_y;
-    const int bz = brick / (P.n_bricks_x * P.n_bricks_y);
-    const int i = bx * 4 + (lane & 3), j = by * 4 + ((lane >> 2) & 3), k = bz * 4 + (lane >> 4);
+    const int nbx = bricks_x<BX, BY, BZ>(P), nby = bricks_y<BX, BY, BZ>(P);
+    const int bx = brick % nbx;
+    const int by = (brick / nbx) % nby;
+    const int bz = brick / (nbx * nby);
+    const int i = bx * BX + (lane % BX), j = by * BY + ((lane / BX) % BY),
+              k = bz * BZ + lane / (BX * BY);
     const bool valid = (i < P.nx) && (j < P.ny) && (k < P.nz);
     const long v = ((long)k * P.ny + j) * P.nx + i;
     float qx, qy, qz;
     voxel_q(P, i, j, k, qx, qy, qz);
     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-    if (DC && MODE == kDose && valid) fac = a.fac[v];
-    // bounding sphere of the brick's 4x4x4 voxel centres
+    if (DC && MODE == kDose && valid) fac = facs[v];
+    // bounding sphere of the brick's voxel centres
     float cqx, cqy, cqz;
-    voxel_q(P, bx * 4, by * 4, bz * 4, cqx, cqy, cqz);
-    cqx += 1.5f * P.dx;
-    cqy += 1.5f * P.dy;
-    cqz += 1.5f * P.dz;
-    const float rb = 1.5f * sqrtf(P.dx * P.dx + P.dy * P.dy + P.dz * P.dz) * 1.0001f + 1e-3f;
+    voxel_q(P, bx * BX, by * BY, bz * BZ, cqx, cqy, cqz);
+    const float hx = 0.5f * (BX - 1) * P.dx, hy = 0.5f * (BY - 1) * P.dy, hz = 0.5f * (BZ - 1) * P.dz;
+    cqx += hx;
+    cqy += hy;
+    cqz += hz;
+    const float rb = sqrtf(hx * hx + hy * hy + hz * hz) * 1.0001f + 1e-3f;
     const float Rc = sqrtf(P.R2) + rb;
     const float Rc2 = Rc * Rc;
 
     float acc = 0.0f;
     int cnt = 0, cost = 0;
     for (int b = 0; b < P.n_beams; ++b) {
-        const BeamDesc& B = a.beams[b];
+        const FSPB_CONST BeamDesc& B = beams[b];
         // rectangle of beamlets in the isocentre plane that can reach the brick
         float vx = qx - B.src[0], vy = qy - B.src[1], vz = qz - B.src[2];
         float z = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
@@ -123,7 +142,7 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
         const int m_hi = uniform(min((int)floorf(fm1), B.nbx - 1));
         const int n_lo = uniform(max((int)ceilf(fn0), 0));
         const int n_hi = uniform(min((int)floorf(fn1), B.nby - 1));
-        const int first = uniform(B.first), nbx = uniform(B.nbx);
+        const int first = uniform(B.first), nbl_x = uniform(B.nbx);
         const int nm = m_hi - m_lo + 1;
         const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
         float accb = 0.0f;
@@ -135,10 +154,10 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
             int ib = 0;
             float fi = 1.0f;
             if (c < total) {
-                ib = first + (n_lo + c / nm) * nbx + (m_lo + c % nm);
-                if (MODE == kDose || fluence) fi = fluence[ib];
+                ib = first + (n_lo + c / nm) * nbl_x + (m_lo + c % nm);
+                if (MODE == kDose || fluence_) fi = fluence[ib];
                 if (fi != 0.0f) {
-                    const float4* dp = reinterpret_cast<const float4*>(a.bl + ib);
+                    const FSPB_GLOBAL float4* dp = bl4 + 6 * ib;   // 96-byte descriptor
                     const float4 r0 = dp[0], r1 = dp[1], r2 = dp[2];
                     float tc = fmaf(cqx, r0.x, fmaf(cqy, r0.y, fmaf(cqz, r0.z, r0.w)));
                     float xc = fmaf(cqx, r1.x, fmaf(cqy, r1.y, fmaf(cqz, r1.z, r1.w)));
@@ -161,11 +180,11 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
             const int pk_f = __builtin_amdgcn_ds_permute(dst << 2, __float_as_int(fi));
             // software pipeline: the next candidate's descriptor is fetched
             // (scalar loads) while the current one is evaluated
-            BeamletDesc dn = a.bl[__builtin_amdgcn_readlane(pk_ib, 0)];
+            BeamletDesc dn = bl[__builtin_amdgcn_readlane(pk_ib, 0)];
             for (int e = 0; e < ncand; ++e) {
                 const BeamletDesc d = dn;
                 const float fe = __int_as_float(__builtin_amdgcn_readlane(pk_f, e));
-                dn = a.bl[__builtin_amdgcn_readlane(pk_ib, min(e + 1, ncand - 1))];
+                dn = bl[__builtin_amdgcn_readlane(pk_ib, min(e + 1, ncand - 1))];
                 float t, xp, yp;
                 // evaluated on every lane (no short circuit) so that the whole
                 // descriptor is fetched in one scalar batch before the branch
@@ -177,8 +196,7 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
                 const float kmag = magnification(t, d);
                 // a candidate with no active lane skips the block (empty exec mask)
                 if (act)
-                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, a.dtab, a.atab, a.tT,
-                                                  a.tTW),
+                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
                                 accb);
             }
         }
@@ -192,6 +210,47 @@ __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __res
         else
             dose[v] = acc;
     }
+}
+
+// One plan: wave w of the grid takes the brick in slot w of `order` (bricks in
+// decreasing order of estimated work, so expensive bricks start early and
+// cheap ones fill the tail; consecutive workgroups are dealt round-robin to
+// the 8 XCDs).
+template <bool DC, int MODE, int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __restrict__ order,
+                                                    const float* __restrict__ fluence,
+                                                    float* __restrict__ dose,
+                                                    int* __restrict__ out_int) {
+    const int slot = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (slot >= bricks_total<BX, BY, BZ>(a.P)) return;
+    const int brick = order ? order[slot] : slot;
+    brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int);
+}
+
+// Many plans in one persistent launch: wave q walks its own static list of
+// (plan, brick) items, built on the host by longest-processing-time-first
+// assignment.  ts_done[plan * n_waves + q] receives the wall clock after the
+// wave's last item of that plan; ts_start[q] the wave's start.  No atomics.
+template <bool DC, int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void dose_forward_batch(
+    const DoseArgs* __restrict__ plans, const int2* __restrict__ items,
+    const int* __restrict__ wave_begin, int n_waves, BatchPtrs ptrs,
+    unsigned long long* __restrict__ ts_done, unsigned long long* __restrict__ ts_start) {
+    const int q = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (q >= n_waves) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (ts_start && lane == 0) ts_start[q] = wall_clock64();
+    const int it0 = uniform(wave_begin[q]), it1 = uniform(wave_begin[q + 1]);
+    for (int it = it0; it < it1; ++it) {
+        const int p = uniform(items[it].x), brick = uniform(items[it].y);
+        brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p], nullptr);
+        if (ts_done && lane == 0) ts_done[(long)p * n_waves + q] = wall_clock64();
+    }
+}
+
+__global__ void fill_u64(unsigned long long* __restrict__ p, long n, unsigned long long v) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x)
+        p[q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -303,8 +362,9 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                     const long v = ((long)k * P.ny + j) * P.nx + i;
                     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                     if (DC) fac = a.fac[v];
-                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P, a.dtab,
-                                                   a.atab, a.tT, a.tTW),
+                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                                   as_global(a.dtab), as_global(a.atab),
+                                                   as_global(a.tT), as_global(a.tTW)),
                                acc);
                 }
             }
@@ -343,31 +403,88 @@ __global__ void sum_counts_final(const unsigned long long* __restrict__ part, in
 }
 
 // ---------------------------------------------------------------------------
-static int fwd_blocks(const PlanConst& P) {
-    long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
-    return (int)((n_bricks + 3) / 4);
+// Brick shapes the kernels are built for (index = TileCfg::shape).
+struct Shape {
+    int x, y, z;
+};
+static const Shape kShapes[kNumShapes] = {{4, 4, 4}, {8, 4, 2}, {4, 8, 2}, {8, 2, 4}};
+
+long brick_count(const PlanConst& P, int shape) {
+    const Shape& S = kShapes[shape];
+    return (long)((P.nx + S.x - 1) / S.x) * ((P.ny + S.y - 1) / S.y) * ((P.nz + S.z - 1) / S.z);
 }
 
-void launch_forward(const DoseArgs& a, bool dc, const int* order, const float* fluence,
-                    float* dose, hipStream_t s) {
-    dim3 grid(fwd_blocks(a.P)), block(256);
+void shape_dims(int shape, int d[3]) {
+    d[0] = kShapes[shape].x;
+    d[1] = kShapes[shape].y;
+    d[2] = kShapes[shape].z;
+}
+
+template <bool DC, int MODE>
+static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
+                        float* dose, int* out_int, hipStream_t s) {
+    const int wpb = cfg.waves_per_block;
+    const long nb = brick_count(a.P, cfg.shape);
+    dim3 grid((unsigned)((nb + wpb - 1) / wpb)), block(kWave * wpb);
+#define FSPB_SHAPE(ID, X, Y, Z)                                                                \
+    case ID:                                                                                   \
+        hipLaunchKernelGGL((dose_forward<DC, MODE, X, Y, Z>), grid, block, 0, s, a, order,     \
+                           fluence, dose, out_int);                                            \
+        break;
+    switch (cfg.shape) {
+        FSPB_SHAPE(0, 4, 4, 4)
+        FSPB_SHAPE(1, 8, 4, 2)
+        FSPB_SHAPE(2, 4, 8, 2)
+        FSPB_SHAPE(3, 8, 2, 4)
+    }
+#undef FSPB_SHAPE
+}
+
+void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
+                    const float* fluence, float* dose, hipStream_t s) {
     if (dc)
-        hipLaunchKernelGGL((dose_forward<true, kDose>), grid, block, 0, s, a, order, fluence, dose,
-                           (int*)nullptr);
+        launch_mode<true, kDose>(a, cfg, order, fluence, dose, nullptr, s);
     else
-        hipLaunchKernelGGL((dose_forward<false, kDose>), grid, block, 0, s, a, order, fluence, dose,
-                           (int*)nullptr);
+        launch_mode<false, kDose>(a, cfg, order, fluence, dose, nullptr, s);
 }
 
-void launch_count(const DoseArgs& a, const int* order, const float* fluence, int* counts,
-                  hipStream_t s) {
-    hipLaunchKernelGGL((dose_forward<false, kCount>), dim3(fwd_blocks(a.P)), dim3(256), 0, s, a,
-                       order, fluence, (float*)nullptr, counts);
+void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
+                  int* counts, hipStream_t s) {
+    launch_mode<false, kCount>(a, cfg, order, fluence, nullptr, counts, s);
 }
 
-void launch_brick_cost(const DoseArgs& a, int* cost, hipStream_t s) {
-    hipLaunchKernelGGL((dose_forward<false, kCost>), dim3(fwd_blocks(a.P)), dim3(256), 0, s, a,
-                       (const int*)nullptr, (const float*)nullptr, (float*)nullptr, cost);
+void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s) {
+    launch_mode<false, kCost>(a, cfg, nullptr, nullptr, nullptr, cost, s);
+}
+
+void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
+                          const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
+                          unsigned long long* ts_done, unsigned long long* ts_start,
+                          hipStream_t s) {
+    const int wpb = cfg.waves_per_block;
+    dim3 grid((unsigned)((n_waves + wpb - 1) / wpb)), block(kWave * wpb);
+#define FSPB_SHAPE(ID, X, Y, Z)                                                                 \
+    case ID:                                                                                    \
+        if (dc)                                                                                 \
+            hipLaunchKernelGGL((dose_forward_batch<true, X, Y, Z>), grid, block, 0, s, plans,   \
+                               items, wave_begin, n_waves, ptrs, ts_done, ts_start);            \
+        else                                                                                    \
+            hipLaunchKernelGGL((dose_forward_batch<false, X, Y, Z>), grid, block, 0, s, plans,  \
+                               items, wave_begin, n_waves, ptrs, ts_done, ts_start);            \
+        break;
+    switch (cfg.shape) {
+        FSPB_SHAPE(0, 4, 4, 4)
+        FSPB_SHAPE(1, 8, 4, 2)
+        FSPB_SHAPE(2, 4, 8, 2)
+        FSPB_SHAPE(3, 8, 2, 4)
+    }
+#undef FSPB_SHAPE
+}
+
+void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<long>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_u64, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,

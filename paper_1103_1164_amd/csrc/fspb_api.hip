@@ -162,6 +162,13 @@ struct fspb_geometry {
     float* w3 = nullptr;
     int* counts = nullptr;
     int* order = nullptr;      // bricks in decreasing order of estimated work
+    float* tmp0 = nullptr;     // smoothing intermediates (alias the depth tables when they fit)
+    float* tmp1 = nullptr;
+    TileCfg tile;
+    std::vector<int> h_cost;   // estimated work per brick for the current tile shape
+    TraceGrid tg{};
+    TraceParams tp{};
+    hipDeviceProp_t prop{};
     unsigned long long* partial = nullptr;
     unsigned long long* total = nullptr;
     // host copies
@@ -332,6 +339,34 @@ const char* fspb_error_string(int code) {
 
 const char* fspb_last_error(void) { return g_last_error.c_str(); }
 
+// Brick schedule for the handle's tile shape: estimated work per brick
+// (candidate beamlets), longest first (counting sort on the integer cost,
+// stable in brick index order).  Synchronises the stream.
+static int build_order(fspb_geometry* G, hipStream_t s) {
+    const long nb = brick_count(G->P, G->tile.shape);
+    launch_brick_cost(G->args(), G->tile, G->order, s);
+    HIP_TRY(hipGetLastError());
+    std::vector<int>& cost = G->h_cost;
+    cost.assign(nb, 0);
+    std::vector<int> idx(nb);
+    HIP_TRY(hipMemcpyAsync(cost.data(), G->order, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int cmax = 0;
+    for (long q = 0; q < nb; ++q) cmax = std::max(cmax, cost[q]);
+    std::vector<int> hist((size_t)cmax + 1, 0);
+    for (long q = 0; q < nb; ++q) ++hist[std::max(cost[q], 0)];
+    int acc = 0;
+    for (int c = cmax; c >= 0; --c) {
+        int h = hist[c];
+        hist[c] = acc;
+        acc += h;
+    }
+    for (long q = 0; q < nb; ++q) idx[hist[std::max(cost[q], 0)]++] = (int)q;
+    HIP_TRY(hipMemcpyAsync(G->order, idx.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return FSPB_OK;
+}
+
 static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
                        const fspb_tables* t, const fspb_options* opts, hipStream_t s,
                        fspb_geometry* G) {
@@ -391,10 +426,8 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     P.at_n = t->A.n;
     P.a_cols = std::max(t->n_theta - 1, 1);
     P.dc = o.dc_enabled;
-    P.n_bricks_x = (nx + 3) / 4;
-    P.n_bricks_y = (ny + 3) / 4;
-    P.n_bricks_z = (nz + 3) / 4;
-    const long n_bricks = (long)P.n_bricks_x * P.n_bricks_y * P.n_bricks_z;
+    long max_bricks = 0;
+    for (int sh = 0; sh < kNumShapes; ++sh) max_bricks = std::max(max_bricks, brick_count(P, sh));
 
     // ---- host-side table packing -------------------------------------------
     const int dn = t->u1x.n;
@@ -511,7 +544,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     ALLOC(G->atab, sizeof(float4) * atab.size());
     ALLOC(G->denstab, sizeof(float) * dens.size());
     ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
-    ALLOC(G->order, sizeof(int) * n_bricks);
+    ALLOC(G->order, sizeof(int) * max_bricks);
     if (o.dc_enabled) {
         ALLOC(G->tTW, 2 * sizeof(float4) * (size_t)nbl * G->k_stride);
         ALLOC(G->rhohat, sizeof(float) * nv);
@@ -529,17 +562,16 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         HIP_TRY(hipMemcpyAsync(G->w3, w3.data(), sizeof(float) * w3.size(), hipMemcpyHostToDevice, s));
         // the two intermediate passes use the (not yet written) depth-table
         // buffer as scratch when it is large enough, else two pool blocks
-        float *tmp0 = nullptr, *tmp1 = nullptr;
         const size_t tt_bytes = sizeof(float2) * (size_t)nbl * G->k_stride;
         if (tt_bytes >= 2 * sizeof(float) * (size_t)nv) {
-            tmp0 = reinterpret_cast<float*>(G->tT);
-            tmp1 = tmp0 + nv;
+            G->tmp0 = reinterpret_cast<float*>(G->tT);
+            G->tmp1 = G->tmp0 + nv;
         } else {
-            ALLOC(tmp0, sizeof(float) * nv);
-            ALLOC(tmp1, sizeof(float) * nv);
+            ALLOC(G->tmp0, sizeof(float) * nv);
+            ALLOC(G->tmp1, sizeof(float) * nv);
         }
-        launch_smooth(ct->density, tmp0, tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3, G->smooth_r,
-                      G->denstab, G->dens, s);
+        launch_smooth(ct->density, G->tmp0, G->tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3,
+                      G->smooth_r, G->denstab, G->dens, s);
         HIP_TRY(hipGetLastError());
 #undef ALLOC
     }
@@ -548,7 +580,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
                     ct->oz + (nz - 0.5) * ct->dz};
     launch_setup(G->beam_in, n_beams, nbl, lo, hi, step, G->frames, s);
     HIP_TRY(hipGetLastError());
-    TraceGrid tg;
+    TraceGrid& tg = G->tg;
     tg.o[0] = ct->ox;
     tg.o[1] = ct->oy;
     tg.o[2] = ct->oz;
@@ -558,7 +590,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     tg.n[0] = nx;
     tg.n[1] = ny;
     tg.n[2] = nz;
-    TraceParams tp;
+    TraceParams& tp = G->tp;
     tp.step = step;
     tp.rho_surface = o.rho_surface;
     tp.theta_step = t->n_theta > 1 ? (double)t->theta_step : 1.0;
@@ -569,27 +601,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
                  G->tinfo, s);
     HIP_TRY(hipGetLastError());
 
-    // schedule: estimated work per brick (candidate beamlets), longest first
-    // (counting sort on the integer cost, stable in brick index order)
-    {
-        launch_brick_cost(G->args(), G->order, s);
-        HIP_TRY(hipGetLastError());
-        std::vector<int> cost(n_bricks), idx(n_bricks);
-        HIP_TRY(hipMemcpyAsync(cost.data(), G->order, sizeof(int) * n_bricks, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        const int cap = 1 << 16;
-        std::vector<int> hist(cap + 1, 0);
-        for (long q = 0; q < n_bricks; ++q) ++hist[std::min(std::max(cost[q], 0), cap)];
-        int acc = 0;
-        for (int c = cap; c >= 0; --c) {
-            int h = hist[c];
-            hist[c] = acc;
-            acc += h;
-        }
-        for (long q = 0; q < n_bricks; ++q) idx[hist[std::min(std::max(cost[q], 0), cap)]++] = (int)q;
-        HIP_TRY(hipMemcpyAsync(G->order, idx.data(), sizeof(int) * n_bricks, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
+    return build_order(G, s);
     return FSPB_OK;
 }
 
@@ -620,7 +632,8 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
 
 int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream) {
     if (!g || !fluence || !dose) return fail(FSPB_E_ARG, "forward: NULL argument");
-    launch_forward(g->args(), g->dc_enabled != 0, g->order, fluence, dose, (hipStream_t)stream);
+    launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose,
+                   (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
@@ -648,7 +661,7 @@ int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
         if ((rc = g->alloc((void**)&g->total, sizeof(unsigned long long))) != FSPB_OK) return rc;
     }
     int* c = counts ? counts : g->counts;
-    launch_count(g->args(), g->order, fluence, c, s);
+    launch_count(g->args(), g->tile, g->order, fluence, c, s);
     HIP_TRY(hipGetLastError());
     launch_sum_counts(c, nv, g->partial, n_part, g->total, s);
     HIP_TRY(hipGetLastError());
@@ -763,6 +776,348 @@ int fspb_release_cached_memory(void) {
     }
     for (void* p : drop) HIP_TRY(hipFree(p));
     return FSPB_OK;
+}
+
+
+int fspb_tile_shapes(int* dims, int max_shapes) {
+    if (dims)
+        for (int q = 0; q < std::min(max_shapes, kNumShapes); ++q) shape_dims(q, dims + 3 * q);
+    return kNumShapes;
+}
+
+int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream) {
+    if (!g) return fail(FSPB_E_ARG, "set_tile: NULL handle");
+    if (shape < 0 || shape >= kNumShapes) return fail(FSPB_E_ARG, "set_tile: shape %d out of range", shape);
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        return fail(FSPB_E_ARG, "set_tile: waves_per_block must be 1, 2 or 4");
+    const bool rebuild = shape != g->tile.shape;
+    g->tile.shape = shape;
+    g->tile.waves_per_block = waves_per_block;
+    return rebuild ? build_order(g, (hipStream_t)stream) : FSPB_OK;
+}
+
+int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block) {
+    if (!g || !shape || !waves_per_block) return fail(FSPB_E_ARG, "get_tile: NULL argument");
+    *shape = g->tile.shape;
+    *waves_per_block = g->tile.waves_per_block;
+    return FSPB_OK;
+}
+
+int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, int reps,
+                  void* stream, fspb_tune_result* results, int max_results, int* n_results) {
+    if (!g || !fluence || !dose_scratch || reps < 1)
+        return fail(FSPB_E_ARG, "autotune: NULL argument or reps < 1");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int wpbs[3] = {1, 2, 4};
+    TileCfg best = g->tile;
+    float best_ms = 1e30f;
+    int n = 0, rc = FSPB_OK;
+    for (int sh = 0; sh < kNumShapes && rc == FSPB_OK; ++sh) {
+        for (int w = 0; w < 3 && rc == FSPB_OK; ++w) {
+            rc = fspb_set_tile(g, sh, wpbs[w], stream);
+            if (rc) break;
+            std::vector<float> ms;
+            launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose_scratch, s);
+            for (int r = 0; r < reps; ++r) {
+                (void)hipEventRecord(e0, s);
+                launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence,
+                               dose_scratch, s);
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(FSPB_E_HIP, "autotune: forward failed");
+                    break;
+                }
+                float t = 0;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ms.push_back(t);
+            }
+            if (rc) break;
+            std::sort(ms.begin(), ms.end());
+            const float med = ms[ms.size() / 2];
+            if (results && n < max_results) {
+                results[n].shape = sh;
+                shape_dims(sh, results[n].dims);
+                results[n].waves_per_block = wpbs[w];
+                results[n].ms = med;
+            }
+            ++n;
+            if (med < best_ms) {
+                best_ms = med;
+                best = g->tile;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (n_results) *n_results = n;
+    return fspb_set_tile(g, best.shape, best.waves_per_block, stream);
+}
+
+int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
+    if (!g || !density) return fail(FSPB_E_ARG, "update_density: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const PlanConst& P = g->P;
+    if (g->dc_created) {
+        launch_smooth(density, g->tmp0, g->tmp1, g->rhohat, g->fac, P.nx, P.ny, P.nz, g->w3,
+                      g->smooth_r, g->denstab, g->dens, s);
+        HIP_TRY(hipGetLastError());
+    }
+    launch_trace(g->frames, g->n_beamlets, density, g->tg, g->tp, g->denstab, g->dens, g->tT,
+                 g->tTW, g->desc, g->tinfo, s);
+    HIP_TRY(hipGetLastError());
+    g->host_ready = false;
+    return FSPB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many plans in one persistent launch.
+struct fspb_batch {
+    int device = 0;
+    int n_plans = 0, n_waves = 0, dc = 0;
+    TileCfg tile;
+    std::vector<fspb_geometry*> plans;
+    std::vector<std::pair<void*, size_t>> blocks;
+    DoseArgs* d_args = nullptr;
+    int2* d_items = nullptr;
+    int* d_begin = nullptr;
+    unsigned long long* ts_done = nullptr;
+    unsigned long long* ts_start = nullptr;
+    long n_items = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double clock_khz = 100000.0;
+
+    int alloc(void** p, size_t bytes) {
+        size_t cls = 0;
+        int rc = pool_alloc(device, p, bytes, &cls);
+        if (rc == FSPB_OK) blocks.push_back({*p, cls});
+        return rc;
+    }
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        for (auto& b : blocks) pool_free(device, b.first, b.second);
+        blocks.clear();
+    }
+};
+
+static int batch_enqueue(fspb_batch* b, const float* const* fluence, float* const* dose,
+                         const float* const* density, hipStream_t s) {
+    for (int p = 0; p < b->n_plans; ++p)
+        if (!fluence[p] || !dose[p]) return fail(FSPB_E_ARG, "batch: NULL fluence or dose of plan %d", p);
+    if (density)
+        for (int p = 0; p < b->n_plans; ++p) {
+            int rc = fspb_update_density(b->plans[p], density[p], s);
+            if (rc) return rc;
+        }
+    BatchPtrs ptrs = {};
+    for (int p = 0; p < b->n_plans; ++p) {
+        ptrs.fluence[p] = fluence[p];
+        ptrs.dose[p] = dose[p];
+    }
+    launch_fill_u64(b->ts_done, (long)b->n_plans * b->n_waves, 0ULL, s);
+    HIP_TRY(hipGetLastError());
+    launch_forward_batch(b->dc != 0, b->tile, b->d_args, b->d_items, b->d_begin, b->n_waves, ptrs,
+                         b->ts_done, b->ts_start, s);
+    HIP_TRY(hipGetLastError());
+    return FSPB_OK;
+}
+
+extern "C" {
+
+int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_per_block,
+                      int waves_per_cu, int policy, void* stream, fspb_batch** out) {
+    if (!out) return fail(FSPB_E_ARG, "batch_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || !geoms) return fail(FSPB_E_ARG, "batch_create: need n >= 1 geometries");
+    if (n > kMaxBatchPlans) return fail(FSPB_E_ARG, "batch_create: at most %d plans", kMaxBatchPlans);
+    if (shape < 0 || shape >= kNumShapes) return fail(FSPB_E_ARG, "batch_create: bad shape");
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        return fail(FSPB_E_ARG, "batch_create: waves_per_block must be 1, 2 or 4");
+    if (waves_per_cu < 1 || waves_per_cu > 32)
+        return fail(FSPB_E_ARG, "batch_create: waves_per_cu must be 1..32");
+    if (policy != FSPB_SCHEDULE_THROUGHPUT && policy != FSPB_SCHEDULE_LATENCY)
+        return fail(FSPB_E_ARG, "batch_create: unknown schedule policy %d", policy);
+    for (int p = 0; p < n; ++p) {
+        if (!geoms[p]) return fail(FSPB_E_ARG, "batch_create: geometry %d is NULL", p);
+        if (geoms[p]->dc_enabled != geoms[0]->dc_enabled)
+            return fail(FSPB_E_ARG, "batch_create: plans must share the density-correction mode");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    fspb_batch* B = new (std::nothrow) fspb_batch();
+    if (!B) return fail(FSPB_E_NOMEM, "host allocation failed");
+    B->device = geoms[0]->device;
+    B->n_plans = n;
+    B->dc = geoms[0]->dc_enabled;
+    B->tile.shape = shape;
+    B->tile.waves_per_block = waves_per_block;
+    B->plans.assign(geoms, geoms + n);
+    auto bail = [&](int rc) {
+        (void)hipStreamSynchronize(s);
+        B->release();
+        delete B;
+        return rc;
+    };
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, B->device) == hipSuccess) cus = prop.multiProcessorCount;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, B->device) == hipSuccess && khz > 0)
+            B->clock_khz = khz;
+    }
+    B->n_waves = waves_per_cu * cus;
+    // items: every brick of every plan with its estimated work for the batch
+    // shape; longest-processing-time-first assignment to the waves
+    struct Item {
+        int plan, brick, cost;
+    };
+    std::vector<Item> items;
+    for (int p = 0; p < n; ++p) {
+        fspb_geometry* g = geoms[p];
+        if (g->tile.shape != shape) {
+            int rc = fspb_set_tile(g, shape, g->tile.waves_per_block, stream);
+            if (rc) return bail(rc);
+        }
+        const long nb = brick_count(g->P, shape);
+        for (long q = 0; q < nb; ++q) items.push_back({p, (int)q, g->h_cost[q] + 4});
+    }
+    if (policy == FSPB_SCHEDULE_THROUGHPUT) {
+        // one longest-first list over all plans: shortest makespan
+        std::stable_sort(items.begin(), items.end(),
+                         [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    } else {
+        // plans in increasing order of total work, each plan's bricks
+        // longest-first: small plans complete early
+        std::vector<long long> tot(n, 0);
+        for (const Item& it : items) tot[it.plan] += it.cost;
+        std::vector<int> rank(n);
+        std::vector<int> ord(n);
+        for (int p = 0; p < n; ++p) ord[p] = p;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return tot[x] < tot[y]; });
+        for (int r = 0; r < n; ++r) rank[ord[r]] = r;
+        std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) {
+            if (rank[x.plan] != rank[y.plan]) return rank[x.plan] < rank[y.plan];
+            return x.cost > y.cost;
+        });
+    }
+    std::vector<std::vector<int2>> per(B->n_waves);
+    std::vector<std::pair<long long, int>> heap;
+    heap.reserve(B->n_waves);
+    for (int w = 0; w < B->n_waves; ++w) heap.push_back({0LL, w});
+    auto cmp = [](const std::pair<long long, int>& a, const std::pair<long long, int>& b) {
+        return a.first > b.first || (a.first == b.first && a.second > b.second);
+    };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    for (const Item& it : items) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        auto& top = heap.back();
+        per[top.second].push_back(make_int2(it.plan, it.brick));
+        top.first += it.cost;
+        std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    std::vector<int2> flat;
+    std::vector<int> begin(B->n_waves + 1, 0);
+    for (int w = 0; w < B->n_waves; ++w) {
+        begin[w] = (int)flat.size();
+        flat.insert(flat.end(), per[w].begin(), per[w].end());
+    }
+    begin[B->n_waves] = (int)flat.size();
+    B->n_items = (long)flat.size();
+    std::vector<DoseArgs> args(n);
+    for (int p = 0; p < n; ++p) args[p] = geoms[p]->args();
+    int rc;
+    if ((rc = B->alloc((void**)&B->d_args, sizeof(DoseArgs) * n))) return bail(rc);
+    if ((rc = B->alloc((void**)&B->d_items, sizeof(int2) * std::max<size_t>(flat.size(), 1)))) return bail(rc);
+    if ((rc = B->alloc((void**)&B->d_begin, sizeof(int) * begin.size()))) return bail(rc);
+    if ((rc = B->alloc((void**)&B->ts_done, sizeof(unsigned long long) * (size_t)n * B->n_waves))) return bail(rc);
+    if ((rc = B->alloc((void**)&B->ts_start, sizeof(unsigned long long) * B->n_waves))) return bail(rc);
+    if (hipMemcpyAsync(B->d_args, args.data(), sizeof(DoseArgs) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(B->d_items, flat.data(), sizeof(int2) * flat.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(B->d_begin, begin.data(), sizeof(int) * begin.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(FSPB_E_HIP, "batch_create: copy failed"));
+    *out = B;
+    return FSPB_OK;
+}
+
+int fspb_batch_forward(fspb_batch* b, const float* const* fluence, float* const* dose, void* stream) {
+    if (!b || !fluence || !dose) return fail(FSPB_E_ARG, "batch_forward: NULL argument");
+    return batch_enqueue(b, fluence, dose, nullptr, (hipStream_t)stream);
+}
+
+int fspb_batch_capture(fspb_batch* b, const float* const* fluence, float* const* dose,
+                       const float* const* density, void* stream) {
+    if (!b || !fluence || !dose) return fail(FSPB_E_ARG, "batch_capture: NULL argument");
+    if (!stream) return fail(FSPB_E_ARG, "batch_capture: capture needs a non-null stream");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = batch_enqueue(b, fluence, dose, density, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FSPB_E_HIP, "batch_capture: %s", hipGetErrorString(e));
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+    return FSPB_OK;
+}
+
+int fspb_batch_replay(fspb_batch* b, void* stream) {
+    if (!b) return fail(FSPB_E_ARG, "batch_replay: NULL batch");
+    if (!b->exec) return fail(FSPB_E_STATE, "batch_replay: nothing captured");
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return FSPB_OK;
+}
+
+int fspb_batch_latencies(const fspb_batch* b, double* plan_ms, double* total_ms, void* stream) {
+    if (!b) return fail(FSPB_E_ARG, "batch_latencies: NULL batch");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<unsigned long long> done((size_t)b->n_plans * b->n_waves), start(b->n_waves);
+    HIP_TRY(hipMemcpy(done.data(), b->ts_done, sizeof(unsigned long long) * done.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(start.data(), b->ts_start, sizeof(unsigned long long) * start.size(), hipMemcpyDeviceToHost));
+    unsigned long long t0 = ~0ULL, tend = 0;
+    for (unsigned long long v : start) t0 = std::min(t0, v);
+    for (int p = 0; p < b->n_plans; ++p) {
+        unsigned long long m = 0;
+        for (int w = 0; w < b->n_waves; ++w) m = std::max(m, done[(size_t)p * b->n_waves + w]);
+        tend = std::max(tend, m);
+        if (plan_ms) plan_ms[p] = m > t0 ? (double)(m - t0) / b->clock_khz : 0.0;
+    }
+    if (total_ms) *total_ms = tend > t0 ? (double)(tend - t0) / b->clock_khz : 0.0;
+    return FSPB_OK;
+}
+
+int fspb_batch_info(const fspb_batch* b, int* n_waves, long long* n_items) {
+    if (!b) return fail(FSPB_E_ARG, "batch_info: NULL batch");
+    if (n_waves) *n_waves = b->n_waves;
+    if (n_items) *n_items = b->n_items;
+    return FSPB_OK;
+}
+
+void fspb_batch_destroy(fspb_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    b->release();
+    delete b;
 }
 
 }  // extern "C"

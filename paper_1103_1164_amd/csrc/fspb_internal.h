@@ -77,7 +77,6 @@ struct PlanConst {
     float inv_d;          // 1 / ray sample step
     float dt_inv, dt_off, at_inv, at_off;  // table coordinate = value * inv + off
     int dt_n, at_n, a_cols, dc;
-    int n_bricks_x, n_bricks_y, n_bricks_z, pad0;
 };
 
 // Density-table grid (host copy of start/step/n for the factor kernel and

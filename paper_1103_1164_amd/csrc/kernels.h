@@ -49,11 +49,33 @@ struct DoseArgs {
     const float4* tTW;
 };
 
-void launch_forward(const DoseArgs& a, bool dc, const int* order, const float* fluence,
-                    float* dose, hipStream_t s);
-void launch_count(const DoseArgs& a, const int* order, const float* fluence, int* counts,
-                  hipStream_t s);
-void launch_brick_cost(const DoseArgs& a, int* cost, hipStream_t s);
+// Forward-kernel tile configuration: brick shape (index into the built
+// shapes) and waves per workgroup.
+constexpr int kNumShapes = 4;
+struct TileCfg {
+    int shape = 0;
+    int waves_per_block = 4;
+};
+long brick_count(const PlanConst& P, int shape);
+void shape_dims(int shape, int d[3]);
+
+void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
+                    const float* fluence, float* dose, hipStream_t s);
+void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
+                  int* counts, hipStream_t s);
+void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s);
+// Per-plan fluence and dose pointers of a batch, passed by value as a kernel
+// argument (so a captured graph keeps them).
+constexpr int kMaxBatchPlans = 64;
+struct BatchPtrs {
+    const float* fluence[kMaxBatchPlans];
+    float* dose[kMaxBatchPlans];
+};
+void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
+                          const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
+                          unsigned long long* ts_done, unsigned long long* ts_start,
+                          hipStream_t s);
+void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStream_t s);
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     hipStream_t s);
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,

@@ -16,6 +16,30 @@
 
 namespace fspb {
 
+// Address-space views: table and grid pointers of a plan may be loaded from
+// memory (batched launches), where the compiler cannot infer that they are
+// global; the casts keep vector loads global and wave-uniform reads scalar.
+// (The host pass only parses these functions; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FSPB_GLOBAL __attribute__((address_space(1)))
+#define FSPB_CONST __attribute__((address_space(4)))
+#else
+#define FSPB_GLOBAL
+#define FSPB_CONST
+#endif
+template <class T>
+__device__ __forceinline__ const FSPB_GLOBAL T* as_global(const T* p) {
+    return (const FSPB_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ FSPB_GLOBAL T* as_global_rw(T* p) {
+    return (FSPB_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const FSPB_CONST T* as_const(const T* p) {
+    return (const FSPB_CONST T*)p;
+}
+
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -39,7 +63,8 @@ __device__ __forceinline__ float clampf(float x, float lo, float hi) {
 }
 
 // SAD / |r_a| for a voxel at depth t below the beamlet's entrance.
-__device__ __forceinline__ float magnification(float t, const BeamletDesc& b) {
+template <class BD>
+__device__ __forceinline__ float magnification(float t, const BD& b) {
     return b.sad * fast_rcp(t + b.s_entry);
 }
 
@@ -47,13 +72,13 @@ __device__ __forceinline__ float magnification(float t, const BeamletDesc& b) {
 // below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
 // fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
 // k = SAD / |r_a| (see magnification()) is computed by the caller.
-template <bool DC>
-__device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
-                                           const BeamletDesc& b, float4 fac, const PlanConst& P,
-                                           const float4* __restrict__ dtab,
-                                           const float4* __restrict__ atab,
-                                           const float2* __restrict__ tT,
-                                           const float4* __restrict__ tTW) {
+template <bool DC, class BD>
+__device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k, const BD& b,
+                                           float4 fac, const PlanConst& P,
+                                           const FSPB_GLOBAL float4* __restrict__ dtab,
+                                           const FSPB_GLOBAL float4* __restrict__ atab,
+                                           const FSPB_GLOBAL float2* __restrict__ tT,
+                                           const FSPB_GLOBAL float4* __restrict__ tTW) {
     // magnification to the isocentre plane and inverse square (Eq. 2)
     float x = xp * k, y = yp * k;
     float isq = k * (0.25f * k);   // (SAD/|r_a|)^2 times the 1/4 of the two 2p factors
@@ -77,7 +102,7 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     float teq, W1 = 0.0f, W2 = 0.0f;
     if (DC) {
         const float4 r0 = tTW[2 * (b.tab_off + j)];
-        const float2 r1 = *reinterpret_cast<const float2*>(&tTW[2 * (b.tab_off + j) + 1]);
+        const float2 r1 = *reinterpret_cast<const FSPB_GLOBAL float2*>(&tTW[2 * (b.tab_off + j) + 1]);
         teq = fmaf(f, r0.y, r0.x);
         W1 = fmaf(f, r0.w, r0.z);
         W2 = fmaf(f, r1.y, r1.x);

@@ -1,0 +1,165 @@
+"""Batched persistent launch, HIP-graph replay, density updates and tile
+configurations (run on an MI355X).
+
+Every voxel sums its pairs in the same order whatever the tile shape, the
+schedule or the launch path, so these tests demand bitwise equality with the
+single-plan forward, which test_gpu_parity.py checks against the oracle."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import fspb_synth as S
+from gpu_helpers import assert_dose_parity, geometry, gpu_dose, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _plans():
+    rng = np.random.default_rng(40)
+    out = []
+    for k, (n, gantries) in enumerate([((23, 19, 13), (0.3, 3.9)), ((30, 17, 22), (1.1,)),
+                                      ((9, 41, 7), (0.0, 2.0, 4.0)), ((36, 36, 20), (5.5, 0.8))]):
+        rho = rng.uniform(0.05, 2.2, size=(n[2], n[1], n[0])).astype(np.float32)
+        beams = [S.Beam(gantry=g, nbx=3 + k, nby=4, wx=0.5, wy=0.4 + 0.1 * k) for g in gantries]
+        out.append(S.plan_small(n=n, density=rho, beams=beams, seed=k, name=f"b{k}"))
+    return out
+
+
+@pytest.mark.parametrize("dc", [1, 0])
+def test_tile_configurations_agree(dc):
+    from paper_1103_1164_amd import Geometry
+    plan = _plans()[3]
+    geo = geometry(plan, dc)
+    ref = gpu_dose(geo, plan.fluence)
+    shapes = Geometry.tile_shapes()
+    assert len(shapes) >= 2 and all(int(np.prod(s)) == 64 for s in shapes)
+    for sh in range(len(shapes)):
+        for wpb in (1, 2, 4):
+            geo.set_tile(sh, wpb)
+            assert geo.get_tile() == (sh, wpb)
+            assert np.array_equal(gpu_dose(geo, plan.fluence), ref), (sh, wpb)
+            n = geo.count_pairs(torch.as_tensor(plan.fluence, device="cuda"))
+            if sh == 0 and wpb == 1:
+                n0 = n
+            assert n == n0
+
+
+@pytest.mark.parametrize("dc", [1, 0])
+def test_batch_equals_single_plan(dc):
+    from paper_1103_1164_amd import Batch
+    plans = _plans()
+    geos = [geometry(p, dc) for p in plans]
+    refs = [gpu_dose(g, p.fluence) for g, p in zip(geos, plans)]
+    fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
+    for shape, wpb, wpc, pol in ((0, 4, 32, "throughput"), (1, 2, 8, "latency"),
+                                 (0, 1, 1, "throughput"), (2, 4, 16, "latency")):
+        b = Batch(geos, shape=shape, waves_per_block=wpb, waves_per_cu=wpc, policy=pol)
+        out = [torch.full(p.shape, -1.0, device="cuda") for p in plans]
+        b.forward(fl, out)
+        torch.cuda.synchronize()
+        for o, r in zip(out, refs):
+            assert np.array_equal(o.cpu().numpy().astype(np.float64), r), (shape, wpb, wpc, pol)
+        ms, total = b.latencies()
+        assert total > 0 and all(0 < m <= total + 1e-9 for m in ms)
+        sx, sy, sz = geos[0].tile_shapes()[shape]
+        n_bricks = sum(-(-p.shape[2] // sx) * -(-p.shape[1] // sy) * -(-p.shape[0] // sz)
+                       for p in plans)
+        assert b.info()["n_items"] == n_bricks
+        b.close()
+
+
+def test_update_density_matches_fresh_geometry():
+    plans = _plans()
+    p0 = plans[0]
+    rng = np.random.default_rng(7)
+    rho2 = rng.uniform(0.05, 2.2, size=p0.density.shape).astype(np.float32)
+    p1 = S.plan_small(n=p0.shape[::-1], density=rho2, beams=p0.beams, fluence=p0.fluence)
+    geo = geometry(p0, 1)
+    d2 = torch.as_tensor(rho2, device="cuda")
+    geo.update_density(d2)
+    fresh = geometry(p1, 1)
+    assert np.array_equal(gpu_dose(geo, p0.fluence), gpu_dose(fresh, p0.fluence))
+    assert torch.equal(geo.smoothed_density(), fresh.smoothed_density())
+    for i in range(0, p0.n_beamlets, 3):
+        a, b = geo.beamlet(i), fresh.beamlet(i)
+        assert a["k_entry"] == b["k_entry"] and np.array_equal(a["T"], b["T"])
+
+
+def test_graph_replay_with_density_updates():
+    from paper_1103_1164_amd import Batch
+    plans = _plans()
+    geos = [geometry(p, 1) for p in plans]
+    rng = np.random.default_rng(11)
+    dens = [torch.as_tensor(rng.uniform(0.05, 2.2, size=p.density.shape).astype(np.float32),
+                            device="cuda") for p in plans]
+    fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
+    out = [torch.zeros(p.shape, device="cuda") for p in plans]
+    # reference: fresh geometries on the new densities
+    refs = []
+    for p, d in zip(plans, dens):
+        q = S.plan_small(n=p.shape[::-1], density=d.cpu().numpy(), beams=p.beams,
+                         fluence=p.fluence)
+        refs.append(gpu_dose(geometry(q, 1), p.fluence))
+    b = Batch(geos)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.capture(fl, out, densities=dens, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for o in out:
+            o.fill_(-5.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            b.replay(stream=s)
+        s.synchronize()
+        for o, r in zip(out, refs):
+            assert np.array_equal(o.cpu().numpy().astype(np.float64), r), rep
+        ms, total = b.latencies(stream=s)
+        assert total > 0
+
+
+def test_autotune_and_cache(tmp_path):
+    from paper_1103_1164_amd.autotune import tune
+    plan = _plans()[3]
+    geo = geometry(plan, 1)
+    ref = gpu_dose(geo, plan.fluence)
+    f = torch.as_tensor(plan.fluence, device="cuda")
+    cache = tmp_path / "tune.json"
+    r1 = tune(geo, f, cache=cache, reps=2)
+    assert not r1["cached"] and len(r1["all"]) == 3 * len(geo.tile_shapes())
+    assert geo.get_tile() == (r1["shape"], r1["waves_per_block"])
+    assert np.array_equal(gpu_dose(geo, plan.fluence), ref)
+    geo2 = geometry(plan, 1)
+    r2 = tune(geo2, f, cache=cache)
+    assert r2["cached"] and geo2.get_tile() == geo.get_tile()
+    assert r1["key"] in json.loads(cache.read_text())
+
+
+def test_c4_batch_full_size(oracle_mod):
+    """Four config-4 plans (the smallest and largest grids and two in
+    between) in one persistent launch: equal to the single-plan forwards and
+    to the oracle on sampled voxels."""
+    from paper_1103_1164_amd import Batch
+    idx = [0, 1, 2, 31]
+    plans = S.plans_c4(idx)
+    say("c4: geometries")
+    geos = [geometry(p, 1) for p in plans]
+    fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
+    out = [torch.empty(p.shape, device="cuda") for p in plans]
+    b = Batch(geos)
+    b.forward(fl, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for k, (p, g, o) in enumerate(zip(plans, geos, out)):
+        single = gpu_dose(g, p.fluence)
+        got = o.cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, single), p.name
+        if k in (0, 3):
+            vox = rng.choice(p.n_vox, size=1500, replace=False)
+            hot = np.argsort(got.reshape(-1))[-300:]
+            vox = np.unique(np.concatenate([vox, hot]))
+            say(f"c4: oracle {p.name} at {vox.size} voxels")
+            d_o, amb, _ = oracle_mod.Oracle(p).dose(vox=vox)
+            assert_dose_parity(got.reshape(-1)[vox], d_o, amb, what=p.name)
