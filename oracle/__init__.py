@@ -68,7 +68,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not LIB_PATH.exists():
+        src = HERE / "fspb_oracle.c"
+        if not LIB_PATH.exists() or LIB_PATH.stat().st_mtime < src.stat().st_mtime:
             build()
         L = C.CDLL(str(LIB_PATH))
         L.orc_create.restype = C.c_void_p
@@ -95,6 +96,21 @@ def lib():
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_pair_counts.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long),
                                       C.POINTER(C.c_int)]
+        L.orc_density_at.restype = C.c_double
+        L.orc_density_at.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.orc_params.restype = C.c_int
+        L.orc_params.argtypes = [C.c_void_p, C.c_long, C.c_int, C.POINTER(C.c_double)]
+        L.orc_pair_given.restype = C.c_double
+        L.orc_pair_given.argtypes = [C.c_void_p, C.c_long, C.c_int, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int)]
+        L.orc_nearest_beamlet.restype = C.c_int
+        L.orc_nearest_beamlet.argtypes = [C.c_void_p, C.c_long, C.c_int, C.POINTER(C.c_double)]
+        L.orc_surrogate_row.restype = C.c_int
+        L.orc_surrogate_row.argtypes = [C.c_void_p, C.c_long, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int)]
+        L.orc_dose_given.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_long,
+                                     C.POINTER(C.c_long), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -230,3 +246,67 @@ class Oracle:
         out = np.zeros(n, dtype=np.int32)
         lib().orc_pair_counts(self.ctx, n, vp, _ptr(out, C.c_int))
         return out if vox is not None else out.reshape(self.shape)
+
+    # -- learned-surrogate support (an extension beside the method) -------
+    def density_at(self, points) -> np.ndarray:
+        """Trilinear density (clamp-to-edge) at points [n, 3]."""
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        out = np.empty(len(pts))
+        for k, q in enumerate(pts):
+            out[k] = lib().orc_density_at(self.ctx, _ptr(q, C.c_double))
+        return out
+
+    def params(self, vox: int, i: int):
+        """(six parameters (u1x, u1y, u2x, u2y, w1, w2), pair flags)."""
+        out = np.zeros(6)
+        fl = lib().orc_params(self.ctx, int(vox), int(i), _ptr(out, C.c_double))
+        return out, fl
+
+    def pair_given(self, vox: int, i: int, prm):
+        prm = np.ascontiguousarray(prm, dtype=np.float64)
+        fl = C.c_int(0)
+        v = lib().orc_pair_given(self.ctx, int(vox), int(i), _ptr(prm, C.c_double), C.byref(fl))
+        return v, fl.value
+
+    def nearest_beamlet(self, vox: int, beam: int):
+        """(beamlet index or -1, distance of the rounding from a tie)."""
+        tie = C.c_double(0.0)
+        i = lib().orc_nearest_beamlet(self.ctx, int(vox), int(beam), C.byref(tie))
+        return i, tie.value
+
+    def surrogate_rows(self, vox, beam):
+        """Surrogate inputs of rows (vox[k], beam[k]): (features [n, 202],
+        nearest beamlet or -1 [n], ambiguity flag [n], tie distance [n])."""
+        vox = np.atleast_1d(np.asarray(vox, dtype=np.int64))
+        beam = np.broadcast_to(np.asarray(beam, dtype=np.int64), vox.shape)
+        feat = np.zeros((vox.size, 202))
+        near = np.zeros(vox.size, dtype=np.int64)
+        amb = np.zeros(vox.size, dtype=np.int32)
+        tie = np.zeros(vox.size)
+        f = np.zeros(202)
+        a = C.c_int(0)
+        for k, (v, b) in enumerate(zip(vox, beam)):
+            near[k] = lib().orc_surrogate_row(self.ctx, int(v), int(b), _ptr(f, C.c_double),
+                                              C.byref(a))
+            amb[k] = a.value
+            if near[k] >= 0:
+                feat[k] = f
+            tie[k] = self.nearest_beamlet(int(v), int(b))[1]
+        return feat, near, amb, tie
+
+    def dose_given(self, prm, fluence=None, vox=None):
+        """Dose with per-(voxel, beam) parameters prm [n, n_beams, 7] (six
+        parameters and a fallback flag).  Returns (dose, amb)."""
+        f = np.ascontiguousarray(self.plan.fluence if fluence is None else fluence,
+                                 dtype=np.float32)
+        if vox is None:
+            n, vp = self.n_vox, None
+        else:
+            vox = np.ascontiguousarray(np.atleast_1d(vox), dtype=np.int64)
+            n, vp = vox.size, _ptr(vox, C.c_long)
+        prm = np.ascontiguousarray(prm, dtype=np.float64)
+        assert prm.shape == (n, len(self.plan.beams), 7)
+        d, a = np.zeros(n), np.zeros(n)
+        lib().orc_dose_given(self.ctx, _ptr(f, C.c_float), n, vp, _ptr(prm, C.c_double),
+                             _ptr(d, C.c_double), _ptr(a, C.c_double))
+        return d, a

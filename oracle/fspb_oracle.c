@@ -24,6 +24,12 @@ typedef struct {
 } frame_t;
 
 typedef struct {
+    double src[3], cax[3], ex[3], ey[3];
+    double sad, a0, b0, wx, wy;
+    int nbx, nby, first;
+} beam_t;
+
+typedef struct {
     int hit;
     double s_in, s_out, s_entry, s_exit, amb_rho, step;
     int k_entry, n_samples, K;
@@ -37,6 +43,7 @@ struct orc_ctx {
     int n_beams, n_beamlets;
     frame_t* fr;
     trace_t* tr;
+    beam_t* bm;
     int rad[3];
     double* wts;      /* normalised 3D smoothing weights, [2rz+1][2ry+1][2rx+1] */
 };
@@ -128,6 +135,19 @@ static void build_frames(orc_ctx* c, const orc_beam* beams) {
         rot_couch(bm->couch, ey0, ey);
         double src[3];
         for (int k = 0; k < 3; ++k) src[k] = bm->iso[k] - bm->sad * cax[k];
+        beam_t* B = &c->bm[b];
+        memcpy(B->src, src, sizeof src);
+        memcpy(B->cax, cax, sizeof cax);
+        memcpy(B->ex, ex, sizeof ex);
+        memcpy(B->ey, ey, sizeof ey);
+        B->sad = bm->sad;
+        B->wx = bm->wx;
+        B->wy = bm->wy;
+        B->a0 = -0.5 * (bm->nbx - 1) * bm->wx + bm->cx;
+        B->b0 = -0.5 * (bm->nby - 1) * bm->wy + bm->cy;
+        B->nbx = bm->nbx;
+        B->nby = bm->nby;
+        B->first = i;
         for (int n = 0; n < bm->nby; ++n) {
             for (int m = 0; m < bm->nbx; ++m, ++i) {
                 frame_t* f = &c->fr[i];
@@ -328,6 +348,7 @@ orc_ctx* orc_create(const orc_grid* g, int n_beams, const orc_beam* beams,
     for (int b = 0; b < n_beams; ++b) c->n_beamlets += beams[b].nbx * beams[b].nby;
     c->fr = (frame_t*)calloc(c->n_beamlets, sizeof(frame_t));
     c->tr = (trace_t*)calloc(c->n_beamlets, sizeof(trace_t));
+    c->bm = (beam_t*)calloc(n_beams, sizeof(beam_t));
     build_frames(c, beams);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < c->n_beamlets; ++i) trace_beamlet(c, i);
@@ -344,6 +365,7 @@ void orc_destroy(orc_ctx* c) {
     }
     free(c->tr);
     free(c->fr);
+    free(c->bm);
     free(c->wts);
     free(c);
 }
@@ -393,7 +415,7 @@ int orc_trace(const orc_ctx* c, int i, double info[10], double* T, double* W1, d
  * rho_c and rhohat_c are the voxel's density and smoothed density clamped to
  * the commissioned range (reading). */
 static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c, double rhohat_c,
-                         int* flags) {
+                         int* flags, const double* given, double* params) {
     const frame_t* f = &c->fr[i];
     const trace_t* t = &c->tr[i];
     const orc_tables* tb = &c->tab;
@@ -436,6 +458,24 @@ static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c,
         if (w1 < 0.0) w1 = 0.0;   /* reading: weights cannot go negative */
         if (w2 < 0.0) w2 = 0.0;
     }
+    if (given) {
+        /* surrogate: the six parameters come from outside (per voxel and
+         * beam); depth, t_eq, A and the inverse square stay per beamlet */
+        u1x = given[0];
+        u1y = given[1];
+        u2x = given[2];
+        u2y = given[3];
+        w1 = given[4];
+        w2 = given[5];
+    }
+    if (params) {
+        params[0] = u1x;
+        params[1] = u1y;
+        params[2] = u2x;
+        params[3] = u2y;
+        params[4] = w1;
+        params[5] = w2;
+    }
     double F = w1 * orc_p(x, u1x, f->x0) * orc_p(y, u1y, f->y0)
              + w2 * orc_p(x, u2x, f->x0) * orc_p(y, u2y, f->y0);
     return F * A * isq;
@@ -463,7 +503,7 @@ double orc_pair(const orc_ctx* c, long vox, int i, int* flags) {
     int fl;
     voxel_center(&c->g, vox, r);
     voxel_densities(c, vox, NULL, &rc, &rhc);
-    double v = pair_value(c, r, i, rc, rhc, &fl);
+    double v = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
     if (flags) *flags = fl;
     return v;
 }
@@ -482,7 +522,7 @@ void orc_dose(const orc_ctx* c, const float* fluence, long n, const long* vox,
         for (int i = 0; i < c->n_beamlets; ++i) {
             if (fluence[i] == 0.0f) continue;
             int fl;
-            double d = pair_value(c, r, i, rc, rhc, &fl);
+            double d = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
             if (fl & 1) {
                 acc += fluence[i] * d;
                 ++np;
@@ -510,7 +550,7 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list, doubl
             for (int q = 0; q < n && !need; ++q) {
                 int fl;
                 int i = list ? list[q] : q;
-                pair_value(c, r, i, 1.0, 1.0, &fl);
+                pair_value(c, r, i, 1.0, 1.0, &fl, NULL, NULL);
                 need = fl != 0;
             }
             rh[v] = need ? orc_smoothed_at(c, v) : 1.0;
@@ -526,7 +566,7 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list, doubl
             int fl;
             voxel_center(&c->g, v, r);
             voxel_densities(c, v, rh, &rc, &rhc);
-            double d = pair_value(c, r, i, rc, rhc, &fl);
+            double d = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
             if (fl & 1) acc += w[v] * d;
             if (fl & 2) a += fabs(w[v] * d);
         }
@@ -545,9 +585,138 @@ void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts) {
         int cnt = 0;
         for (int i = 0; i < c->n_beamlets; ++i) {
             int fl;
-            pair_value(c, r, i, 1.0, 1.0, &fl);
+            pair_value(c, r, i, 1.0, 1.0, &fl, NULL, NULL);
             if (fl & 1) ++cnt;
         }
         counts[q] = cnt;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Learned-surrogate support.  The surrogate is an extension beside the
+ * method (not in the paper): for a (voxel, beam) row it predicts the six
+ * Section 2.1 parameters (u1x, u1y, u2x, u2y, w1, w2) from a density patch.
+ * The functions below define its inputs and training targets, and the dose
+ * it produces, so that the tests can check the GPU's. */
+
+double orc_density_at(const orc_ctx* c, const double p[3]) { return trilinear(&c->g, p); }
+
+int orc_params(const orc_ctx* c, long vox, int i, double out[6]) {
+    double r[3], rc, rhc;
+    int fl;
+    voxel_center(&c->g, vox, r);
+    voxel_densities(c, vox, NULL, &rc, &rhc);
+    for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    pair_value(c, r, i, rc, rhc, &fl, NULL, out);
+    return fl;
+}
+
+double orc_pair_given(const orc_ctx* c, long vox, int i, const double prm[6], int* flags) {
+    double r[3];
+    int fl;
+    voxel_center(&c->g, vox, r);
+    double v = pair_value(c, r, i, 1.0, 1.0, &fl, prm, NULL);
+    if (flags) *flags = fl;
+    return v;
+}
+
+/* The beamlet of `beam` whose isocentre-plane centre lies nearest to the
+ * voxel's central projection from the source (ties round up); -1 if the
+ * voxel is not in front of the source.  *tie gets the distance of either
+ * rounding decision from its tie, in beamlet widths. */
+int orc_nearest_beamlet(const orc_ctx* c, long vox, int beam, double* tie) {
+    const beam_t* B = &c->bm[beam];
+    double r[3];
+    voxel_center(&c->g, vox, r);
+    double v[3] = {r[0] - B->src[0], r[1] - B->src[1], r[2] - B->src[2]};
+    double z = dot3(v, B->cax);
+    if (tie) *tie = 1.0;
+    if (!(z > 0.0)) return -1;
+    double a = B->sad * dot3(v, B->ex) / z, b = B->sad * dot3(v, B->ey) / z;
+    double ga = (a - B->a0) / B->wx, gb = (b - B->b0) / B->wy;
+    int m = clampi((int)floor(ga + 0.5), 0, B->nbx - 1);
+    int n = clampi((int)floor(gb + 0.5), 0, B->nby - 1);
+    if (tie) {
+        double ta = fabs(ga - floor(ga) - 0.5), tb = fabs(gb - floor(gb) - 0.5);
+        *tie = ta < tb ? ta : tb;
+    }
+    return B->first + n * B->nbx + m;
+}
+
+/* One surrogate input row for (voxel, beam).  The nearest beamlet i must
+ * hit the body and its pair with the voxel must be counted (inside the ROI,
+ * below the entrance); otherwise the row is invalid and -1 is returned.
+ * Patch: along the ray from the source S to the voxel centre r (length L,
+ * unit direction u), 8 planes at distances L - t (7 - k) / 7, k = 0..7,
+ * from the depth of the entrance (t = the voxel's depth for beamlet i) to
+ * the voxel; in each plane a 5 x 5 lattice at 0.5 cm along e1 and e2,
+ * where e1 is the beam's lateral x axis made orthogonal to u and
+ * e2 = e1 x u.  feat[25 k + 5 b + a] = trilinear density at
+ * S + s_k u + 0.5 (a - 2) e1 + 0.5 (b - 2) e2;  feat[200] = t,
+ * feat[201] = theta_i.  *amb gets 1 when the pair test of beamlet i lies
+ * within the ambiguity tolerance of its boundary. */
+int orc_surrogate_row(const orc_ctx* c, long vox, int beam, double feat[202], int* amb) {
+    double tie;
+    if (amb) *amb = 0;
+    int i = orc_nearest_beamlet(c, vox, beam, &tie);
+    if (i < 0) return -1;
+    double prm[6];
+    int fl = orc_params(c, vox, i, prm);
+    if (amb) *amb = (fl & 2) ? 1 : 0;
+    if (!(fl & 1)) return -1;
+    const frame_t* f = &c->fr[i];
+    const trace_t* tr = &c->tr[i];
+    const beam_t* B = &c->bm[beam];
+    double r[3];
+    voxel_center(&c->g, vox, r);
+    double v[3] = {r[0] - f->src[0], r[1] - f->src[1], r[2] - f->src[2]};
+    double t = dot3(v, f->d) - tr->s_entry;
+    double L = sqrt(dot3(v, v));
+    double u[3] = {v[0] / L, v[1] / L, v[2] / L};
+    double e1[3], e2[3];
+    double pr = dot3(B->ex, u);
+    for (int k = 0; k < 3; ++k) e1[k] = B->ex[k] - pr * u[k];
+    normalize3(e1);
+    cross3(e1, u, e2);
+    for (int k = 0; k < 8; ++k) {
+        double s = L - t * (7 - k) / 7.0;
+        for (int b = 0; b < 5; ++b)
+            for (int a = 0; a < 5; ++a) {
+                double p[3];
+                for (int q = 0; q < 3; ++q)
+                    p[q] = f->src[q] + s * u[q] + 0.5 * (a - 2) * e1[q] + 0.5 * (b - 2) * e2[q];
+                feat[25 * k + 5 * b + a] = trilinear(&c->g, p);
+            }
+    }
+    feat[200] = t;
+    feat[201] = f->theta;
+    return i;
+}
+
+/* Dose with the surrogate's parameters: D(r) = sum_i f_i D_i(r) where each
+ * pair takes the six parameters of its (voxel, beam) row,
+ * prm[(q * n_beams + b) * 7 + 0..5], unless the row's fallback flag
+ * prm[... + 6] is non-zero, in which case the pair is evaluated by the
+ * method itself.  amb as for orc_dose. */
+void orc_dose_given(const orc_ctx* c, const float* fluence, long n, const long* vox,
+                    const double* prm, double* dose, double* amb) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < n; ++q) {
+        long v = vox ? vox[q] : q;
+        double r[3], rc, rhc;
+        voxel_center(&c->g, v, r);
+        voxel_densities(c, v, NULL, &rc, &rhc);
+        double acc = 0.0, a = 0.0;
+        for (int i = 0; i < c->n_beamlets; ++i) {
+            if (fluence[i] == 0.0f) continue;
+            const double* row = prm + (q * c->n_beams + c->fr[i].beam) * 7;
+            int fl;
+            double d = row[6] != 0.0 ? pair_value(c, r, i, rc, rhc, &fl, NULL, NULL)
+                                     : pair_value(c, r, i, rc, rhc, &fl, row, NULL);
+            if (fl & 1) acc += fluence[i] * d;
+            if (fl & 2) a += fabs(fluence[i] * d);
+        }
+        dose[q] = acc;
+        if (amb) amb[q] = a;
     }
 }

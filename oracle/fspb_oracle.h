@@ -125,6 +125,40 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list,
  * voxel; vox may be NULL for the whole grid. */
 void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts);
 
+
+/* ---- Learned-surrogate support (an extension beside the method, not in
+ * the paper).  A row is a (voxel, beam); its six parameters are
+ * (u1x, u1y, u2x, u2y, w1, w2) in the units of the tables. ---- */
+
+/* Trilinear density at a point (clamp-to-edge), as the ray trace samples it.
+ * Pinned: reproduces voxel values at centres and linear fields exactly. */
+double orc_density_at(const orc_ctx* c, const double p[3]);
+/* The six parameters the pair (vox, i) uses: with density correction on,
+ * after Section 2.1; otherwise the water values.  Returns the orc_pair flags
+ * (the parameters are meaningful when bit 0 is set).  Pinned: water values
+ * in water, closed forms in a uniform medium. */
+int orc_params(const orc_ctx* c, long vox, int i, double out[6]);
+/* Pair dose with the six parameters given (Eqs. 2-4; depth, t_eq, A and the
+ * inverse square of beamlet i).  Pinned: equals orc_pair when given
+ * orc_params of the same pair. */
+double orc_pair_given(const orc_ctx* c, long vox, int i, const double prm[6], int* flags);
+/* Nearest beamlet of a beam to a voxel by central projection onto the
+ * isocentre plane (ties round up), or -1.  *tie (may be NULL) gets the
+ * smaller distance of the two rounding decisions from a tie, in beamlet
+ * widths.  Pinned: a voxel on a beamlet's axis selects that beamlet. */
+int orc_nearest_beamlet(const orc_ctx* c, long vox, int beam, double* tie);
+/* Surrogate input row (200 patch densities, depth, theta) of (voxel, beam),
+ * definition at the function.  Returns the nearest beamlet, or -1 when the
+ * row is invalid.  *amb (may be NULL) flags a pair test within tolerance of
+ * its boundary.  Pinned: linear density fields give the analytic patch. */
+int orc_surrogate_row(const orc_ctx* c, long vox, int beam, double feat[202], int* amb);
+/* Dose with per-(voxel, beam) parameters prm[n][n_beams][7] (six parameters
+ * and a fallback flag: non-zero means the method's own parameters).
+ * Pinned: all-fallback equals orc_dose; rows set to orc_params of the
+ * nearest beamlet give orc_dose in a uniform medium. */
+void orc_dose_given(const orc_ctx* c, const float* fluence, long n, const long* vox,
+                    const double* prm, double* dose, double* amb);
+
 #ifdef __cplusplus
 }
 #endif

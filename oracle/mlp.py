@@ -35,28 +35,47 @@ def gelu_grad(x):
     return 0.5 * (1.0 + th) + 0.5 * x * (1.0 - th ** 2) * _C * (1.0 + 3 * 0.044715 * x ** 2)
 
 
-def forward(p, X):
+def _same(a):
+    return a
+
+
+def round_bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    Goes through float32 first, as a float32 value is what a kernel rounds."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
+
+
+def forward(p, X, q=_same):
+    """q rounds the activations that feed the next product (identity by
+    default; round_bf16 mimics a kernel that stores them in BF16)."""
     X = np.asarray(X, np.float64)
     Z1 = X @ p["W1"] + p["b1"]
-    H1 = gelu(Z1)
+    H1 = q(gelu(Z1))
     Z2 = H1 @ p["W2"] + p["b2"]
-    H2 = gelu(Z2)
+    H2 = q(gelu(Z2))
     Y = H2 @ p["W3"] + p["b3"]
     return Y, (X, Z1, H1, Z2, H2)
 
 
-def loss_and_grads(p, X, T):
-    Y, (X, Z1, H1, Z2, H2) = forward(p, X)
+def loss_and_grads(p, X, T, q=_same):
+    """Mean-square loss and its gradients.  With q = round_bf16 the operands
+    of every product are rounded where a BF16 kernel rounds them (the
+    activations, the output gradient and the pre-activation gradients);
+    bias gradients sum the unrounded values."""
+    Y, (X, Z1, H1, Z2, H2) = forward(p, X, q)
     T = np.asarray(T, np.float64)
     n = Y.size
     loss = float(np.sum((Y - T) ** 2) / n)
     dY = 2.0 * (Y - T) / n
-    g = {"W3": H2.T @ dY, "b3": dY.sum(0)}
-    dZ2 = (dY @ p["W3"].T) * gelu_grad(Z2)
-    g["W2"] = H1.T @ dZ2
+    g = {"W3": H2.T @ q(dY), "b3": dY.sum(0)}
+    dZ2 = (q(dY) @ p["W3"].T) * gelu_grad(Z2)
+    g["W2"] = H1.T @ q(dZ2)
     g["b2"] = dZ2.sum(0)
-    dZ1 = (dZ2 @ p["W2"].T) * gelu_grad(Z1)
-    g["W1"] = X.T @ dZ1
+    dZ1 = (q(dZ2) @ p["W2"].T) * gelu_grad(Z1)
+    g["W1"] = X.T @ q(dZ1)
     g["b1"] = dZ1.sum(0)
     return loss, g
 

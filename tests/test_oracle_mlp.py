@@ -71,3 +71,27 @@ def test_adam_matches_torch():
         opt.step()
         for t, n in zip(tp, M.NAMES):
             assert np.max(np.abs(t.detach().numpy() - p[n])) < 1e-14
+
+
+def test_round_bf16_matches_torch():
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.normal(0, 1, 5000), rng.normal(0, 1e-3, 1000), [0.0, -0.0, 1.0, -3.5]])
+    # values exactly halfway between two bfloat16 numbers (ties to even)
+    base = rng.normal(0, 1, 200).astype(np.float32).view(np.uint32) & 0xFFFF0000
+    x = np.concatenate([x, (base | 0x8000).view(np.float32).astype(np.float64)])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.round_bf16(x), want)
+
+
+def test_rounded_grads_stay_near_exact():
+    """With the BF16 rounding points the gradients move by about the BF16
+    resolution (2^-8 relative), not more."""
+    rng = np.random.default_rng(5)
+    p = _params(5)
+    X = M.round_bf16(rng.normal(0, 1, (64, M.N_IN)))
+    T = rng.normal(0, 1, (64, M.N_OUT))
+    _, g = M.loss_and_grads(p, X, T)
+    _, gq = M.loss_and_grads(p, X, T, q=M.round_bf16)
+    for n in M.NAMES:
+        rel = np.linalg.norm(gq[n] - g[n]) / np.linalg.norm(g[n])
+        assert 0 < rel < 1e-2, (n, rel)
