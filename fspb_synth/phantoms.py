@@ -196,6 +196,18 @@ def c5_phantom(seed: int) -> np.ndarray:
     return c2_density(seed)
 
 
+C5_TRAIN_SEEDS = range(1000, 1200)
+C5_HELDOUT_SEEDS = range(2000, 2010)
+
+
+def plan_c5(seed: int, tables: Tables | None = None) -> Plan:
+    """C2 geometry (7 beams of 20 x 20 beamlets, 128 x 128 x 96 grid) on the
+    random head of `seed`, fluences as for C2."""
+    p = plan_c2(seed, tables)
+    p.name = f"c5_head_{seed}"
+    return p
+
+
 def plan_small(n=(24, 20, 16), spacing=(0.25, 0.25, 0.25), density=1.0,
                beams: Sequence[Beam] | None = None, fluence=None,
                tables: Tables | None = None, options: Options | None = None,

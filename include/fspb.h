@@ -45,6 +45,8 @@
 #ifndef FSPB_H
 #define FSPB_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -287,6 +289,116 @@ int fspb_batch_info(const fspb_batch* b, int* n_waves, long long* n_items);
 
 /* Frees the batch (not its geometries).  NULL-safe. */
 void fspb_batch_destroy(fspb_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the density correction (an extension beside the
+ * method; it changes nothing above).  A small MLP predicts the six Section
+ * 2.1 parameters (u1x, u1y, u2x, u2y, w1, w2) of a (voxel, beam) row from a
+ * density patch; the dose then uses that prediction for every beamlet of the
+ * beam at the voxel, while depth, t_eq, A and the inverse square stay per
+ * beamlet.  Rows whose guard fires fall back to the corrected parameters.
+ *
+ * Network: 202 inputs -> 64 -> 64 -> 6, tanh-approximated GELU, BF16 weights
+ * and activations with FP32 accumulation on the matrix cores, FP32 master
+ * weights, Adam.  Parameters, flat FP32 (FSPB_MLP_PARAMS values), row-major:
+ *   W1 [202][64], b1 [64], W2 [64][64], b2 [64], W3 [64][6], b3 [6]
+ * with y = W3^T gelu(W2^T gelu(W1^T x + b1) + b2) + b3.
+ *
+ * Input row (FSPB_MLP_IN values, stored BF16 in rows of FSPB_MLP_IN_PAD with
+ * zero padding): the nearest beamlet of the beam is the one whose
+ * isocentre-plane centre lies nearest to the voxel's central projection from
+ * the source (ties round up); the row is valid when that beamlet reaches the
+ * body and its pair with the voxel passes the pair test.  On the ray from
+ * the source to the voxel centre (direction u), plane k = 0..7 lies
+ * t (7 - k) / 7 before the voxel, t being the voxel's depth for the nearest
+ * beamlet; each plane holds a 5 x 5 lattice at 0.5 cm along e1 (the beam's
+ * x axis made orthogonal to u) and e2 = e1 x u.  Input 25 k + 5 b + a is the
+ * trilinear density at lattice point (a, b) minus 1; input 200 is
+ * t / 10 cm - 1 and input 201 is 10 theta of the nearest beamlet.
+ * Targets are the corrected parameters of the nearest beamlet at the voxel
+ * (u in 1/cm); the network learns them standardised, value = y std + mean.
+ * ------------------------------------------------------------------------ */
+#define FSPB_MLP_IN 202
+#define FSPB_MLP_IN_PAD 224
+#define FSPB_MLP_HIDDEN 64
+#define FSPB_MLP_OUT 6
+#define FSPB_MLP_PARAMS 17542
+#define FSPB_MLP_MAX_ROWS (1 << 22)   /* rows per training or gradient call */
+
+typedef struct fspb_mlp fspb_mlp;
+
+typedef struct {
+    float lr, beta1, beta2, eps;
+} fspb_adam;
+
+/* Guard: a row falls back when a patch density leaves [rho_lo, rho_hi],
+ * when max |rho - rho(voxel)| over the two planes next to the voxel exceeds
+ * het_max, or when a predicted parameter leaves [band_lo[c], band_hi[c]]. */
+typedef struct {
+    float rho_lo, rho_hi, het_max;
+    float band_lo[6], band_hi[6];
+} fspb_surrogate_guard;
+
+/* Creates a network on the current device from params (host, FSPB_MLP_PARAMS
+ * values); Adam moments start at zero, step at 0, scaling at mean 0 / std 1,
+ * and the guard open (nothing falls back but invalid rows). */
+int fspb_mlp_create(const float* params, fspb_mlp** out);
+
+/* Target standardisation (host, 6 values each; std > 0). */
+int fspb_mlp_set_scaling(fspb_mlp* m, const float* mean, const float* stdev);
+
+/* Fallback guard (host struct, copied). */
+int fspb_mlp_set_guard(fspb_mlp* m, const fspb_surrogate_guard* guard);
+
+/* Mean-square loss over n rows (1 <= n <= FSPB_MLP_MAX_ROWS) of x (device,
+ * BF16 bit patterns [n][224]) against standardised targets t (device, FP32
+ * [n][6]), and its gradient with respect to the parameters (device, FP32
+ * [FSPB_MLP_PARAMS], flat layout above).  loss (device, 1 float) and grad
+ * may each be NULL.  The network is unchanged. */
+int fspb_mlp_loss_grad(fspb_mlp* m, const uint16_t* x, const float* t, long long n, float* grad,
+                       float* loss, void* stream);
+
+/* One Adam step on the loss of the n rows (as fspb_mlp_loss_grad); loss
+ * (device, may be NULL) receives the loss before the step.  Deterministic:
+ * equal states and inputs give bitwise equal results. */
+int fspb_mlp_train_step(fspb_mlp* m, const uint16_t* x, const float* t, long long n,
+                        const fspb_adam* opt, float* loss, void* stream);
+
+/* Network outputs (standardised units) y (device, FP32 [n][6]) of n >= 0
+ * rows x (device, BF16 [n][224]). */
+int fspb_mlp_predict(fspb_mlp* m, const uint16_t* x, long long n, float* y, void* stream);
+
+/* Checkpoint: parameters, Adam moments (host, FSPB_MLP_PARAMS each; any may
+ * be NULL) and the step count.  get synchronises the device; set replaces
+ * the state (a NULL moment array is set to zero). */
+int fspb_mlp_get_state(const fspb_mlp* m, float* params, float* adam_m, float* adam_v,
+                       long long* step);
+int fspb_mlp_set_state(fspb_mlp* m, const float* params, const float* adam_m,
+                       const float* adam_v, long long step);
+
+/* Frees the network.  NULL-safe; waits for queued device work. */
+void fspb_mlp_destroy(fspb_mlp* m);
+
+/* Training rows for the n (voxel, beam) pairs in rows (device, int32
+ * [n][2]) of a geometry created with density correction on; density is the
+ * CT the geometry was built from (device, [nz][ny][nx]).  Writes x (device,
+ * BF16 [n][224]), t (device, FP32 [n][6], the corrected parameters of the
+ * nearest beamlet, unstandardised) and valid (device, int32 [n], 1 if the
+ * row is valid; invalid rows get zeros). */
+int fspb_surrogate_samples(fspb_geometry* g, const float* density, const int* rows, long long n,
+                           uint16_t* x, float* t, int* valid, void* stream);
+
+/* Fused gather + inference for every (voxel, beam) row: prm (device, FP32
+ * [n_beams][n_vox][8]) gets (u1x, u1y, u2x, u2y) * log2(e), w1, w2, the
+ * fallback flag (1 or 0) and 0.  Needs a density-corrected geometry. */
+int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* density, float* prm,
+                         void* stream);
+
+/* Eq. 1 with the surrogate's rows prm (as written by fspb_surrogate_infer):
+ * a pair whose row's fallback flag is 0 uses the row's parameters, any other
+ * pair the corrected ones.  dose as for fspb_forward. */
+int fspb_forward_surrogate(fspb_geometry* g, const float* fluence, const float* prm, float* dose,
+                           void* stream);
 
 /* Frees the handle.  NULL-safe.  Waits for queued device work to finish,
  * then returns the handle's device buffers to the library's per-device cache

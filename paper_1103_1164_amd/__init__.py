@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FspbError, check, load
 
-__all__ = ["Geometry", "Batch", "FspbDose", "FspbError", "load"]
+__all__ = ["Geometry", "Batch", "Mlp", "FspbDose", "FspbError", "load"]
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -44,6 +44,7 @@ class Geometry:
         if not (isinstance(density, torch.Tensor) and density.is_cuda):
             raise TypeError("density must be a CUDA (HIP) tensor")
         density = density.to(torch.float32).contiguous()
+        self._density = density          # the CT the tables were traced through
         self.device = density.device
         nz, ny, nx = density.shape
         self.shape = (nz, ny, nx)
@@ -81,6 +82,7 @@ class Geometry:
         self._h = h
         self.n_beamlets = int(sum(int(b.nbx) * int(b.nby) for b in beams))
         self.n_vox = nx * ny * nz
+        self.n_beams = len(beams)
 
     @classmethod
     def from_plan(cls, plan, device="cuda", dc_enabled: Optional[int] = None, stream=None):
@@ -159,6 +161,62 @@ class Geometry:
             raise ValueError("density must be a contiguous float32 CUDA tensor of the grid's size")
         check(load().fspb_update_density(self._handle(), C.c_void_p(d.data_ptr()), _stream(stream)),
               "fspb_update_density")
+        self._density = d
+
+    # -- learned surrogate ------------------------------------------------------
+    def _ct(self, density):
+        d = self._density if density is None else density
+        if not (isinstance(d, torch.Tensor) and d.is_cuda and d.dtype == torch.float32
+                and d.is_contiguous() and d.numel() == self.n_vox):
+            raise ValueError("density must be a contiguous float32 CUDA tensor of the grid's size")
+        return d
+
+    def surrogate_samples(self, rows: torch.Tensor, density=None, stream=None):
+        """Training rows for (voxel, beam) pairs rows [n, 2] (int32, device):
+        returns (x BF16 [n, 224], targets FP32 [n, 6], valid int32 [n])."""
+        r = rows
+        if not (isinstance(r, torch.Tensor) and r.is_cuda and r.dtype == torch.int32
+                and r.is_contiguous() and r.dim() == 2 and r.shape[1] == 2):
+            raise ValueError("rows must be a contiguous int32 CUDA tensor [n, 2]")
+        n = r.shape[0]
+        x = torch.empty((n, _lib.FSPB_MLP_IN_PAD), dtype=torch.bfloat16, device=self.device)
+        t = torch.empty((n, _lib.FSPB_MLP_OUT), dtype=torch.float32, device=self.device)
+        v = torch.empty(n, dtype=torch.int32, device=self.device)
+        check(load().fspb_surrogate_samples(self._handle(), C.c_void_p(self._ct(density).data_ptr()),
+                                            C.c_void_p(r.data_ptr()), n, C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(t.data_ptr()), C.c_void_p(v.data_ptr()),
+                                            _stream(stream)), "fspb_surrogate_samples")
+        return x, t, v
+
+    def surrogate_infer(self, mlp: "Mlp", density=None, out: Optional[torch.Tensor] = None,
+                        stream=None) -> torch.Tensor:
+        """Every (voxel, beam) row: [n_beams, n_vox, 8] = (u1x, u1y, u2x, u2y)
+        log2 e, w1, w2, fallback flag, 0."""
+        shape = (self.n_beams, self.n_vox, 8)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 tensor {shape}")
+        check(load().fspb_surrogate_infer(self._handle(), mlp._handle(),
+                                          C.c_void_p(self._ct(density).data_ptr()),
+                                          C.c_void_p(out.data_ptr()), _stream(stream)),
+              "fspb_surrogate_infer")
+        return out
+
+    def forward_surrogate(self, fluence: torch.Tensor, prm: torch.Tensor,
+                          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        f = _dev_f32(fluence, self.device)
+        if f.numel() != self.n_beamlets:
+            raise ValueError(f"fluence has {f.numel()} values, plan has {self.n_beamlets} beamlets")
+        if (tuple(prm.shape) != (self.n_beams, self.n_vox, 8) or prm.dtype != torch.float32
+                or not prm.is_contiguous()):
+            raise ValueError("prm must come from surrogate_infer")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        check(load().fspb_forward_surrogate(self._handle(), C.c_void_p(f.data_ptr()),
+                                            C.c_void_p(prm.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            _stream(stream)), "fspb_forward_surrogate")
+        return out
 
     @staticmethod
     def tile_shapes():
@@ -296,6 +354,148 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """The learned surrogate's network (202 -> 64 -> 64 -> 6, GELU): BF16
+    MFMA training and inference in libfspb, FP32 master weights, Adam.
+    Parameters are flat FP32 in the layout W1 [202][64], b1, W2 [64][64], b2,
+    W3 [64][6], b3."""
+
+    N_IN, N_PAD, N_HID, N_OUT = (_lib.FSPB_MLP_IN, _lib.FSPB_MLP_IN_PAD, _lib.FSPB_MLP_HIDDEN,
+                                 _lib.FSPB_MLP_OUT)
+    N_PARAMS = _lib.FSPB_MLP_PARAMS
+
+    def __init__(self, params, device="cuda"):
+        L = load()
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size != self.N_PARAMS:
+            raise ValueError(f"need {self.N_PARAMS} parameters, got {p.size}")
+        self.device = torch.device(device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.fspb_mlp_create(p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)),
+                  "fspb_mlp_create")
+        self._h = h
+        self.scaling = (np.zeros(6, np.float32), np.ones(6, np.float32))
+        self.guard = None
+
+    @classmethod
+    def initial(cls, seed: int = 0, device="cuda") -> "Mlp":
+        return cls(cls.init_params(seed), device)
+
+    @staticmethod
+    def init_params(seed: int = 0) -> np.ndarray:
+        """Glorot-uniform weights, zero biases (seeded)."""
+        rng = np.random.default_rng(seed)
+        out = []
+        for fi, fo in ((202, 64), (64, 64), (64, 6)):
+            a = np.sqrt(6.0 / (fi + fo))
+            out += [rng.uniform(-a, a, size=fi * fo), np.zeros(fo)]
+        return np.concatenate(out).astype(np.float32)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fspb_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if not self._h:
+            raise FspbError(_lib.FSPB_E_STATE, "network is closed")
+        return self._h
+
+    @staticmethod
+    def _rows(x, t=None):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.bfloat16
+                and x.is_contiguous() and x.dim() == 2 and x.shape[1] == _lib.FSPB_MLP_IN_PAD):
+            raise ValueError("x must be a contiguous bfloat16 CUDA tensor [n, 224]")
+        if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda
+                                  and t.dtype == torch.float32 and t.is_contiguous()
+                                  and tuple(t.shape) == (x.shape[0], _lib.FSPB_MLP_OUT)):
+            raise ValueError("targets must be a contiguous float32 CUDA tensor [n, 6]")
+        return x.shape[0]
+
+    def set_scaling(self, mean, stdev) -> None:
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(stdev, dtype=np.float32)
+        check(load().fspb_mlp_set_scaling(self._handle(), m.ctypes.data_as(C.POINTER(C.c_float)),
+                                          s.ctypes.data_as(C.POINTER(C.c_float))),
+              "fspb_mlp_set_scaling")
+        self.scaling = (m.copy(), s.copy())
+
+    def set_guard(self, rho_lo=-np.inf, rho_hi=np.inf, het_max=np.inf, band_lo=None,
+                  band_hi=None) -> None:
+        big = float(np.finfo(np.float32).max)
+        clip = lambda v: float(np.clip(v, -big, big))
+        bl = [-big] * 6 if band_lo is None else [clip(v) for v in band_lo]
+        bh = [big] * 6 if band_hi is None else [clip(v) for v in band_hi]
+        g = _lib.fspb_surrogate_guard(clip(rho_lo), clip(rho_hi), clip(het_max),
+                                      (C.c_float * 6)(*bl), (C.c_float * 6)(*bh))
+        check(load().fspb_mlp_set_guard(self._handle(), C.byref(g)), "fspb_mlp_set_guard")
+        self.guard = dict(rho_lo=rho_lo, rho_hi=rho_hi, het_max=het_max,
+                          band_lo=list(bl), band_hi=list(bh))
+
+    def loss_grad(self, x, t, stream=None):
+        """(loss [1], gradient [N_PARAMS]) of the mean-square loss; FP32 device."""
+        n = self._rows(x, t)
+        g = torch.empty(self.N_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        check(load().fspb_mlp_loss_grad(self._handle(), C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(t.data_ptr()), n, C.c_void_p(g.data_ptr()),
+                                        C.c_void_p(loss.data_ptr()), _stream(stream)),
+              "fspb_mlp_loss_grad")
+        return loss, g
+
+    def train_step(self, x, t, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, loss=None, stream=None):
+        """One Adam step; returns the (device) loss before the step."""
+        n = self._rows(x, t)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        opt = _lib.fspb_adam(float(lr), float(betas[0]), float(betas[1]), float(eps))
+        check(load().fspb_mlp_train_step(self._handle(), C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(t.data_ptr()), n, C.byref(opt),
+                                         C.c_void_p(loss.data_ptr()), _stream(stream)),
+              "fspb_mlp_train_step")
+        return loss
+
+    def predict(self, x, stream=None) -> torch.Tensor:
+        n = self._rows(x)
+        y = torch.empty((n, _lib.FSPB_MLP_OUT), dtype=torch.float32, device=x.device)
+        check(load().fspb_mlp_predict(self._handle(), C.c_void_p(x.data_ptr()), n,
+                                      C.c_void_p(y.data_ptr()), _stream(stream)),
+              "fspb_mlp_predict")
+        return y
+
+    def state(self) -> dict:
+        """Checkpoint (host copies): params, Adam moments, step, scaling."""
+        a = [np.empty(self.N_PARAMS, np.float32) for _ in range(3)]
+        step = C.c_longlong(0)
+        fp = lambda v: v.ctypes.data_as(C.POINTER(C.c_float))
+        check(load().fspb_mlp_get_state(self._handle(), fp(a[0]), fp(a[1]), fp(a[2]),
+                                        C.byref(step)), "fspb_mlp_get_state")
+        return dict(params=a[0], adam_m=a[1], adam_v=a[2], step=np.int64(step.value),
+                    mean=self.scaling[0].copy(), std=self.scaling[1].copy())
+
+    def load_state(self, st: dict) -> None:
+        a = [np.ascontiguousarray(st[k], dtype=np.float32) for k in ("params", "adam_m", "adam_v")]
+        fp = lambda v: v.ctypes.data_as(C.POINTER(C.c_float))
+        check(load().fspb_mlp_set_state(self._handle(), fp(a[0]), fp(a[1]), fp(a[2]),
+                                        int(st["step"])), "fspb_mlp_set_state")
+        if "mean" in st:
+            self.set_scaling(st["mean"], st["std"])
+
+    def save(self, path) -> None:
+        np.savez(path, **self.state())
+
+    def restore(self, path) -> None:
+        with np.load(path, allow_pickle=False) as z:
+            self.load_state({k: z[k] for k in z.files})
 
 
 class FspbDose(torch.autograd.Function):

@@ -74,6 +74,19 @@ class fspb_tune_result(C.Structure):
                 ("ms", C.c_float)]
 
 
+class fspb_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class fspb_surrogate_guard(C.Structure):
+    _fields_ = [("rho_lo", C.c_float), ("rho_hi", C.c_float), ("het_max", C.c_float),
+                ("band_lo", C.c_float * 6), ("band_hi", C.c_float * 6)]
+
+
+FSPB_MLP_IN, FSPB_MLP_IN_PAD, FSPB_MLP_HIDDEN, FSPB_MLP_OUT = 202, 224, 64, 6
+FSPB_MLP_PARAMS = 17542
+FSPB_MLP_MAX_ROWS = 1 << 22
+
 # name -> (restype, argtypes); the list of every symbol include/fspb.h declares
 SIGNATURES = {
     "fspb_create_geometry": (C.c_int, [C.POINTER(fspb_ct), C.c_int, C.POINTER(fspb_beam),
@@ -106,6 +119,26 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.c_void_p]),
     "fspb_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
     "fspb_batch_destroy": (None, [C.c_void_p]),
+    "fspb_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_void_p)]),
+    "fspb_mlp_set_scaling": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "fspb_mlp_set_guard": (C.c_int, [C.c_void_p, C.POINTER(fspb_surrogate_guard)]),
+    "fspb_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong,
+                                      C.POINTER(fspb_adam), C.c_void_p, C.c_void_p]),
+    "fspb_mlp_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p,
+                                   C.c_void_p]),
+    "fspb_mlp_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                     C.POINTER(C.c_float), C.POINTER(C.c_longlong)]),
+    "fspb_mlp_set_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                     C.POINTER(C.c_float), C.c_longlong]),
+    "fspb_mlp_destroy": (None, [C.c_void_p]),
+    "fspb_surrogate_samples": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_surrogate_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
+    "fspb_forward_surrogate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
     "fspb_destroy": (None, [C.c_void_p]),
     "fspb_release_cached_memory": (C.c_int, []),
     "fspb_error_string": (C.c_char_p, [C.c_int]),

@@ -39,33 +39,17 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Voxel centre relative to P0; identical in every kernel so that forward,
-// adjoint and count take the same pair decisions.
-__device__ __forceinline__ void voxel_q(const PlanConst& P, int i, int j, int k, float& qx,
-                                        float& qy, float& qz) {
-    qx = fmaf((float)i, P.dx, P.qx0);
-    qy = fmaf((float)j, P.dy, P.qy0);
-    qz = fmaf((float)k, P.dz, P.qz0);
-}
-
-// Depth below the entrance and lateral offsets of a voxel for one beamlet,
-// and the pair test of Algorithm A1 step 8 (inside the ROI cylinder, t >= 0).
-template <class BD>
-__device__ __forceinline__ bool pair_coords(const BD& d, const PlanConst& P, float qx, float qy,
-                                            float qz, float& t, float& xp, float& yp) {
-    t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
-    xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
-    yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
-    return (t >= 0.0f) & (fmaf(xp, xp, yp * yp) <= P.R2);
-}
-
 // ---------------------------------------------------------------------------
 // Forward pass over one brick, three modes sharing the candidate search:
 //   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
 //   kCount  number of evaluated pairs per voxel
 //   kCost   number of candidate beamlets per brick (scheduling estimate)
+//   kSurr   the dose with the learned surrogate's parameters: per (voxel,
+//           beam) row prm[2 (b n_vox + v) + 0..1] = ((u1x, u1y, u2x, u2y)
+//           log2 e, (w1, w2, fallback, 0)); a row whose fallback flag is set
+//           takes the density-corrected pair instead
 // A brick is BX x BY x BZ = 64 voxels, one per lane.
-enum { kDose = 0, kCount = 1, kCost = 2 };
+enum { kDose = 0, kCount = 1, kCost = 2, kSurr = 3 };
 
 template <int BX, int BY, int BZ>
 __device__ __forceinline__ int bricks_x(const PlanConst& P) { return (P.nx + BX - 1) / BX; }
@@ -78,7 +62,9 @@ __device__ __forceinline__ int bricks_total(const PlanConst& P) {
 
 template <bool DC, int MODE, int BX, int BY, int BZ>
 __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
-                                           const float* fluence_, float* dose_, int* out_int_) {
+                                           const float* fluence_, float* dose_, int* out_int_,
+                                           const float4* prm_ = nullptr) {
+    static_assert(MODE != kSurr || DC, "the surrogate replaces the density-corrected parameters");
     static_assert(BX * BY * BZ == kWave, "a brick holds one voxel per lane");
     const PlanConst& P = a.P;
     const FSPB_CONST BeamDesc* __restrict__ beams = as_const(a.beams);
@@ -104,7 +90,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     float qx, qy, qz;
     voxel_q(P, i, j, k, qx, qy, qz);
     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-    if (DC && MODE == kDose && valid) fac = facs[v];
+    if (DC && (MODE == kDose || MODE == kSurr) && valid) fac = facs[v];
     // bounding sphere of the brick's voxel centres
     float cqx, cqy, cqz;
     voxel_q(P, bx * BX, by * BY, bz * BZ, cqx, cqy, cqz);
@@ -118,8 +104,18 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
 
     float acc = 0.0f;
     int cnt = 0, cost = 0;
+    const FSPB_GLOBAL float4* __restrict__ prm = as_global(prm_);
+    const long n_vox = (long)P.nx * P.ny * P.nz;
     for (int b = 0; b < P.n_beams; ++b) {
         const FSPB_CONST BeamDesc& B = beams[b];
+        // surrogate row of this voxel and beam
+        float4 s_ul = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s_w = s_ul;
+        bool own = false;
+        if (MODE == kSurr && valid) {
+            s_ul = prm[2 * ((long)b * n_vox + v)];
+            s_w = prm[2 * ((long)b * n_vox + v) + 1];
+            own = s_w.z == 0.0f;
+        }
         // rectangle of beamlets in the isocentre plane that can reach the brick
         float vx = qx - B.src[0], vy = qy - B.src[1], vz = qz - B.src[2];
         float z = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
@@ -195,9 +191,17 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                 }
                 const float kmag = magnification(t, d);
                 // a candidate with no active lane skips the block (empty exec mask)
-                if (act)
+                if (MODE == kSurr) {
+                    if (act & own)
+                        accb = fmaf(fe, pair_dose_given(t, xp, yp, kmag, d, s_ul, s_w, P, atab, tTW),
+                                    accb);
+                    else if (act)
+                        accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
+                                    accb);
+                } else if (act) {
                     accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
                                 accb);
+                }
             }
         }
         acc += accb;
@@ -220,11 +224,12 @@ template <bool DC, int MODE, int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __restrict__ order,
                                                     const float* __restrict__ fluence,
                                                     float* __restrict__ dose,
-                                                    int* __restrict__ out_int) {
+                                                    int* __restrict__ out_int,
+                                                    const float4* __restrict__ prm) {
     const int slot = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (slot >= bricks_total<BX, BY, BZ>(a.P)) return;
     const int brick = order ? order[slot] : slot;
-    brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int);
+    brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int, prm);
 }
 
 // Many plans in one persistent launch: wave q walks its own static list of
@@ -422,14 +427,14 @@ void shape_dims(int shape, int d[3]) {
 
 template <bool DC, int MODE>
 static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
-                        float* dose, int* out_int, hipStream_t s) {
+                        float* dose, int* out_int, hipStream_t s, const float4* prm = nullptr) {
     const int wpb = cfg.waves_per_block;
     const long nb = brick_count(a.P, cfg.shape);
     dim3 grid((unsigned)((nb + wpb - 1) / wpb)), block(kWave * wpb);
 #define FSPB_SHAPE(ID, X, Y, Z)                                                                \
     case ID:                                                                                   \
         hipLaunchKernelGGL((dose_forward<DC, MODE, X, Y, Z>), grid, block, 0, s, a, order,     \
-                           fluence, dose, out_int);                                            \
+                           fluence, dose, out_int, prm);                                       \
         break;
     switch (cfg.shape) {
         FSPB_SHAPE(0, 4, 4, 4)
@@ -446,6 +451,11 @@ void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
         launch_mode<true, kDose>(a, cfg, order, fluence, dose, nullptr, s);
     else
         launch_mode<false, kDose>(a, cfg, order, fluence, dose, nullptr, s);
+}
+
+void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
+                              const float* fluence, const float4* prm, float* dose, hipStream_t s) {
+    launch_mode<true, kSurr>(a, cfg, order, fluence, dose, nullptr, s, prm);
 }
 
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,

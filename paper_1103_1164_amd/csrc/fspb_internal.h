@@ -46,7 +46,9 @@ struct alignas(16) BeamletDesc {
     int tab_off;       // first sample of this beamlet's depth tables
     int K;             // depth-table length (0 if the beamlet misses the body)
     int hit;
-    int pad[3];
+    float theta;       // angle to the beam's central axis
+    int beam;          // index of the beam the beamlet belongs to
+    int pad;
 };
 static_assert(sizeof(BeamletDesc) == 96, "BeamletDesc layout");
 

@@ -258,6 +258,9 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
     o.c_x = (float)(v0[0] * f.ex[0] + v0[1] * f.ex[1] + v0[2] * f.ex[2]);
     o.c_y = (float)(v0[0] * f.ey[0] + v0[1] * f.ey[1] + v0[2] * f.ey[2]);
     o.sad = (float)f.sad;
+    o.theta = (float)f.theta;
+    o.beam = f.beam;
+    o.pad = 0;
     o.x0 = (float)f.x0;
     o.y0 = (float)f.y0;
     {

@@ -61,6 +61,10 @@ void shape_dims(int shape, int d[3]);
 
 void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
                     const float* fluence, float* dose, hipStream_t s);
+// Dose with the learned surrogate's per-(voxel, beam) parameters (see
+// dose.hip, mode kSurr); needs a density-corrected geometry.
+void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
+                              const float* fluence, const float4* prm, float* dose, hipStream_t s);
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                   int* counts, hipStream_t s);
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s);

@@ -62,6 +62,26 @@ __device__ __forceinline__ float clampf(float x, float lo, float hi) {
     return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
+// Voxel centre relative to P0; identical in every kernel so that forward,
+// adjoint and count take the same pair decisions.
+__device__ __forceinline__ void voxel_q(const PlanConst& P, int i, int j, int k, float& qx,
+                                        float& qy, float& qz) {
+    qx = fmaf((float)i, P.dx, P.qx0);
+    qy = fmaf((float)j, P.dy, P.qy0);
+    qz = fmaf((float)k, P.dz, P.qz0);
+}
+
+// Depth below the entrance and lateral offsets of a voxel for one beamlet,
+// and the pair test of Algorithm A1 step 8 (inside the ROI cylinder, t >= 0).
+template <class BD>
+__device__ __forceinline__ bool pair_coords(const BD& d, const PlanConst& P, float qx, float qy,
+                                            float qz, float& t, float& xp, float& yp) {
+    t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
+    xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
+    yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
+    return (t >= 0.0f) & (fmaf(xp, xp, yp * yp) <= P.R2);
+}
+
 // SAD / |r_a| for a voxel at depth t below the beamlet's entrance.
 template <class BD>
 __device__ __forceinline__ float magnification(float t, const BD& b) {
@@ -144,6 +164,67 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
     float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
     float F = fmaf(w1, p1, w2 * p2);
+    return F * A * isq;
+}
+
+// The six Section 2.1 parameters a pair uses, in the units of the tables
+// (u in 1/cm, weights dimensionless): out = (u1x, u1y, u2x, u2y, w1, w2).
+// Same arithmetic as pair_dose<true>; exported as training targets of the
+// learned surrogate.
+template <class BD>
+__device__ __forceinline__ void dc_params(float t, const BD& b, float4 fac, const PlanConst& P,
+                                          const float4* __restrict__ dtab,
+                                          const float4* __restrict__ tTW, float out[6]) {
+    const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
+    const int jd = (int)cd;
+    const float fd = fract(cd);
+    const float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
+    const float c = t * P.inv_d;
+    const int j = max(min((int)c, b.K - 2), 0);
+    const float f = fract(c);
+    const float4 r0 = tTW[2 * (b.tab_off + j)];
+    const float4 r1 = tTW[2 * (b.tab_off + j) + 1];
+    const float W1 = fmaf(f, r0.w, r0.z), W2 = fmaf(f, r1.y, r1.x);
+    const float inv_l2e = 1.0f / kLog2e;
+    out[0] = fmaf(fd, us.x, u0.x) * fac.x * inv_l2e;
+    out[1] = fmaf(fd, us.y, u0.y) * fac.x * inv_l2e;
+    out[2] = fmaf(fd, us.z, u0.z) * fac.y * inv_l2e;
+    out[3] = fmaf(fd, us.w, u0.w) * fac.y * inv_l2e;
+    out[4] = fmaxf(fac.z * (fmaf(fd, wv.z, wv.x) + W1), 0.0f);
+    out[5] = fmaxf(fac.w * (fmaf(fd, wv.w, wv.y) + W2), 0.0f);
+}
+
+// Unit-fluence dose of a pair whose six parameters are given (the learned
+// surrogate's prediction for the voxel and the beamlet's beam):
+// ul = (u1x, u1y, u2x, u2y) * log2(e), wv = (w1, w2, ., .).  Depth, t_eq, A
+// and the inverse square stay the beamlet's own (Eq. 2).  Needs the
+// density-corrected tables (tTW).
+template <class BD>
+__device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, float k, const BD& b,
+                                                 float4 ul, float4 wv, const PlanConst& P,
+                                                 const FSPB_GLOBAL float4* __restrict__ atab,
+                                                 const FSPB_GLOBAL float4* __restrict__ tTW) {
+    float x = xp * k, y = yp * k;
+    float isq = k * (0.25f * k);
+    const float c = t * P.inv_d;
+    const int j = max(min((int)c, b.K - 2), 0);
+    const float f = fract(c);
+    const float4 r0 = tTW[2 * (b.tab_off + j)];
+    const float teq = fmaf(f, r0.y, r0.x);
+    const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
+    const int ja = (int)ca;
+    const float fa = fract(ca);
+    const float4 ae = atab[ja * P.a_cols + b.th_col];
+    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
+    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+    float ax = fabsf(x), ay = fabsf(y);
+    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
+    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
+    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
+    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    float p1 = penumbra2(ul.x, dmx, dpx, sgx, o2x) * penumbra2(ul.y, dmy, dpy, sgy, o2y);
+    float p2 = penumbra2(ul.z, dmx, dpx, sgx, o2x) * penumbra2(ul.w, dmy, dpy, sgy, o2y);
+    float F = fmaf(wv.x, p1, wv.y * p2);
     return F * A * isq;
 }
 

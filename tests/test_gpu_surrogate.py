@@ -1,0 +1,300 @@
+"""The learned surrogate on an MI355X: MFMA training kernels against the FP64
+MLP reference, checkpoint/resume, the GPU-gathered input rows and targets
+against the oracle's definition, fused inference, and the dose with the
+predicted parameters against the oracle's dose with the same parameters.
+
+Tolerances.  The kernels store activations, output gradients and
+pre-activation gradients in BF16 (unit roundoff 2^-9) and accumulate in FP32.
+Against the reference evaluated with the same BF16 rounding points
+(oracle.mlp with q = round_bf16) the remaining differences are FP32
+accumulation order, the device tanh and the rare BF16 value that rounds the
+other way, so gradients agree to 5e-3 in relative Frobenius norm per
+parameter block and standardised outputs to 5e-3 absolute; against the
+unrounded FP64 reference to 3e-2.  Input rows are compared to one BF16 ulp;
+targets (FP32 tables and smoothing vs FP64) to 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+import fspb_synth as S
+from gpu_helpers import assert_dose_parity, geometry, say
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+LOG2E = 1.4426950408889634
+
+
+def _bf16_values(x: torch.Tensor) -> np.ndarray:
+    return x.float().cpu().numpy().astype(np.float64)
+
+
+def _split(flat):
+    out, o = {}, 0
+    for n in M.NAMES:
+        k = int(np.prod(M.SHAPES[n]))
+        out[n] = np.asarray(flat[o:o + k], np.float64).reshape(M.SHAPES[n])
+        o += k
+    return out
+
+
+def _gpu_view(flat32):
+    """Parameters as the kernels use them: BF16 weights, FP32 biases."""
+    p = _split(flat32)
+    for n in ("W1", "W2", "W3"):
+        p[n] = M.round_bf16(p[n])
+    return p
+
+
+def _rand_rows(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 224), np.float32)
+    x[:, :202] = rng.normal(0, 1, (n, 202))
+    xb = torch.as_tensor(x, device="cuda").to(torch.bfloat16)
+    t = torch.as_tensor(rng.normal(0, 1, (n, 6)).astype(np.float32), device="cuda")
+    return xb, t
+
+
+_OFF = dict(zip(M.NAMES, np.cumsum([0] + [int(np.prod(M.SHAPES[n])) for n in M.NAMES])[:-1]))
+
+
+def _params(seed, scale=1.0):
+    """Glorot weights (scaled) with nonzero biases, flat FP32."""
+    from paper_1103_1164_amd import Mlp
+    p = Mlp.init_params(seed) * scale
+    rng = np.random.default_rng(seed + 1)
+    for n in ("b1", "b2", "b3"):
+        k = M.SHAPES[n][0]
+        p[_OFF[n]:_OFF[n] + k] = rng.normal(0, 0.1, k)
+    return p.astype(np.float32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n", [200, 32, 1, 4133])
+def test_mlp_gradients_match_reference(n):
+    from paper_1103_1164_amd import Mlp
+    p32 = _params(3)
+    mlp = Mlp(p32)
+    x, t = _rand_rows(n, 10 + n)
+    say(f"mlp grads: n={n}")
+    loss, g = mlp.loss_grad(x, t)
+    torch.cuda.synchronize()
+    g = _split(g.cpu().numpy())
+    p = _gpu_view(p32)
+    X, T = _bf16_values(x)[:, :202], t.cpu().numpy().astype(np.float64)
+    l_q, g_q = M.loss_and_grads(p, X, T, q=M.round_bf16)
+    l_e, g_e = M.loss_and_grads(p, X, T)
+    assert abs(loss.item() - l_q) <= 1e-3 * l_q
+    for k in M.NAMES:
+        assert _rel(g[k], g_q[k]) < 5e-3, (k, _rel(g[k], g_q[k]))
+        assert _rel(g[k], g_e[k]) < 3e-2, (k, _rel(g[k], g_e[k]))
+
+
+def test_mlp_predict_matches_reference():
+    from paper_1103_1164_amd import Mlp
+    p32 = _params(5)
+    mlp = Mlp(p32)
+    x, _ = _rand_rows(77, 5)
+    y = mlp.predict(x).cpu().numpy()
+    Y, _ = M.forward(_gpu_view(p32), _bf16_values(x)[:, :202], q=M.round_bf16)
+    assert np.max(np.abs(y - Y)) < 5e-3
+    assert mlp.predict(x[:0]).shape == (0, 6)
+
+
+def test_adam_steps_match_reference():
+    from paper_1103_1164_amd import Mlp
+    p32 = _params(7)
+    mlp = Mlp(p32)
+    x, t = _rand_rows(300, 7)
+    p = _split(p32)
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    for k in (1, 2, 3):
+        _, g = mlp.loss_grad(x, t)           # the gradient the step will use
+        g = _split(g.cpu().numpy())
+        mlp.train_step(x, t, lr=3e-3, betas=(0.9, 0.99), eps=1e-7)
+        p, m, v = M.adam_step(p, g, m, v, k, lr=3e-3, beta1=0.9, beta2=0.99, eps=1e-7)
+        st = mlp.state()
+        assert st["step"] == k
+        got = _split(st["params"])
+        for name in M.NAMES:
+            assert np.allclose(got[name], p[name], rtol=1e-5, atol=1e-7), (k, name)
+        for name, ref in (("adam_m", m), ("adam_v", v)):
+            gm = _split(st[name])
+            for q in M.NAMES:
+                assert np.allclose(gm[q], ref[q], rtol=1e-5, atol=1e-12), (k, name, q)
+        p = _split(st["params"])             # continue from the device's FP32 state
+        m = _split(st["adam_m"])
+        v = _split(st["adam_v"])
+
+
+def test_training_resumes_bitwise(tmp_path):
+    from paper_1103_1164_amd import Mlp
+    x, t = _rand_rows(1000, 9)
+    a = Mlp(_params(9))
+    for _ in range(5):
+        a.train_step(x[:600], t[:600])
+    ck = tmp_path / "ck.npz"
+    a.save(ck)
+    la = [a.train_step(x[600 - 64 * k:], t[600 - 64 * k:]).item() for k in range(3)]
+    b = Mlp(Mlp.init_params(123))
+    b.restore(ck)
+    lb = [b.train_step(x[600 - 64 * k:], t[600 - 64 * k:]).item() for k in range(3)]
+    sa, sb = a.state(), b.state()
+    assert la == lb
+    for k in ("params", "adam_m", "adam_v"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sa["step"] == sb["step"] == 8
+
+
+def test_loss_decreases_on_a_smooth_target():
+    from paper_1103_1164_amd import Mlp
+    rng = np.random.default_rng(11)
+    x, _ = _rand_rows(4096, 11)
+    X = _bf16_values(x)[:, :202]
+    W = rng.normal(0, 0.1, (202, 6))
+    t = torch.as_tensor(np.tanh(X @ W).astype(np.float32), device="cuda")
+    mlp = Mlp(Mlp.init_params(0))
+    first = mlp.train_step(x, t, lr=3e-3).item()
+    for _ in range(300):
+        last = mlp.train_step(x, t, lr=3e-3).item()
+    assert last < 0.1 * first
+
+
+# ---------------------------------------------------------------------------
+def _hetero_plan(seed=0, n=(30, 26, 22)):
+    rng = np.random.default_rng(seed)
+    Z, Y, X = np.meshgrid(*[np.arange(k) for k in n[::-1]], indexing="ij")
+    rho = rng.normal(1.03, 0.02, size=n[::-1])
+    rho[(X - 12) ** 2 + (Y - 14) ** 2 + (Z - 10) ** 2 < 16] = 0.01     # air cavity
+    rho[(X > 20) & (Y < 10)] = 1.8                                      # bone block
+    rho[Y < 3] = 0.001                                                  # air in front
+    beams = [S.Beam(gantry=0.2, nbx=6, nby=5, wx=0.5, wy=0.5),
+             S.Beam(gantry=2.4, couch=0.3, nbx=5, nby=5, wx=0.6, wy=0.4, cx=0.2)]
+    return S.plan_small(n=n, density=rho.astype(np.float32), beams=beams, seed=seed,
+                        name=f"hetero{seed}")
+
+
+def test_sample_rows_match_oracle(oracle_mod):
+    plan = _hetero_plan(1)
+    geo = geometry(plan, 1)
+    o = oracle_mod.Oracle(plan)
+    rng = np.random.default_rng(2)
+    n = 700
+    vox = rng.integers(0, o.n_vox, size=n)
+    beam = rng.integers(0, 2, size=n)
+    # rows outside the grid or beam list come back invalid
+    vox[:3] = [-1, o.n_vox, 5]
+    beam[:3] = [0, 1, 7]
+    rows = torch.as_tensor(np.stack([vox, beam], 1).astype(np.int32), device="cuda")
+    x, t, valid = geo.surrogate_samples(rows)
+    x, t, valid = _bf16_values(x), t.cpu().numpy(), valid.cpu().numpy()
+    assert not valid[:3].any() and not x[:3].any() and not t[:3].any()
+    feat, near, amb, tie = o.surrogate_rows(vox[3:], beam[3:])
+    ok = (amb == 0) & (tie > 1e-3)
+    x, t, valid = x[3:], t[3:], valid[3:]
+    assert np.array_equal(valid[ok] == 1, near[ok] >= 0)
+    sel = ok & (near >= 0)
+    assert sel.sum() > 150 and (ok & (near < 0)).sum() > 20
+    want = np.zeros((n - 3, 224))
+    want[:, :200] = feat[:, :200] - 1.0
+    want[:, 200] = feat[:, 200] * 0.1 - 1.0
+    want[:, 201] = 10.0 * feat[:, 201]
+    wb = M.round_bf16(want)
+    err = np.abs(x[sel] - wb[sel])
+    assert np.all(err <= 2.0 ** -7 * np.abs(wb[sel]) + 1e-5), float(err.max())
+    assert not x[sel][:, 202:].any()
+    for k in np.flatnonzero(sel)[:200]:
+        prm, _ = o.params(int(vox[3 + k]), int(near[k]))
+        assert np.allclose(t[k], prm, rtol=1e-4, atol=1e-5), (k, t[k], prm)
+    assert not t[~valid.astype(bool)].any()
+
+
+def _trained_like(seed, mean, std):
+    """A network with arbitrary but fixed weights and a given scaling."""
+    from paper_1103_1164_amd import Mlp
+    mlp = Mlp(_params(seed, scale=0.5))
+    mlp.set_scaling(mean, std)
+    return mlp
+
+
+def test_infer_matches_oracle(oracle_mod):
+    plan = _hetero_plan(2)
+    geo = geometry(plan, 1)
+    o = oracle_mod.Oracle(plan)
+    mean = np.array([2.0, 2.1, 0.7, 0.65, 0.6, 0.3], np.float32)
+    std = np.array([0.3, 0.3, 0.1, 0.1, 0.05, 0.05], np.float32)
+    mlp = _trained_like(21, mean, std)
+    band_lo = mean - 1.0 * std
+    band_hi = mean + 1.0 * std
+    mlp.set_guard(0.005, 1.85, 0.3, band_lo, band_hi)
+    prm = geo.surrogate_infer(mlp).cpu().numpy()
+    assert prm.shape == (2, o.n_vox, 8)
+    rng = np.random.default_rng(3)
+    vox = rng.integers(0, o.n_vox, size=400)
+    beam = rng.integers(0, 2, size=400)
+    feat, near, amb, tie = o.surrogate_rows(vox, beam)
+    X = np.zeros((400, 202))
+    X[:, :200] = feat[:, :200] - 1.0
+    X[:, 200] = feat[:, 200] * 0.1 - 1.0
+    X[:, 201] = 10.0 * feat[:, 201]
+    Y, _ = M.forward(_gpu_view(_params(21, scale=0.5)), M.round_bf16(X), q=M.round_bf16)
+    val = Y * std + mean
+    rows = prm[beam, vox]
+    ok = (amb == 0) & (tie > 1e-3)
+    n_checked = n_fb = 0
+    for k in np.flatnonzero(ok):
+        if near[k] < 0:
+            assert rows[k, 6] == 1.0 and not rows[k, :6].any()
+            n_fb += 1
+            continue
+        patch = feat[k, :200]
+        rc = patch[25 * 7 + 12]
+        het = np.max(np.abs(patch[150:] - rc))
+        margin_rho = min(abs(patch.min() - 0.005), abs(patch.max() - 1.85), abs(het - 0.3))
+        margin_band = np.min(np.minimum(np.abs(val[k] - band_lo), np.abs(val[k] - band_hi)) / std)
+        if margin_rho < 1e-4 or margin_band < 1e-2:
+            continue                      # decided too close to a threshold to compare
+        fb = (patch.min() < 0.005 or patch.max() > 1.85 or het > 0.3
+              or np.any(val[k] < band_lo) or np.any(val[k] > band_hi))
+        assert rows[k, 6] == float(fb), k
+        n_fb += int(fb)
+        if not fb:
+            got = np.concatenate([rows[k, :4] / LOG2E, rows[k, 4:6]])
+            want = np.concatenate([val[k, :4], np.maximum(val[k, 4:6], 0.0)])
+            assert np.all(np.abs((got - want) / std) < 5e-3), (k, got, want)
+            n_checked += 1
+    assert n_checked > 20 and n_fb > 20, (n_checked, n_fb)
+
+
+@pytest.mark.parametrize("het", [0.3, -1.0])
+def test_forward_surrogate_matches_oracle(oracle_mod, het):
+    plan = _hetero_plan(4)
+    geo = geometry(plan, 1)
+    o = oracle_mod.Oracle(plan)
+    mean = np.array([2.0, 2.0, 0.7, 0.7, 0.6, 0.3], np.float32)
+    std = np.array([0.3, 0.3, 0.1, 0.1, 0.05, 0.05], np.float32)
+    mlp = _trained_like(31, mean, std)
+    mlp.set_guard(-1.0, 3.0, het)
+    f = torch.as_tensor(plan.fluence, device="cuda")
+    prm = geo.surrogate_infer(mlp)
+    d = geo.forward_surrogate(f, prm).cpu().numpy().astype(np.float64).reshape(-1)
+    P = prm.cpu().numpy()
+    rng = np.random.default_rng(5)
+    vox = rng.choice(o.n_vox, size=500, replace=False)
+    rows = np.zeros((vox.size, 2, 7))
+    rows[..., :4] = np.transpose(P[:, vox, :4], (1, 0, 2)) / LOG2E
+    rows[..., 4:6] = np.transpose(P[:, vox, 4:6], (1, 0, 2))
+    rows[..., 6] = np.transpose(P[:, vox, 6], (1, 0))
+    d_o, amb = o.dose_given(rows, vox=vox)
+    d_all, _, _ = o.dose()
+    assert_dose_parity(d[vox], d_o, amb, scale=np.abs(d_all).max(), what=f"surrogate het={het}")
+    if het < 0:
+        assert P[:, :, 6].min() == 1.0
+        ref = geo.forward(f).cpu().numpy().reshape(-1)
+        assert np.allclose(d, ref, rtol=1e-6, atol=1e-7 * np.abs(ref).max())
+    else:
+        assert 0.0 < P[:, :, 6].mean() < 1.0
