@@ -316,7 +316,8 @@ void fspb_batch_destroy(fspb_batch* b);
  * trilinear density at lattice point (a, b) minus 1; input 200 is
  * t / 10 cm - 1 and input 201 is 10 theta of the nearest beamlet.
  * Targets are the corrected parameters of the nearest beamlet at the voxel
- * (u in 1/cm); the network learns them standardised, value = y std + mean.
+ * (u in 1/cm).  The network's outputs are z = (log u1x, log u1y, log u2x,
+ * log u2y, w1, w2) standardised: z = y std + mean.
  * ------------------------------------------------------------------------ */
 #define FSPB_MLP_IN 202
 #define FSPB_MLP_IN_PAD 224
@@ -332,8 +333,10 @@ typedef struct {
 } fspb_adam;
 
 /* Guard: a row falls back when a patch density leaves [rho_lo, rho_hi],
- * when max |rho - rho(voxel)| over the two planes next to the voxel exceeds
- * het_max, or when a predicted parameter leaves [band_lo[c], band_hi[c]]. */
+ * when the larger of max |rho - rho(voxel)| over the two planes next to the
+ * voxel and |rho_hat(voxel) - rho(voxel)| (rho_hat: the smoothed density of
+ * Section 2.1) exceeds het_max, or when a predicted parameter (u1x, u1y,
+ * u2x, u2y, w1, w2) leaves [band_lo[c], band_hi[c]]. */
 typedef struct {
     float rho_lo, rho_hi, het_max;
     float band_lo[6], band_hi[6];
@@ -344,7 +347,8 @@ typedef struct {
  * and the guard open (nothing falls back but invalid rows). */
 int fspb_mlp_create(const float* params, fspb_mlp** out);
 
-/* Target standardisation (host, 6 values each; std > 0). */
+/* Standardisation of the network's outputs z (host, 6 values each;
+ * std > 0). */
 int fspb_mlp_set_scaling(fspb_mlp* m, const float* mean, const float* stdev);
 
 /* Fallback guard (host struct, copied). */

@@ -1419,8 +1419,8 @@ int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* densi
     if ((rc = check_surrogate_geometry(g, "surrogate_infer")) != FSPB_OK) return rc;
     if (!m || !density || !prm) return fail(FSPB_E_ARG, "surrogate_infer: NULL argument");
     if (m->device != g->device) return fail(FSPB_E_STATE, "surrogate_infer: handles on different devices");
-    launch_surrogate_infer(g->args(), density, m->weights(), m->sc, m->gd, (float4*)prm,
-                           (hipStream_t)stream);
+    launch_surrogate_infer(g->args(), density, g->rhohat, m->weights(), m->sc, m->gd,
+                           (float4*)prm, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }

@@ -48,15 +48,17 @@ struct AdamParams {
     float bc1, bc2;   // 1 - beta^step
 };
 
-// Network outputs are standardised targets: value = y * std + mean.
+// Network outputs are standardised targets: z = y * std + mean, where z is
+// (log u1x, log u1y, log u2x, log u2y, w1, w2).
 struct SurrogateScale {
     float mean[kMlpOut], stdev[kMlpOut];
 };
 
 // A row falls back to the density-corrected parameters when it is invalid
 // (no nearest-beamlet pair), when a patch density leaves [rho_lo, rho_hi],
-// when the largest |rho - rho(voxel)| over the two planes next to the voxel
-// exceeds het_max, or when a predicted parameter leaves [band_lo, band_hi].
+// when the larger of max |rho - rho(voxel)| over the two planes next to the
+// voxel and |rho_hat(voxel) - rho(voxel)| exceeds het_max, or when a
+// predicted parameter (u, w) leaves [band_lo, band_hi].
 struct SurrogateGuard {
     float rho_lo, rho_hi, het_max;
     float band_lo[kMlpOut], band_hi[kMlpOut];
@@ -79,8 +81,8 @@ void launch_surrogate_samples(const DoseArgs& a, const float* rho, const int2* r
                               __bf16* X, float* T, int* valid, hipStream_t s);
 // Every (voxel, beam) row: prm[2 (b n_vox + v)] = (u1x, u1y, u2x, u2y) log2 e,
 // prm[2 (b n_vox + v) + 1] = (w1, w2, fallback flag, 0).
-void launch_surrogate_infer(const DoseArgs& a, const float* rho, const MlpWeights& W,
-                            const SurrogateScale& sc, const SurrogateGuard& g, float4* prm,
-                            hipStream_t s);
+void launch_surrogate_infer(const DoseArgs& a, const float* rho, const float* rhohat,
+                            const MlpWeights& W, const SurrogateScale& sc,
+                            const SurrogateGuard& g, float4* prm, hipStream_t s);
 
 }  // namespace fspb

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(128) void mlp_train_kernel(const __bf16* __restrict
     if (lane == 0) g.red[wid] = lsum;
     __syncthreads();
     float* gout = grad + (long)blockIdx.x * kMlpParams;
-    if (threadIdx.x == 0) loss[blockIdx.x] = g.red[0] + g.red[1];
+    if (threadIdx.x == 0) loss[blockIdx.x] = (g.red[0] + g.red[1]) * (0.5f * scale);   // mean share
 
     // dW3[in][out] = H2^T dY  (M = 64 inputs, N = 16 outputs, K = 32 rows)
     for (int mt = wid; mt < 4; mt += 2) {
@@ -556,6 +556,7 @@ __device__ __forceinline__ void copy_rows16(__bf16* dst, int dst_stride, const _
 
 __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                                                               const float* __restrict__ rho,
+                                                              const float* __restrict__ rhohat,
                                                               MlpWeights W, SurrogateScale sc,
                                                               SurrogateGuard gd,
                                                               float4* __restrict__ prm) {
@@ -588,21 +589,45 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
         RowGeo r;
         r.valid = false;
         if (row_in) r = row_geometry(a, rho, v, b);
-        const bool any = __ballot(r.valid) != 0;
+        // The heterogeneity test runs first, on the cheapest data: the
+        // smoothed density at the voxel, then the two planes next to it
+        // (k-steps 4-6, kept as A fragments).  A wave whose rows all fall
+        // back skips the rest of the gather and the network.
         float rmin = FLT_MAX, rmax = -FLT_MAX, het = 0.0f;
+        if (r.valid) het = fabsf(rhohat[v] - r.rho_c);
+        bool live = r.valid && het <= gd.het_max;
+        constexpr int kNear = 4;            // first k-step that holds plane 6
+        bf16x8 xn[kK1 / 32 - kNear];
+        if (__ballot(live) != 0) {
+#pragma unroll
+            for (int q = 0; q < kK1 / 32 - kNear; ++q) {
+                xn[q] = bf16x8{};
+                if (live) xn[q] = gather8(rho, P, r, kNear + q, lane, rmin, rmax, het);
+            }
+            row_stats_combine(rmin, rmax, het);
+            live = live && het <= gd.het_max;
+        }
+        const bool any = __ballot(live) != 0;
         if (any) {
-            // layer 1, the inputs gathered one k-step (8 features a lane) at a time
+            // layer 1, the remaining inputs gathered one k-step (8 features a
+            // lane) at a time
             f32x4 acc[4];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-            for (int kt = 0; kt < kK1 / 32; ++kt) {
+            for (int kt = 0; kt < kNear; ++kt) {
                 bf16x8 xk = {};
-                if (r.valid) xk = gather8(rho, P, r, kt, lane, rmin, rmax, het);
+                if (live) xk = gather8(rho, P, r, kt, lane, rmin, rmax, het);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[nt] = mfma(xk, ld8(L.w1 + (nt * 16 + fr) * kW1S + kt * 32 + fk), acc[nt]);
             }
+#pragma unroll
+            for (int q = 0; q < kK1 / 32 - kNear; ++q)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = mfma(xn[q], ld8(L.w1 + (nt * 16 + fr) * kW1S + (kNear + q) * 32 + fk),
+                                   acc[nt]);
             row_stats_combine(rmin, rmax, het);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
@@ -641,14 +666,15 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
         __syncthreads();
         if (lane < 16 && row_in) {
             float o[kMlpOut];
-            bool fb = !r.valid;
-            if (r.valid) {
+            bool fb = !live;
+            if (live) {
 #pragma unroll
                 for (int c = 0; c < kMlpOut; ++c) {
                     o[c] = fmaf(yl[lane * 8 + c], sc.stdev[c], sc.mean[c]);
+                    if (c < 4) o[c] = __expf(o[c]);     // the network predicts log u
                     fb |= !(o[c] >= gd.band_lo[c] && o[c] <= gd.band_hi[c]);
                 }
-                fb |= !(rmin >= gd.rho_lo && rmax <= gd.rho_hi && het <= gd.het_max);
+                fb |= !(rmin >= gd.rho_lo && rmax <= gd.rho_hi);
             }
             float4 ul = make_float4(0.f, 0.f, 0.f, 0.f), wv = make_float4(0.f, 0.f, 1.f, 0.f);
             if (!fb) {
@@ -703,14 +729,14 @@ void launch_surrogate_samples(const DoseArgs& a, const float* rho, const int2* r
                        a, rho, rows, n, X, T, valid);
 }
 
-void launch_surrogate_infer(const DoseArgs& a, const float* rho, const MlpWeights& W,
-                            const SurrogateScale& sc, const SurrogateGuard& g, float4* prm,
-                            hipStream_t s) {
+void launch_surrogate_infer(const DoseArgs& a, const float* rho, const float* rhohat,
+                            const MlpWeights& W, const SurrogateScale& sc,
+                            const SurrogateGuard& g, float4* prm, hipStream_t s) {
     const long n_vox = (long)a.P.nx * a.P.ny * a.P.nz;
     const long n_groups = ((n_vox + 15) / 16 * a.P.n_beams + kInferWaves - 1) / kInferWaves;
     const unsigned grid = (unsigned)std::min<long>(n_groups, 2048);
-    hipLaunchKernelGGL(surrogate_infer_kernel, dim3(grid), dim3(64 * kInferWaves), 0, s, a, rho, W,
-                       sc, g, prm);
+    hipLaunchKernelGGL(surrogate_infer_kernel, dim3(grid), dim3(64 * kInferWaves), 0, s, a, rho,
+                       rhohat, W, sc, g, prm);
 }
 
 void launch_mlp_loss_sum(const float* parts, int n_parts, float* out, hipStream_t s) {

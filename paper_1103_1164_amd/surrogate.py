@@ -32,7 +32,7 @@ from . import Geometry, Mlp
 class Dataset:
     x: torch.Tensor          # BF16 [n, 224] scaled inputs
     t: torch.Tensor          # FP32 [n, 6] targets (unstandardised)
-    mean: np.ndarray         # target standardisation
+    mean: np.ndarray         # standardisation of the network targets
     std: np.ndarray
     rho_lo: float            # density range the rows were gathered from
     rho_hi: float
@@ -90,16 +90,24 @@ def build_dataset(plans: Iterable, rows_per_plan: int, seed: int = 0,
     perm = torch.randperm(x.shape[0], generator=g).to(x.device)
     x, t = x[perm].contiguous(), t[perm].contiguous()
     tt = t.double()
-    mean = tt.mean(0).cpu().numpy()
-    std = np.maximum(tt.std(0).cpu().numpy(), 1e-6)
+    zz = network_targets(t).double()
+    mean = zz.mean(0).cpu().numpy()
+    std = np.maximum(zz.std(0).cpu().numpy(), 1e-6)
     return Dataset(x, t, mean.astype(np.float32), std.astype(np.float32), rho_lo, rho_hi,
                    tt.min(0).values.cpu().numpy(), tt.max(0).values.cpu().numpy())
+
+
+def network_targets(t: torch.Tensor) -> torch.Tensor:
+    """What the network predicts: (log u1x, log u1y, log u2x, log u2y, w1, w2)."""
+    z = t.clone()
+    z[:, :4] = torch.log(t[:, :4])
+    return z
 
 
 def standardised_targets(data: Dataset) -> torch.Tensor:
     m = torch.as_tensor(data.mean, device=data.t.device)
     s = torch.as_tensor(data.std, device=data.t.device)
-    return ((data.t - m) / s).contiguous()
+    return ((network_targets(data.t) - m) / s).contiguous()
 
 
 def fit(mlp: Mlp, data: Dataset, epochs: int = 20, batch: int = 8192, lr: float = 2e-3,
@@ -151,7 +159,9 @@ def evaluate(mlp: Mlp, plan, geo: Optional[Geometry] = None, fluence=None) -> di
     geo.set_dc(True)
     fb = prm[:, :, 6]
     out = dict(err_surrogate=dose_error(d_s, d_dc), err_plain=dose_error(d_plain, d_dc),
-               fallback_fraction=float(fb.mean().item()), max_dose=float(d_dc.max().item()))
+               fallback_fraction=float(fb.mean().item()),
+               served_fraction=float((fb == 0).float().mean().item()),
+               max_dose=float(d_dc.max().item()))
     if own:
         geo.close()
     return out

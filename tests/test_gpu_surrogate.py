@@ -125,7 +125,10 @@ def test_adam_steps_match_reference():
         for name, ref in (("adam_m", m), ("adam_v", v)):
             gm = _split(st[name])
             for q in M.NAMES:
-                assert np.allclose(gm[q], ref[q], rtol=1e-5, atol=1e-12), (k, name, q)
+                # m and v are FP32 running sums: rounding is absolute where
+                # they nearly cancel, so the bound scales with the array
+                tol = 1e-6 * np.abs(ref[q]).max()
+                assert np.allclose(gm[q], ref[q], rtol=1e-5, atol=tol), (k, name, q)
         p = _split(st["params"])             # continue from the device's FP32 state
         m = _split(st["adam_m"])
         v = _split(st["adam_v"])
@@ -225,11 +228,13 @@ def test_infer_matches_oracle(oracle_mod):
     plan = _hetero_plan(2)
     geo = geometry(plan, 1)
     o = oracle_mod.Oracle(plan)
-    mean = np.array([2.0, 2.1, 0.7, 0.65, 0.6, 0.3], np.float32)
-    std = np.array([0.3, 0.3, 0.1, 0.1, 0.05, 0.05], np.float32)
+    # outputs z = (log u1x, log u1y, log u2x, log u2y, w1, w2), standardised
+    mean = np.array([np.log(2.0), np.log(2.1), np.log(0.7), np.log(0.65), 0.6, 0.3], np.float32)
+    std = np.array([0.3, 0.3, 0.2, 0.2, 0.05, 0.05], np.float32)
     mlp = _trained_like(21, mean, std)
-    band_lo = mean - 1.0 * std
-    band_hi = mean + 1.0 * std
+    zlo, zhi = mean - std, mean + std
+    band_lo = np.concatenate([np.exp(zlo[:4]), zlo[4:]])
+    band_hi = np.concatenate([np.exp(zhi[:4]), zhi[4:]])
     mlp.set_guard(0.005, 1.85, 0.3, band_lo, band_hi)
     prm = geo.surrogate_infer(mlp).cpu().numpy()
     assert prm.shape == (2, o.n_vox, 8)
@@ -237,12 +242,14 @@ def test_infer_matches_oracle(oracle_mod):
     vox = rng.integers(0, o.n_vox, size=400)
     beam = rng.integers(0, 2, size=400)
     feat, near, amb, tie = o.surrogate_rows(vox, beam)
+    rhohat = o.smoothed(vox)
     X = np.zeros((400, 202))
     X[:, :200] = feat[:, :200] - 1.0
     X[:, 200] = feat[:, 200] * 0.1 - 1.0
     X[:, 201] = 10.0 * feat[:, 201]
     Y, _ = M.forward(_gpu_view(_params(21, scale=0.5)), M.round_bf16(X), q=M.round_bf16)
-    val = Y * std + mean
+    z = Y * std + mean
+    val = np.concatenate([np.exp(z[:, :4]), z[:, 4:]], axis=1)
     rows = prm[beam, vox]
     ok = (amb == 0) & (tie > 1e-3)
     n_checked = n_fb = 0
@@ -253,9 +260,9 @@ def test_infer_matches_oracle(oracle_mod):
             continue
         patch = feat[k, :200]
         rc = patch[25 * 7 + 12]
-        het = np.max(np.abs(patch[150:] - rc))
+        het = max(np.max(np.abs(patch[150:] - rc)), abs(rhohat[k] - rc))
         margin_rho = min(abs(patch.min() - 0.005), abs(patch.max() - 1.85), abs(het - 0.3))
-        margin_band = np.min(np.minimum(np.abs(val[k] - band_lo), np.abs(val[k] - band_hi)) / std)
+        margin_band = np.min(np.minimum(np.abs(z[k] - zlo), np.abs(z[k] - zhi)) / std)
         if margin_rho < 1e-4 or margin_band < 1e-2:
             continue                      # decided too close to a threshold to compare
         fb = (patch.min() < 0.005 or patch.max() > 1.85 or het > 0.3
@@ -263,8 +270,8 @@ def test_infer_matches_oracle(oracle_mod):
         assert rows[k, 6] == float(fb), k
         n_fb += int(fb)
         if not fb:
-            got = np.concatenate([rows[k, :4] / LOG2E, rows[k, 4:6]])
-            want = np.concatenate([val[k, :4], np.maximum(val[k, 4:6], 0.0)])
+            got = np.concatenate([np.log(rows[k, :4] / LOG2E), rows[k, 4:6]])
+            want = np.concatenate([z[k, :4], np.maximum(z[k, 4:6], 0.0)])
             assert np.all(np.abs((got - want) / std) < 5e-3), (k, got, want)
             n_checked += 1
     assert n_checked > 20 and n_fb > 20, (n_checked, n_fb)
@@ -275,8 +282,8 @@ def test_forward_surrogate_matches_oracle(oracle_mod, het):
     plan = _hetero_plan(4)
     geo = geometry(plan, 1)
     o = oracle_mod.Oracle(plan)
-    mean = np.array([2.0, 2.0, 0.7, 0.7, 0.6, 0.3], np.float32)
-    std = np.array([0.3, 0.3, 0.1, 0.1, 0.05, 0.05], np.float32)
+    mean = np.array([np.log(2.0), np.log(2.0), np.log(0.7), np.log(0.7), 0.6, 0.3], np.float32)
+    std = np.array([0.3, 0.3, 0.2, 0.2, 0.05, 0.05], np.float32)
     mlp = _trained_like(31, mean, std)
     mlp.set_guard(-1.0, 3.0, het)
     f = torch.as_tensor(plan.fluence, device="cuda")
@@ -298,3 +305,32 @@ def test_forward_surrogate_matches_oracle(oracle_mod, het):
         assert np.allclose(d, ref, rtol=1e-6, atol=1e-7 * np.abs(ref).max())
     else:
         assert 0.0 < P[:, :, 6].mean() < 1.0
+
+
+def test_trained_surrogate_gain_and_guard():
+    """The gain test.  A network trained by the library's own kernels on 60
+    random heads (config-5 geometry) carries the 3D correction: on a head it
+    has not seen, its dose error against the density-corrected method is far
+    below the conventional method's (no correction).  With the guard
+    calibrated on two other held-out heads, the error is within 1% of the
+    maximum dose while the network still serves a share of the rows."""
+    from paper_1103_1164_amd import Mlp
+    from paper_1103_1164_amd import surrogate as SU
+    say("surrogate: data set")
+    data = SU.build_dataset((S.plan_c5(s) for s in list(S.C5_TRAIN_SEEDS)[:60]), 5000, seed=1)
+    mlp = Mlp.initial(0)
+    say("surrogate: training")
+    hist = SU.fit(mlp, data, epochs=30)
+    assert hist[-1] < 0.05 * hist[0], hist
+    test = S.plan_c5(2002)
+    mlp.set_guard()                          # open: every valid row uses the network
+    open_ = SU.evaluate(mlp, test)
+    say(f"surrogate: open guard {open_}")
+    assert open_["err_surrogate"] < 0.5 * open_["err_plain"], open_
+    cal = SU.calibrate(mlp, [S.plan_c5(2000), S.plan_c5(2001)], data)
+    say(f"surrogate: guard het_max {cal['het_max']}")
+    assert cal["met"] and cal["het_max"] >= 0.0, cal["table"]
+    rep = SU.evaluate(mlp, test)
+    say(f"surrogate: calibrated {rep}")
+    assert rep["err_surrogate"] <= 0.01, rep
+    assert rep["served_fraction"] > 0.2 * open_["served_fraction"], (rep, open_)
