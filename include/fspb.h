@@ -218,8 +218,9 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream);
 /* ---- forward-kernel tiling and autotuning -------------------------------
  * The forward kernel assigns one 64-voxel brick to each wavefront.  Brick
  * shapes (voxels along x, y, z) are listed by fspb_tile_shapes; a tile
- * configuration is a shape index and 1, 2 or 4 waves per workgroup.  Results
- * do not depend on the configuration (each voxel sums its pairs in the same
+ * configuration is a shape index and 1, 2 or 4 waves per workgroup (a new
+ * handle starts with shape 1, 8 x 4 x 2 voxels, and 2 waves).  Results do
+ * not depend on the configuration (each voxel sums its pairs in the same
  * order). */
 typedef struct {
     int shape;            /* shape index */

@@ -53,8 +53,8 @@ struct DoseArgs {
 // shapes) and waves per workgroup.
 constexpr int kNumShapes = 4;
 struct TileCfg {
-    int shape = 0;
-    int waves_per_block = 4;
+    int shape = 1;            // 8 x 4 x 2 bricks (the autotuner's choice on the 2.5 mm heads)
+    int waves_per_block = 2;
 };
 long brick_count(const PlanConst& P, int shape);
 void shape_dims(int shape, int d[3]);
