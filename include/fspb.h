@@ -219,7 +219,7 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream);
  * The forward kernel assigns one 64-voxel brick to each wavefront.  Brick
  * shapes (voxels along x, y, z) are listed by fspb_tile_shapes; a tile
  * configuration is a shape index and 1, 2 or 4 waves per workgroup (a new
- * handle starts with shape 1, 8 x 4 x 2 voxels, and 2 waves).  Results do
+ * handle starts with shape 0, 4 x 4 x 4 voxels, and 4 waves).  Results do
  * not depend on the configuration (each voxel sums its pairs in the same
  * order). */
 typedef struct {
@@ -234,7 +234,7 @@ typedef struct {
 int fspb_tile_shapes(int* dims, int max_shapes);
 
 /* Selects the tile configuration of a handle (recomputes its brick schedule
- * when the shape changes; synchronises the stream then). */
+ * on the stream when the shape changes). */
 int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream);
 int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block);
 

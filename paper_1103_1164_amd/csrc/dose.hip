@@ -43,7 +43,8 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // Forward pass over one brick, three modes sharing the candidate search:
 //   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
 //   kCount  number of evaluated pairs per voxel
-//   kCost   number of candidate beamlets per brick (scheduling estimate)
+//   kCost   number of beamlets in the brick's candidate rectangles
+//           (scheduling estimate)
 //   kSurr   the dose with the learned surrogate's parameters: per (voxel,
 //           beam) row prm[2 (b n_vox + v) + 0..1] = ((u1x, u1y, u2x, u2y)
 //           log2 e, (w1, w2, fallback, 0)); a row whose fallback flag is set
@@ -141,6 +142,12 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
         const int first = uniform(B.first), nbl_x = uniform(B.nbx);
         const int nm = m_hi - m_lo + 1;
         const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
+        if (MODE == kCost) {
+            // scheduling estimate: the size of the candidate rectangle (the
+            // sphere filter below is left out; it only sharpens the count)
+            cost += total;
+            continue;
+        }
         float accb = 0.0f;
         for (int base = 0; base < total; base += kWave) {
             // 64 candidates at once: one per lane, tested against the brick's
@@ -163,10 +170,6 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
             }
             const unsigned long long mask = __ballot(pass);
             const int ncand = __popcll(mask);
-            if (MODE == kCost) {
-                cost += ncand;
-                continue;
-            }
             if (ncand == 0) continue;
             // compact: the r-th passing candidate moves to lane r
             const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -273,6 +276,9 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                                                     float* __restrict__ grad) {
     __shared__ int s_off[256];
     __shared__ int s_lo[256];
+    __shared__ int s_vbase[256];     // voxel index of the row's first voxel
+    __shared__ float s_qy[256];      // the row's voxel-centre y and z (relative to P0)
+    __shared__ float s_qz[256];
     __shared__ int s_wsum[4];
     __shared__ float s_red[4];
     const PlanConst& P = a.P;
@@ -293,6 +299,12 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
         const double A = a1 * a1 + a2 * a2;
         const double R2s = (double)P.R2 * (1.0 + 1e-4);
         const double t_slack = 1e-3;
+        // the interval bounds are padded by a voxel, so reciprocals instead
+        // of divisions cannot lose a voxel the exact pair test would accept
+        const double inv2A = A < 1e-20 ? 0.0 : 0.5 / A;
+        const double inv_a3 = a3 != 0.0 ? 1.0 / a3 : 0.0;
+        const FSPB_GLOBAL float4* __restrict__ facs = as_global(a.fac);
+        const FSPB_GLOBAL float* __restrict__ wv = as_global(w);
         const int n_rows = P.ny * P.nz;
         for (int r0 = 0; r0 < n_rows; r0 += 256) {
             const int row = r0 + tid;
@@ -301,6 +313,9 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                 const int j = row % P.ny, k = row / P.ny;
                 float qx, qy, qz;
                 voxel_q(P, 0, j, k, qx, qy, qz);
+                s_vbase[tid] = row * P.nx;
+                s_qy[tid] = qy;
+                s_qz[tid] = qz;
                 double xp0 = (double)qx * d.ex[0] + (double)qy * d.ex[1] + (double)qz * d.ex[2] + d.c_x;
                 double yp0 = (double)qx * d.ey[0] + (double)qy * d.ey[1] + (double)qz * d.ey[2] + d.c_y;
                 double t0 = (double)qx * d.d[0] + (double)qy * d.d[1] + (double)qz * d.d[2] + d.c_t;
@@ -316,12 +331,12 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                         empty = true;
                     } else {
                         double sq = sqrt(disc);
-                        flo = fmax(flo, (-B - sq) / (2.0 * A) - 1.0);
-                        fhi = fmin(fhi, (-B + sq) / (2.0 * A) + 1.0);
+                        flo = fmax(flo, (-B - sq) * inv2A - 1.0);
+                        fhi = fmin(fhi, (-B + sq) * inv2A + 1.0);
                     }
                 }
-                if (a3 > 0.0) flo = fmax(flo, (-t_slack - t0) / a3 - 1.0);
-                else if (a3 < 0.0) fhi = fmin(fhi, (-t_slack - t0) / a3 + 1.0);
+                if (a3 > 0.0) flo = fmax(flo, (-t_slack - t0) * inv_a3 - 1.0);
+                else if (a3 < 0.0) fhi = fmin(fhi, (-t_slack - t0) * inv_a3 + 1.0);
                 else if (t0 < -t_slack) empty = true;
                 if (!empty && flo <= fhi) {
                     int ilo = max((int)floor(fmax(flo, -1.0)), 0);
@@ -357,19 +372,18 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                 }
                 while (rlo < 255 && s_off[rlo + 1] <= e) ++rlo;
                 if (e >= total) continue;
-                const int rr = r0 + rlo;
                 const int i = s_lo[rlo] + (e - s_off[rlo]);
-                const int j = rr % P.ny, k = rr / P.ny;
-                float qx, qy, qz;
-                voxel_q(P, i, j, k, qx, qy, qz);
+                // the voxel centre as voxel_q computes it (same pair decisions
+                // as the forward kernel)
+                const float qx = fmaf((float)i, P.dx, P.qx0), qy = s_qy[rlo], qz = s_qz[rlo];
                 float t, xp, yp;
                 if (pair_coords(d, P, qx, qy, qz, t, xp, yp)) {
-                    const long v = ((long)k * P.ny + j) * P.nx + i;
+                    const unsigned v = (unsigned)(s_vbase[rlo] + i);
                     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-                    if (DC) fac = a.fac[v];
-                    acc = fmaf(w[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
-                                                   as_global(a.dtab), as_global(a.atab),
-                                                   as_global(a.tT), as_global(a.tTW)),
+                    if (DC) fac = facs[v];
+                    acc = fmaf(wv[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                                    as_global(a.dtab), as_global(a.atab),
+                                                    as_global(a.tT), as_global(a.tTW)),
                                acc);
                 }
             }
@@ -380,6 +394,45 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
     if (lane == 0) s_red[wid] = acc;
     __syncthreads();
     if (tid == 0) grad[ib] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Brick schedule: bricks in decreasing order of estimated work (candidate
+// beamlets), by a counting sort in one workgroup.  Bricks of equal cost may
+// come out in any order: each voxel's sum does not depend on the schedule.
+constexpr int kOrderBins = 4096;
+
+__global__ __launch_bounds__(1024) void order_bricks(const int* __restrict__ cost, int n,
+                                                     int* __restrict__ order) {
+    __shared__ int hist[kOrderBins];
+    __shared__ int s_wsum[16];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    for (int b = tid; b < kOrderBins; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    // bin 0 holds the most expensive bricks
+    auto bin = [&](int q) { return kOrderBins - 1 - min(max(cost[q], 0), kOrderBins - 1); };
+    for (int q = tid; q < n; q += blockDim.x) atomicAdd(&hist[bin(q)], 1);
+    __syncthreads();
+    // exclusive scan of the 4096 bins, 4 consecutive bins a thread
+    const int b0 = 4 * tid;
+    const int c0 = hist[b0], c1 = hist[b0 + 1], c2 = hist[b0 + 2], c3 = hist[b0 + 3];
+    const int local = c0 + c1 + c2 + c3;
+    const int incl = wave_incl_scan_int(local, lane);
+    if (lane == kWave - 1) s_wsum[wid] = incl;
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wid; ++w) off += s_wsum[w];
+    const int ex = off + incl - local;
+    hist[b0] = ex;
+    hist[b0 + 1] = ex + c0;
+    hist[b0 + 2] = ex + c0 + c1;
+    hist[b0 + 3] = ex + c0 + c1 + c2;
+    __syncthreads();
+    for (int q = tid; q < n; q += blockDim.x) order[atomicAdd(&hist[bin(q)], 1)] = q;
+}
+
+void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s) {
+    hipLaunchKernelGGL(order_bricks, dim3(1), dim3(1024), 0, s, cost, (int)n, order);
 }
 
 // ---------------------------------------------------------------------------

@@ -141,6 +141,38 @@ int check_table(const fspb_table1d& t, const char* name) {
 
 }  // namespace
 
+// Packed commissioned tables (water, A and density tables in the layouts the
+// kernels read), shared by every geometry built from bitwise-identical tables
+// on a device.  Sets stay while a geometry uses them; unused ones are kept
+// (up to kMaxIdleTableSets per process) for the next plan, and
+// fspb_release_cached_memory frees them.
+struct TableSet {
+    int device = 0;
+    std::vector<uint32_t> key;   // every table parameter and value, bitwise
+    float4* dtab = nullptr;
+    float4* atab = nullptr;
+    float* denstab = nullptr;
+    DensTabs dens{};
+    int refs = 0;
+    unsigned long long last_use = 0;
+};
+
+namespace {
+constexpr int kMaxIdleTableSets = 8;
+std::mutex g_tables_mu;
+unsigned long long g_tables_clock = 0;
+std::vector<TableSet*>& table_sets() {
+    static auto* v = new std::vector<TableSet*>();   // never destroyed
+    return *v;
+}
+void free_table_set(TableSet* t) {
+    (void)hipFree(t->dtab);
+    (void)hipFree(t->atab);
+    (void)hipFree(t->denstab);
+    delete t;
+}
+}  // namespace
+
 struct fspb_geometry {
     int device = 0;
     PlanConst P{};
@@ -166,10 +198,12 @@ struct fspb_geometry {
     float* w3 = nullptr;
     int* counts = nullptr;
     int* order = nullptr;      // bricks in decreasing order of estimated work
+    int* cost = nullptr;       // estimated work per brick (candidate beamlets)
     float* tmp0 = nullptr;     // smoothing intermediates (alias the depth tables when they fit)
     float* tmp1 = nullptr;
     TileCfg tile;
-    std::vector<int> h_cost;   // estimated work per brick for the current tile shape
+    std::vector<int> h_cost;   // host copy of cost (fetched when a batch needs it)
+    bool h_cost_valid = false;
     TraceGrid tg{};
     TraceParams tp{};
     hipDeviceProp_t prop{};
@@ -207,9 +241,16 @@ struct fspb_geometry {
         return a;
     }
 
+    TableSet* tabs = nullptr;      // shared commissioned tables (not owned)
+
     void release() {
         for (auto& b : blocks) pool_free(device, b.first, b.second);
         blocks.clear();
+        if (tabs) {
+            std::lock_guard<std::mutex> lk(g_tables_mu);
+            --tabs->refs;
+            tabs = nullptr;
+        }
     }
 
     int fetch_host() const;
@@ -344,30 +385,137 @@ const char* fspb_error_string(int code) {
 const char* fspb_last_error(void) { return g_last_error.c_str(); }
 
 // Brick schedule for the handle's tile shape: estimated work per brick
-// (candidate beamlets), longest first (counting sort on the integer cost,
-// stable in brick index order).  Synchronises the stream.
+// (candidate beamlets), longest first, built on the device (asynchronous).
 static int build_order(fspb_geometry* G, hipStream_t s) {
     const long nb = brick_count(G->P, G->tile.shape);
-    launch_brick_cost(G->args(), G->tile, G->order, s);
+    launch_brick_cost(G->args(), G->tile, G->cost, s);
+    launch_order_bricks(G->cost, nb, G->order, s);
     HIP_TRY(hipGetLastError());
-    std::vector<int>& cost = G->h_cost;
-    cost.assign(nb, 0);
-    std::vector<int> idx(nb);
-    HIP_TRY(hipMemcpyAsync(cost.data(), G->order, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+    G->h_cost_valid = false;
+    return FSPB_OK;
+}
+
+// Host copy of the brick costs for the batch scheduler (synchronises s).
+static int fetch_cost(fspb_geometry* G, hipStream_t s) {
+    if (G->h_cost_valid) return FSPB_OK;
+    const long nb = brick_count(G->P, G->tile.shape);
+    G->h_cost.assign(nb, 0);
+    HIP_TRY(hipMemcpyAsync(G->h_cost.data(), G->cost, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int cmax = 0;
-    for (long q = 0; q < nb; ++q) cmax = std::max(cmax, cost[q]);
-    std::vector<int> hist((size_t)cmax + 1, 0);
-    for (long q = 0; q < nb; ++q) ++hist[std::max(cost[q], 0)];
-    int acc = 0;
-    for (int c = cmax; c >= 0; --c) {
-        int h = hist[c];
-        hist[c] = acc;
-        acc += h;
+    G->h_cost_valid = true;
+    return FSPB_OK;
+}
+
+// Packs the commissioned tables into the kernels' layouts (once per
+// distinct set and device):
+//   dtab[3j..3j+2]: (u1x, u1y, u2x, u2y) log2 e at depth sample j, their
+//                   slopes to sample j+1, and (w1, w2, w1', w2')
+//   atab[j a_cols + r]: (A[r][j], A[r+1][j], A[r][j+1]-A[r][j], A[r+1][j+1]-A[r+1][j])
+//   denstab: the six density tables back to back (offsets in dens)
+static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** out) {
+    std::vector<uint32_t> key;
+    auto put_f = [&](float v) {
+        uint32_t u;
+        memcpy(&u, &v, 4);
+        key.push_back(u);
+    };
+    auto put_tab = [&](const fspb_table1d& tb, size_t count) {
+        key.push_back((uint32_t)tb.n);
+        put_f(tb.start);
+        put_f(tb.step);
+        const size_t k0 = key.size();
+        key.resize(k0 + count);
+        memcpy(key.data() + k0, tb.v, sizeof(float) * count);
+    };
+    key.push_back((uint32_t)t->n_theta);
+    put_f(t->theta_step);
+    put_tab(t->A, (size_t)t->n_theta * t->A.n);
+    const fspb_table1d* all[12] = {&t->u1x, &t->u1y, &t->u2x, &t->u2y, &t->w1, &t->w2,
+                                   &t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
+    for (const fspb_table1d* tb : all) put_tab(*tb, (size_t)tb->n);
+
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto& sets = table_sets();
+    for (TableSet* ts : sets)
+        if (ts->device == dev && ts->key == key) {
+            ++ts->refs;
+            ts->last_use = ++g_tables_clock;
+            *out = ts;
+            return FSPB_OK;
+        }
+
+    const int dn = t->u1x.n;
+    std::vector<float4> dtab(3 * (size_t)dn);
+    const fspb_table1d* U[4] = {&t->u1x, &t->u1y, &t->u2x, &t->u2y};
+    auto at = [](const fspb_table1d& tb, int i) { return (double)tb.v[std::min(i, tb.n - 1)]; };
+    for (int j = 0; j < dn; ++j) {
+        float u[4], du[4];
+        for (int q = 0; q < 4; ++q) {
+            u[q] = (float)(at(*U[q], j) * 1.4426950408889634);
+            du[q] = (float)((at(*U[q], j + 1) - at(*U[q], j)) * 1.4426950408889634);
+        }
+        dtab[3 * j + 0] = make_float4(u[0], u[1], u[2], u[3]);
+        dtab[3 * j + 1] = make_float4(du[0], du[1], du[2], du[3]);
+        dtab[3 * j + 2] = make_float4(t->w1.v[j], t->w2.v[j], (float)(at(t->w1, j + 1) - at(t->w1, j)),
+                                      (float)(at(t->w2, j + 1) - at(t->w2, j)));
     }
-    for (long q = 0; q < nb; ++q) idx[hist[std::max(cost[q], 0)]++] = (int)q;
-    HIP_TRY(hipMemcpyAsync(G->order, idx.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const int an = t->A.n, nth = t->n_theta, ac = a_cols;
+    std::vector<float4> atab((size_t)an * ac);
+    auto A = [&](int r, int j) {
+        return (double)t->A.v[(size_t)std::min(r, nth - 1) * an + std::min(j, an - 1)];
+    };
+    for (int j = 0; j < an; ++j)
+        for (int r = 0; r < ac; ++r)
+            atab[(size_t)j * ac + r] = make_float4((float)A(r, j), (float)A(r + 1, j),
+                                                   (float)(A(r, j + 1) - A(r, j)),
+                                                   (float)(A(r + 1, j + 1) - A(r + 1, j)));
+    TableSet* ts = new (std::nothrow) TableSet();
+    if (!ts) return fail(FSPB_E_NOMEM, "host allocation failed");
+    ts->device = dev;
+    const fspb_table1d* D[6] = {&t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
+    DTab* DT[6] = {&ts->dens.fu1, &ts->dens.fu2, &ts->dens.fw1, &ts->dens.fw2, &ts->dens.b1,
+                   &ts->dens.b2};
+    std::vector<float> dens;
+    for (int q = 0; q < 6; ++q) {
+        DT[q]->start = D[q]->start;
+        DT[q]->step = D[q]->n > 1 ? D[q]->step : 1.0f;
+        DT[q]->inv_step = D[q]->n > 1 ? (float)(1.0 / D[q]->step) : 0.0f;
+        DT[q]->n = D[q]->n;
+        DT[q]->off = (int)dens.size();
+        dens.insert(dens.end(), D[q]->v, D[q]->v + D[q]->n);
+    }
+    hipError_t e = hipMalloc((void**)&ts->dtab, sizeof(float4) * dtab.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&ts->atab, sizeof(float4) * atab.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&ts->denstab, sizeof(float) * dens.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(ts->dtab, dtab.data(), sizeof(float4) * dtab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ts->atab, atab.data(), sizeof(float4) * atab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ts->denstab, dens.data(), sizeof(float) * dens.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_table_set(ts);
+        return fail(e == hipErrorOutOfMemory ? FSPB_E_NOMEM : FSPB_E_HIP,
+                    "uploading the commissioned tables failed: %s", hipGetErrorString(e));
+    }
+    ts->key = std::move(key);
+    ts->refs = 1;
+    ts->last_use = ++g_tables_clock;
+    // keep at most kMaxIdleTableSets unused sets: drop the least recently used
+    int idle = 0;
+    for (TableSet* x : sets) idle += x->refs == 0;
+    while (idle > kMaxIdleTableSets) {
+        auto it = std::min_element(sets.begin(), sets.end(), [](TableSet* a, TableSet* b) {
+            if ((a->refs == 0) != (b->refs == 0)) return a->refs == 0;
+            return a->last_use < b->last_use;
+        });
+        free_table_set(*it);
+        sets.erase(it);
+        --idle;
+    }
+    sets.push_back(ts);
+    *out = ts;
     return FSPB_OK;
 }
 
@@ -406,8 +554,10 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     double L[3] = {nx * (double)ct->dx, ny * (double)ct->dy, nz * (double)ct->dz};
     double diag = sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     G->k_stride = (int)floor(diag / step) + 3;
-    if ((long long)G->k_stride * nbl > (1LL << 31) - 1)
-        return fail(FSPB_E_ARG, "depth tables of %d x %d samples exceed 2^31-1", nbl, G->k_stride);
+    // the pair kernels address the depth tables (32-byte records) with
+    // 32-bit byte offsets
+    if ((long long)G->k_stride * nbl > (1LL << 27) - 1)
+        return fail(FSPB_E_ARG, "depth tables of %d x %d samples exceed 2^27-1", nbl, G->k_stride);
 
     PlanConst& P = G->P;
     P.nx = nx;
@@ -433,43 +583,13 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     long max_bricks = 0;
     for (int sh = 0; sh < kNumShapes; ++sh) max_bricks = std::max(max_bricks, brick_count(P, sh));
 
-    // ---- host-side table packing -------------------------------------------
-    const int dn = t->u1x.n;
-    std::vector<float4> dtab(3 * (size_t)dn);
-    const fspb_table1d* U[4] = {&t->u1x, &t->u1y, &t->u2x, &t->u2y};
-    auto at = [](const fspb_table1d& tb, int i) { return (double)tb.v[std::min(i, tb.n - 1)]; };
-    for (int j = 0; j < dn; ++j) {
-        float u[4], du[4];
-        for (int q = 0; q < 4; ++q) {
-            u[q] = (float)(at(*U[q], j) * 1.4426950408889634);
-            du[q] = (float)((at(*U[q], j + 1) - at(*U[q], j)) * 1.4426950408889634);
-        }
-        dtab[3 * j + 0] = make_float4(u[0], u[1], u[2], u[3]);
-        dtab[3 * j + 1] = make_float4(du[0], du[1], du[2], du[3]);
-        dtab[3 * j + 2] = make_float4(t->w1.v[j], t->w2.v[j], (float)(at(t->w1, j + 1) - at(t->w1, j)),
-                                      (float)(at(t->w2, j + 1) - at(t->w2, j)));
-    }
-    const int an = t->A.n, nth = t->n_theta, ac = P.a_cols;
-    std::vector<float4> atab((size_t)an * ac);
-    auto A = [&](int r, int j) {
-        return (double)t->A.v[(size_t)std::min(r, nth - 1) * an + std::min(j, an - 1)];
-    };
-    for (int j = 0; j < an; ++j)
-        for (int r = 0; r < ac; ++r)
-            atab[(size_t)j * ac + r] = make_float4((float)A(r, j), (float)A(r + 1, j),
-                                                   (float)(A(r, j + 1) - A(r, j)),
-                                                   (float)(A(r + 1, j + 1) - A(r + 1, j)));
-    const fspb_table1d* D[6] = {&t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
-    DTab* DT[6] = {&G->dens.fu1, &G->dens.fu2, &G->dens.fw1, &G->dens.fw2, &G->dens.b1, &G->dens.b2};
-    std::vector<float> dens;
-    for (int q = 0; q < 6; ++q) {
-        DT[q]->start = D[q]->start;
-        DT[q]->step = D[q]->n > 1 ? D[q]->step : 1.0f;
-        DT[q]->inv_step = D[q]->n > 1 ? (float)(1.0 / D[q]->step) : 0.0f;
-        DT[q]->n = D[q]->n;
-        DT[q]->off = (int)dens.size();
-        dens.insert(dens.end(), D[q]->v, D[q]->v + D[q]->n);
-    }
+    // ---- commissioned tables: packed and uploaded once per distinct set -------
+    int rc;
+    if ((rc = acquire_tables(G->device, t, P.a_cols, &G->tabs)) != FSPB_OK) return rc;
+    G->dtab = G->tabs->dtab;
+    G->atab = G->tabs->atab;
+    G->denstab = G->tabs->denstab;
+    G->dens = G->tabs->dens;
     G->dens.rho_min = o.rho_min;
     G->dens.rho_max = o.rho_max;
 
@@ -536,34 +656,38 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     }
 
     // ---- device buffers ----------------------------------------------------
-    int rc;
 #define ALLOC(ptr, bytes)                                                   \
     if ((rc = G->alloc((void**)&(ptr), (bytes))) != FSPB_OK) return rc;
-    ALLOC(G->beams, sizeof(BeamDesc) * n_beams);
-    ALLOC(G->beam_in, sizeof(BeamIn) * n_beams);
+    // the small per-plan inputs (beam descriptors, setup inputs, smoothing
+    // weights) travel in one block and one copy
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t off_bin = align(sizeof(BeamDesc) * n_beams);
+    const size_t off_w3 = off_bin + align(sizeof(BeamIn) * n_beams);
+    const size_t small_bytes = off_w3 + sizeof(float) * w3.size();
+    std::vector<unsigned char> small(small_bytes, 0);
+    memcpy(small.data(), bd.data(), sizeof(BeamDesc) * n_beams);
+    memcpy(small.data() + off_bin, bin.data(), sizeof(BeamIn) * n_beams);
+    memcpy(small.data() + off_w3, w3.data(), sizeof(float) * w3.size());
+    unsigned char* dsmall = nullptr;
+    ALLOC(dsmall, small_bytes);
+    G->beams = reinterpret_cast<BeamDesc*>(dsmall);
+    G->beam_in = reinterpret_cast<BeamIn*>(dsmall + off_bin);
+    G->w3 = reinterpret_cast<float*>(dsmall + off_w3);
     ALLOC(G->frames, sizeof(Frame64) * nbl);
     ALLOC(G->desc, sizeof(BeamletDesc) * nbl);
     ALLOC(G->tinfo, sizeof(TraceInfo) * nbl);
-    ALLOC(G->dtab, sizeof(float4) * dtab.size());
-    ALLOC(G->atab, sizeof(float4) * atab.size());
-    ALLOC(G->denstab, sizeof(float) * dens.size());
     ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
     ALLOC(G->order, sizeof(int) * max_bricks);
+    ALLOC(G->cost, sizeof(int) * max_bricks);
     if (o.dc_enabled) {
         ALLOC(G->tTW, 2 * sizeof(float4) * (size_t)nbl * G->k_stride);
         ALLOC(G->rhohat, sizeof(float) * nv);
         ALLOC(G->fac, sizeof(float4) * nv);
-        ALLOC(G->w3, sizeof(float) * w3.size());
     }
-    HIP_TRY(hipMemcpyAsync(G->beams, bd.data(), sizeof(BeamDesc) * n_beams, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(G->beam_in, bin.data(), sizeof(BeamIn) * n_beams, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(G->dtab, dtab.data(), sizeof(float4) * dtab.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(G->atab, atab.data(), sizeof(float4) * atab.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(G->denstab, dens.data(), sizeof(float) * dens.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dsmall, small.data(), small_bytes, hipMemcpyHostToDevice, s));
 
     // ---- kernels 1-4 ---------------------------------------------------------
     if (o.dc_enabled) {
-        HIP_TRY(hipMemcpyAsync(G->w3, w3.data(), sizeof(float) * w3.size(), hipMemcpyHostToDevice, s));
         // the two intermediate passes use the (not yet written) depth-table
         // buffer as scratch when it is large enough, else two pool blocks
         const size_t tt_bytes = sizeof(float2) * (size_t)nbl * G->k_stride;
@@ -605,7 +729,8 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
                  G->tinfo, s);
     HIP_TRY(hipGetLastError());
 
-    return build_order(G, s);
+    if ((rc = build_order(G, s)) != FSPB_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s));   // the caller may free ct->density now
     return FSPB_OK;
 }
 
@@ -769,6 +894,18 @@ void fspb_destroy(fspb_geometry* g) {
 }
 
 int fspb_release_cached_memory(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_tables_mu);
+        auto& sets = table_sets();
+        for (auto it = sets.begin(); it != sets.end();) {
+            if ((*it)->refs == 0) {
+                free_table_set(*it);
+                it = sets.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
     std::vector<void*> drop;
     {
         std::lock_guard<std::mutex> lk(pool().mu);
@@ -992,6 +1129,8 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
             if (rc) return bail(rc);
         }
         const long nb = brick_count(g->P, shape);
+        int rc = fetch_cost(g, (hipStream_t)stream);
+        if (rc) return bail(rc);
         for (long q = 0; q < nb; ++q) items.push_back({p, (int)q, g->h_cost[q] + 4});
     }
     if (policy == FSPB_SCHEDULE_THROUGHPUT) {

@@ -53,8 +53,8 @@ struct DoseArgs {
 // shapes) and waves per workgroup.
 constexpr int kNumShapes = 4;
 struct TileCfg {
-    int shape = 1;            // 8 x 4 x 2 bricks (the autotuner's choice on the 2.5 mm heads)
-    int waves_per_block = 2;
+    int shape = 0;            // 4 x 4 x 4 bricks
+    int waves_per_block = 4;
 };
 long brick_count(const PlanConst& P, int shape);
 void shape_dims(int shape, int d[3]);
@@ -68,6 +68,8 @@ void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                   int* counts, hipStream_t s);
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s);
+// order[0..n) = bricks by decreasing cost[brick] (one workgroup, no host round trip)
+void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s);
 // Per-plan fluence and dose pointers of a batch, passed by value as a kernel
 // argument (so a captured graph keeps them).
 constexpr int kMaxBatchPlans = 64;

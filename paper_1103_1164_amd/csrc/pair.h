@@ -40,6 +40,15 @@ __device__ __forceinline__ const FSPB_CONST T* as_const(const T* p) {
     return (const FSPB_CONST T*)p;
 }
 
+// Element at a 32-bit byte offset from a global base: the load can use the
+// scalar-base + 32-bit vector-offset form, with no 64-bit address arithmetic.
+// Every table a plan owns is below 4 GiB (checked when the plan is created).
+template <class T>
+__device__ __forceinline__ T load_at(const FSPB_GLOBAL T* base, unsigned byte_off) {
+    return *reinterpret_cast<const FSPB_GLOBAL T*>(reinterpret_cast<const FSPB_GLOBAL char*>(base) +
+                                                   byte_off);
+}
+
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -110,9 +119,9 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     // end value.
     // water parameters at geometric depth t
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
-    const int jd = (int)cd;
+    const unsigned od = 48u * (unsigned)cd;             // 3 float4 per depth sample
     const float fd = fract(cd);
-    const float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
+    const float4 u0 = load_at(dtab, od), us = load_at(dtab, od + 16u), wv = load_at(dtab, od + 32u);
 
     // per-beamlet radiological depth and weight drift at depth t (Section 2.2);
     // t >= 0 and voxel centres never reach the last table interval
@@ -121,21 +130,22 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     const float f = fract(c);
     float teq, W1 = 0.0f, W2 = 0.0f;
     if (DC) {
-        const float4 r0 = tTW[2 * (b.tab_off + j)];
-        const float2 r1 = *reinterpret_cast<const FSPB_GLOBAL float2*>(&tTW[2 * (b.tab_off + j) + 1]);
+        const unsigned ot = 32u * (unsigned)(b.tab_off + j);   // one 32-byte record
+        const float4 r0 = load_at(tTW, ot);
+        const float2 r1 = load_at(reinterpret_cast<const FSPB_GLOBAL float2*>(tTW), ot + 16u);
         teq = fmaf(f, r0.y, r0.x);
         W1 = fmaf(f, r0.w, r0.z);
         W2 = fmaf(f, r1.y, r1.x);
     } else {
-        const float2 te = tT[b.tab_off + j];
+        const float2 te = load_at(tT, 8u * (unsigned)(b.tab_off + j));
         teq = fmaf(f, te.y, te.x);
     }
 
     // A(t_eq, theta): bilinear, theta column fixed per beamlet
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
-    const int ja = (int)ca;
     const float fa = fract(ca);
-    const float4 ae = atab[ja * P.a_cols + b.th_col];
+    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
+                                        16u * (unsigned)b.th_col);
 
     float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
     float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
@@ -209,12 +219,12 @@ __device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, fl
     const float c = t * P.inv_d;
     const int j = max(min((int)c, b.K - 2), 0);
     const float f = fract(c);
-    const float4 r0 = tTW[2 * (b.tab_off + j)];
+    const float4 r0 = load_at(tTW, 32u * (unsigned)(b.tab_off + j));
     const float teq = fmaf(f, r0.y, r0.x);
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
-    const int ja = (int)ca;
     const float fa = fract(ca);
-    const float4 ae = atab[ja * P.a_cols + b.th_col];
+    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
+                                        16u * (unsigned)b.th_col);
     float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
     float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
     float ax = fabsf(x), ay = fabsf(y);
