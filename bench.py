@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training and timing the learned surrogate (config 5)")
+    ap.add_argument("--no-paper-cases", action="store_true",
+                    help="skip the paper-shaped head-and-neck and lung plans")
     ap.add_argument("--surrogate-plans", type=int, default=200,
                     help="training heads for the surrogate (config 5 uses 200)")
     ap.add_argument("--forward-only", type=int, default=0,
@@ -168,6 +170,9 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(plan, a.cpu_sample)
+    paper = None
+    if not a.no_paper_cases:
+        paper = paper_cases(time_loop)
     surr = None
     if not a.no_surrogate:
         surr = surrogate_c5(plan, geo, flu, pairs_fwd, a.surrogate_plans, time_loop)
@@ -212,6 +217,7 @@ def main():
         "cpu_baseline": cpu,
         "batch_c4": batch,
         "surrogate_c5": surr,
+        "paper_cases": paper,
         "paper_context": "Tesla C1060, real H&N/lung IMRT plans (Table 4): median T_gpu "
                          "0.37 s DC (0.33 s plain), T_tr 0.20 s; different hardware and workload",
     }
@@ -223,6 +229,61 @@ def _opts(o, dc):
     o = copy.copy(o)
     o.dc_enabled = int(dc)
     return o
+
+
+def paper_cases(time_loop, n=10):
+    """Plans shaped like the paper's largest head-and-neck (H5) and a lung
+    case (L2), Table 1 scales: per-plan time (geometry + DC forward, the
+    paper's T_gpu) and forward rates, with the paper's own times (Tesla
+    C1060, real plans) beside them as context."""
+    import numpy as np
+    import torch
+
+    import fspb_synth as S
+    from paper_1103_1164_amd import Geometry
+
+    paper_tgpu = {"paper_h5_like": (1.31, 1.10), "paper_l2_like": (0.40, 0.36)}
+    out = {}
+    for mk in (S.plan_paper_h5, S.plan_paper_l2):
+        plan = mk()
+        dens = torch.as_tensor(plan.density, device="cuda")
+        flu = torch.as_tensor(plan.fluence, device="cuda")
+        dose = torch.empty(plan.shape, device="cuda")
+
+        def make(dc=1):
+            return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables,
+                            _opts(plan.options, dc))
+
+        for _ in range(2):
+            g = make()
+            g.forward(flu, out=dose)
+            g.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            g = make()
+            g.forward(flu, out=dose)
+            g.close()
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / n
+        geo = make()
+        pairs = geo.count_pairs(flu)
+        fwd_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
+        geo.set_dc(False)
+        plain_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
+        geo.close()
+        dc_s, plain_s = paper_tgpu[plan.name]
+        out[plan.name] = {
+            "voxels": plan.n_vox, "beamlets": plan.n_beamlets, "beams": len(plan.beams),
+            "spacing_cm": list(plan.spacing), "beamlet_cm": [plan.beams[0].wx, plan.beams[0].wy],
+            "pairs_forward": int(pairs), "ms_per_plan": round(step_ms, 4),
+            "forward_ms": round(fwd_ms, 4), "plain_forward_ms": round(plain_ms, 4),
+            "forward_evals_per_s": pairs / (fwd_ms * 1e-3),
+            "paper_tgpu_s_dc": dc_s, "paper_tgpu_s_plain": plain_s,
+            "note": "paper times: Tesla C1060 on the real plan of that name (Table 4); "
+                    "this plan only matches its shape (Table 1)",
+        }
+    return out
 
 
 def surrogate_c5(plan, geo, flu, pairs_fwd, n_plans, time_loop):

@@ -20,12 +20,13 @@ from .plan import Beam, Options, Plan, grid_origin_centered
 from .phantoms import (
     plan_c1, plan_c2, plan_c3, plans_c4, plan_c4, c5_phantom, plan_c5, plan_small,
     c2_density, c3_density, slab_density, c3_objective, C3_ISO, C5_TRAIN_SEEDS, C5_HELDOUT_SEEDS,
+    plan_paper_h5, plan_paper_l2, PAPER_SPACING,
 )
 
 __all__ = [
     "Tables", "Table1D", "make_tables", "constant_tables",
     "Beam", "Options", "Plan", "grid_origin_centered",
     "plan_c1", "plan_c2", "plan_c3", "plans_c4", "plan_c4", "c5_phantom", "plan_c5",
-    "C5_TRAIN_SEEDS", "C5_HELDOUT_SEEDS",
+    "C5_TRAIN_SEEDS", "C5_HELDOUT_SEEDS", "plan_paper_h5", "plan_paper_l2", "PAPER_SPACING",
     "plan_small", "c2_density", "c3_density", "slab_density", "c3_objective", "C3_ISO",
 ]

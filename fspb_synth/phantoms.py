@@ -208,6 +208,42 @@ def plan_c5(seed: int, tables: Tables | None = None) -> Plan:
     return p
 
 
+# Paper-shaped plans (Table 1 scales): CT down-sampled to 0.4 x 0.4 x 0.25 cm,
+# beamlets of 0.2 x 0.5 cm (0.2 along the beam's x axis, the leaf motion).
+PAPER_SPACING = (0.4, 0.4, 0.25)
+
+
+def plan_paper_h5(seed: int = 5, tables: Tables | None = None) -> Plan:
+    """Head-and-neck case shaped like H5: 128 x 128 x 72 voxels, 7
+    non-coplanar beams (couch 0, +-20, +-30, +-15 degrees), 40 x 37 beamlets
+    each (10,360 in all, H5 has 10,369), fluence U[0,1] with 30% zeros."""
+    n = (128, 128, 72)
+    origin = grid_origin_centered(n, PAPER_SPACING)
+    rho = c2_density(seed, n, PAPER_SPACING, semi=(8.0, 10.0, 8.5))
+    rng = np.random.default_rng(seed + 10_000)
+    couch = (0.0, 20.0, -20.0, 30.0, -30.0, 15.0, -15.0)
+    beams = [Beam(gantry=math.radians(51.4 * k), couch=math.radians(couch[k]), nbx=40, nby=37,
+                  wx=0.2, wy=0.5) for k in range(7)]
+    f = _fluence_zeros(rng, sum(b.n_beamlets for b in beams))
+    return Plan("paper_h5_like", rho, PAPER_SPACING, origin, beams, f, tables or make_tables(0),
+                Options())
+
+
+def plan_paper_l2(seed: int = 6, tables: Tables | None = None) -> Plan:
+    """Lung case shaped like L2: 128 x 128 x 103 voxels, 6 coplanar beams at
+    60 degree steps on the right-lung target, 26 x 11 beamlets each (1,716 in
+    all, L2 has 1,720), fluence U[0,1] with 30% zeros."""
+    n = (128, 128, 103)
+    origin = grid_origin_centered(n, PAPER_SPACING)
+    rho = c3_density(seed, n, PAPER_SPACING)
+    rng = np.random.default_rng(seed + 10_000)
+    beams = [Beam(gantry=math.radians(60.0 * k), iso=C3_ISO, nbx=26, nby=11, wx=0.2, wy=0.5)
+             for k in range(6)]
+    f = _fluence_zeros(rng, sum(b.n_beamlets for b in beams))
+    return Plan("paper_l2_like", rho, PAPER_SPACING, origin, beams, f, tables or make_tables(0),
+                Options())
+
+
 def plan_small(n=(24, 20, 16), spacing=(0.25, 0.25, 0.25), density=1.0,
                beams: Sequence[Beam] | None = None, fluence=None,
                tables: Tables | None = None, options: Options | None = None,

@@ -128,17 +128,29 @@ def _sample_voxels(shape, d_gpu, n, seed):
     return np.unique(np.concatenate([rand, hot]))
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3"])
+_FULL = {"c2": S.plan_c2, "c3": S.plan_c3, "paper_h5": S.plan_paper_h5, "paper_l2": S.plan_paper_l2}
+
+
+@pytest.mark.parametrize("cfg", list(_FULL))
 def test_full_size_forward_sampled(oracle_mod, cfg):
-    plan = S.plan_c2() if cfg == "c2" else S.plan_c3()
+    """Configs 2 and 3, and the paper-shaped plans (Table 1 scales: 0.4 x 0.4
+    x 0.25 cm voxels, 0.2 x 0.5 cm beamlets, non-coplanar beams for the
+    head-and-neck case)."""
+    plan = _FULL[cfg]()
     say(f"{cfg}: geometry")
     geo = geometry(plan, 1)
     d_gpu = gpu_dose(geo, plan.fluence)
     info = geo.info()
-    assert info["n_entry_ambiguous"] == 0 and info["n_hit"] == plan.n_beamlets
+    assert info["n_entry_ambiguous"] == 0
     vox = _sample_voxels(plan.shape, d_gpu, 3000, seed=7)
     say(f"{cfg}: oracle at {vox.size} voxels")
     orc = oracle_mod.Oracle(plan)
+    # beamlets that reach the body: all of them in configs 2 and 3; the
+    # paper-shaped head's outer beamlet rows pass beside it
+    hits = sum(orc.trace(i)["hit"] for i in range(plan.n_beamlets))
+    assert info["n_hit"] == hits
+    if cfg in ("c2", "c3"):
+        assert hits == plan.n_beamlets
     d_o, amb, pc = orc.dose(vox=vox)
     # the scale is the oracle maximum over the sample, which includes the
     # hottest GPU voxels
@@ -318,3 +330,19 @@ def test_errors_on_gpu():
     finally:
         del os.environ["FSPB_TEST_FAIL_ALLOC"]
     assert geometry(plan, 1).info()["n_hit"] == 1
+
+
+def test_paper_h5_adjoint_sampled(oracle_mod):
+    """The transpose on the paper-shaped head-and-neck plan, on sampled
+    beamlets of every beam."""
+    plan = S.plan_paper_h5()
+    geo = geometry(plan, 1)
+    rng = np.random.default_rng(8)
+    w = rng.uniform(0.0, 1.0, size=plan.n_vox).astype(np.float32)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    per = plan.beams[0].n_beamlets
+    pick = np.concatenate([b * per + rng.choice(per, size=2, replace=False)
+                           for b in range(len(plan.beams))])
+    say(f"paper_h5 adjoint: oracle on {pick.size} beamlets")
+    g_o, amb = oracle_mod.Oracle(plan).adjoint(w, beamlets=pick)
+    assert_dose_parity(g[pick], g_o, amb, scale=np.abs(g_o).max(), what="paper_h5 adjoint")

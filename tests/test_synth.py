@@ -37,3 +37,19 @@ def test_tables_unit_at_water():
         assert tab.values[i] == np.float32(1.0)
     assert t.b1.values[i] == 0.0 and t.b2.values[i] == 0.0
     assert t.A.values.shape == (26, 801)
+
+
+def test_paper_shaped_plans():
+    """Table 1 shapes: 128 x 128 x 72 (head) and 128 x 128 x 103 (lung) at
+    0.4 x 0.4 x 0.25 cm, 0.2 x 0.5 cm beamlets; the head case non-coplanar."""
+    import math
+    h, l = S.plan_paper_h5(), S.plan_paper_l2()
+    assert h.shape == (72, 128, 128) and l.shape == (103, 128, 128)
+    assert h.spacing == l.spacing == (0.4, 0.4, 0.25)
+    assert len(h.beams) == 7 and len(l.beams) == 6
+    assert abs(h.n_beamlets - 10369) < 20 and abs(l.n_beamlets - 1720) < 10
+    assert len({round(b.couch, 6) for b in h.beams}) > 1 and all(b.couch == 0 for b in l.beams)
+    assert all((b.wx, b.wy) == (0.2, 0.5) for b in h.beams + l.beams)
+    assert np.array_equal(h.density, S.plan_paper_h5().density)
+    assert 0.25 < float(np.mean(h.fluence == 0)) < 0.35
+    assert math.isclose(h.origin[2], -0.5 * 71 * 0.25)
