@@ -148,7 +148,15 @@ def main():
     adj_ms = time_loop(lambda: geo.adjoint(w, out=grad), n_side)
     geo.set_dc(False)
     plain_ms = time_loop(lambda: geo.forward(flu, out=dose), n_side)
+    d_plain = dose.clone()
     geo.set_dc(True)
+    # the paper's evaluation (3%/3 mm gamma) of conventional FSPB against DC
+    from paper_1103_1164_amd import gamma_index
+    d_dc = geo.forward(flu)
+    g_out = torch.empty_like(d_dc)
+    _, g_stats = gamma_index(d_dc, d_plain, plan.spacing, out=g_out)
+    gamma_ms = time_loop(lambda: gamma_index(d_dc, d_plain, plan.spacing, out=g_out), 5)
+    del d_plain, d_dc, g_out
     # geometry (kernels 1-4) and host work of a step: the step minus its forward
     geom_ms = ms_step - fwd_ms
     # host<->device transfers of the CT in and the dose out (pinned host memory)
@@ -213,6 +221,9 @@ def main():
         "adjoint_evals_per_s": pairs_all / (adj_ms * 1e-3),
         "h2d_ct_ms": round(h2d_ms, 4),
         "d2h_dose_ms": round(d2h_ms, 4),
+        "gamma_plain_vs_dc": {k: (round(v, 5) if isinstance(v, float) else v)
+                              for k, v in g_stats.items()} | {"ms": round(gamma_ms, 4),
+                                                               "criteria": "3%/3 mm, global"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batch_c4": batch,

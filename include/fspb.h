@@ -405,6 +405,42 @@ int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* densi
 int fspb_forward_surrogate(fspb_geometry* g, const float* fluence, const float* prm, float* dose,
                            void* stream);
 
+/* ------------------------------------------------------------------------
+ * 3D gamma index (the evaluation of Section 2.3: distance-to-agreement and
+ * dose-difference criteria, the dose criterion global to the maximum
+ * reference dose).  For every voxel r of the reference grid
+ *   gamma(r)^2 = min(cap^2, min over voxel offsets o with |o| <= cap * dist
+ *                of |o|^2 / dist^2 + (E(r + o) - R(r))^2 / (dose_frac D)^2)
+ * with |o| the physical length of the offset (anisotropic voxels allowed),
+ * offsets leaving the grid skipped, and D = dose_max (or max R).  Statistics:
+ * the maximum gamma over the grid, and the mean gamma and the fraction with
+ * gamma < 1 over voxels with R >= iso_frac D.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    float dist;        /* distance criterion, cm (0: 0.3) */
+    float dose_frac;   /* dose criterion as a fraction of D (0: 0.03) */
+    float gamma_cap;   /* search radius cap * dist; gamma is at most cap (0: 5) */
+    float dose_max;    /* D; <= 0: the maximum of the reference */
+    float iso_frac;    /* statistics region R >= iso_frac D (0: 0.5) */
+} fspb_gamma_params;
+
+typedef struct {
+    double gamma_max;      /* over the whole grid */
+    double gamma_avg_iso;  /* mean over the statistics region */
+    double pass_rate_iso;  /* fraction of the region with gamma < 1 */
+    double dose_max;       /* D used */
+    long long n_iso;       /* voxels in the region */
+} fspb_gamma_stats;
+
+/* ref, eval: device [nz][ny][nx] on the same grid (spacing dx, dy, dz cm).
+ * gamma: device [nz][ny][nx] output or NULL; stats: host output or NULL;
+ * params: host struct or NULL for the defaults.  Synchronises the stream.
+ * Errors: FSPB_E_ARG for bad sizes or criteria, or a search sphere of more
+ * than 4096 voxel offsets. */
+int fspb_gamma(const float* ref, const float* eval, int nx, int ny, int nz, float dx, float dy,
+               float dz, const fspb_gamma_params* params, float* gamma, fspb_gamma_stats* stats,
+               void* stream);
+
 /* Frees the handle.  NULL-safe.  Waits for queued device work to finish,
  * then returns the handle's device buffers to the library's per-device cache
  * (reused by later fspb_create_geometry calls). */

@@ -22,7 +22,7 @@ import torch
 from . import _lib
 from ._lib import FspbError, check, load
 
-__all__ = ["Geometry", "Batch", "Mlp", "FspbDose", "FspbError", "load"]
+__all__ = ["Geometry", "Batch", "Mlp", "FspbDose", "FspbError", "gamma_index", "load"]
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -496,6 +496,31 @@ class Mlp:
     def restore(self, path) -> None:
         with np.load(path, allow_pickle=False) as z:
             self.load_state({k: z[k] for k in z.files})
+
+
+def gamma_index(ref: torch.Tensor, ev: torch.Tensor, spacing, dist: float = 0.3,
+                dose_frac: float = 0.03, cap: float = 5.0, dose_max: float = 0.0,
+                iso_frac: float = 0.5, out: Optional[torch.Tensor] = None, stream=None):
+    """3D gamma index of ev against ref (same grid, [nz][ny][nx], spacing
+    (dx, dy, dz) cm): returns (gamma grid, statistics dict)."""
+    for t in (ref, ev):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                and t.is_contiguous() and t.dim() == 3):
+            raise ValueError("ref and ev must be contiguous float32 CUDA tensors [nz][ny][nx]")
+    if ref.shape != ev.shape:
+        raise ValueError("ref and ev must have the same shape")
+    nz, ny, nx = ref.shape
+    if out is None:
+        out = torch.empty_like(ref)
+    p = _lib.fspb_gamma_params(float(dist), float(dose_frac), float(cap), float(dose_max),
+                               float(iso_frac))
+    st = _lib.fspb_gamma_stats()
+    with torch.cuda.device(ref.device):
+        check(load().fspb_gamma(C.c_void_p(ref.data_ptr()), C.c_void_p(ev.data_ptr()), nx, ny, nz,
+                                *map(float, spacing), C.byref(p), C.c_void_p(out.data_ptr()),
+                                C.byref(st), _stream(stream)), "fspb_gamma")
+    return out, dict(gamma_max=st.gamma_max, gamma_avg_iso=st.gamma_avg_iso,
+                     pass_rate_iso=st.pass_rate_iso, dose_max=st.dose_max, n_iso=st.n_iso)
 
 
 class FspbDose(torch.autograd.Function):

@@ -83,6 +83,16 @@ class fspb_surrogate_guard(C.Structure):
                 ("band_lo", C.c_float * 6), ("band_hi", C.c_float * 6)]
 
 
+class fspb_gamma_params(C.Structure):
+    _fields_ = [("dist", C.c_float), ("dose_frac", C.c_float), ("gamma_cap", C.c_float),
+                ("dose_max", C.c_float), ("iso_frac", C.c_float)]
+
+
+class fspb_gamma_stats(C.Structure):
+    _fields_ = [("gamma_max", C.c_double), ("gamma_avg_iso", C.c_double),
+                ("pass_rate_iso", C.c_double), ("dose_max", C.c_double), ("n_iso", C.c_longlong)]
+
+
 FSPB_MLP_IN, FSPB_MLP_IN_PAD, FSPB_MLP_HIDDEN, FSPB_MLP_OUT = 202, 224, 64, 6
 FSPB_MLP_PARAMS = 17542
 FSPB_MLP_MAX_ROWS = 1 << 22
@@ -139,6 +149,9 @@ SIGNATURES = {
                                        C.c_void_p]),
     "fspb_forward_surrogate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p]),
+    "fspb_gamma": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_float,
+                             C.c_float, C.c_float, C.POINTER(fspb_gamma_params), C.c_void_p,
+                             C.POINTER(fspb_gamma_stats), C.c_void_p]),
     "fspb_destroy": (None, [C.c_void_p]),
     "fspb_release_cached_memory": (C.c_int, []),
     "fspb_error_string": (C.c_char_p, [C.c_int]),
