@@ -45,6 +45,7 @@ class Options:
     rho_max: float = 2.0
     sample_step: float = 0.0      # 0 -> half the smallest voxel size
     dc_enabled: int = 1           # 1: 3D density correction, 0: plain FSPB
+    siddon: int = 0               # 1: exact (Siddon) depth tables instead of uniform samples
 
 
 @dataclass

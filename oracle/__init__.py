@@ -59,7 +59,7 @@ class _Options(C.Structure):
     _fields_ = [("roi_radius", C.c_double), ("rho_surface", C.c_double),
                 ("smooth_sigma", C.c_double), ("rho_min", C.c_double),
                 ("rho_max", C.c_double), ("sample_step", C.c_double),
-                ("dc_enabled", C.c_int)]
+                ("dc_enabled", C.c_int), ("siddon", C.c_int)]
 
 
 _lib = None
@@ -96,6 +96,8 @@ def lib():
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_pair_counts.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long),
                                       C.POINTER(C.c_int)]
+        L.orc_trace_siddon.restype = C.c_int
+        L.orc_trace_siddon.argtypes = [C.c_void_p, C.c_int] + [C.POINTER(C.c_double)] * 5 + [C.c_int]
         L.orc_density_at.restype = C.c_double
         L.orc_density_at.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.orc_params.restype = C.c_int
@@ -127,7 +129,7 @@ def p(x: float, u: float, x0: float) -> float:
 class Oracle:
     """FP64 oracle for one plan (``fspb_synth.Plan``)."""
 
-    def __init__(self, plan, dc_enabled: int | None = None):
+    def __init__(self, plan, dc_enabled: int | None = None, siddon: int | None = None):
         self.plan = plan
         self._keep = []
         g = plan.density
@@ -152,8 +154,9 @@ class Oracle:
                                                       "fu1", "fu2", "fw1", "fw2", "b1", "b2")])
         o = plan.options
         dc = o.dc_enabled if dc_enabled is None else dc_enabled
+        sid = getattr(o, "siddon", 0) if siddon is None else siddon
         opts = _Options(float(o.roi_radius), float(o.rho_surface), float(o.smooth_sigma),
-                        float(o.rho_min), float(o.rho_max), float(o.sample_step), int(dc))
+                        float(o.rho_min), float(o.rho_max), float(o.sample_step), int(dc), int(sid))
         self._structs = (grid, beams, tabs, opts)
         self.ctx = lib().orc_create(C.byref(grid), len(plan.beams), beams, C.byref(tabs),
                                     C.byref(opts))
@@ -184,6 +187,13 @@ class Oracle:
         return dict(hit=bool(info[0]), s_in=info[1], s_out=info[2], s_entry=info[3],
                     k_entry=int(info[4]), K=int(info[5]), s_exit=info[6], amb_rho=info[7],
                     step=info[8], n_samples=int(info[9]), T=T[:K], W1=W1[:K], W2=W2[:K])
+
+    def trace_siddon(self, i: int) -> dict:
+        """Siddon segment tables of beamlet i (context built with siddon=1)."""
+        K = lib().orc_trace_siddon(self.ctx, int(i), None, None, None, None, None, 0)
+        a = [np.zeros(max(K, 1)) for _ in range(5)]
+        lib().orc_trace_siddon(self.ctx, int(i), *[_ptr(v, C.c_double) for v in a], K)
+        return dict(K=K, t=a[0][:K], T=a[1][:K], W1=a[2][:K], W2=a[3][:K], rho=a[4][:K])
 
     # -- smoothing --------------------------------------------------------
     def smoothed(self, vox=None) -> np.ndarray:

@@ -34,6 +34,9 @@ typedef struct {
     double s_in, s_out, s_entry, s_exit, amb_rho, step;
     int k_entry, n_samples, K;
     double *T, *W1, *W2;
+    /* Siddon tables (siddon mode): segment starts and integrals */
+    int Ks;
+    double *st, *sT, *sW1, *sW2, *srho, *sb1, *sb2;
 } trace_t;
 
 struct orc_ctx {
@@ -283,6 +286,120 @@ static void trace_beamlet(orc_ctx* c, int i) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Siddon's exact radiological path (the alternative Section 2.2 sets
+ * aside): the density is constant inside each voxel, the axis is cut at
+ * every voxel-boundary plane it crosses inside the grid box, and each
+ * segment contributes density x length.  The crossing depths are sorted and
+ * each segment's voxel is the one holding its midpoint.
+ * reading: the entrance is the start of the first segment whose voxel
+ *   density reaches rho_surface; past the box exit the last segment's
+ *   density continues (the analogue of clamp-to-edge). */
+static int cmp_double(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void trace_siddon(orc_ctx* c, int i) {
+    const orc_grid* g = &c->g;
+    const frame_t* f = &c->fr[i];
+    trace_t* t = &c->tr[i];
+    t->Ks = 0;
+    t->hit = 0;
+    double lo[3] = {g->ox - 0.5 * g->dx, g->oy - 0.5 * g->dy, g->oz - 0.5 * g->dz};
+    double del[3] = {g->dx, g->dy, g->dz};
+    int n[3] = {g->nx, g->ny, g->nz};
+    double s_in = t->s_in, s_out = t->s_out;
+    if (!(s_in < s_out)) return;
+    int cap = 2 + n[0] + n[1] + n[2] + 3;
+    double* cut = (double*)malloc(sizeof(double) * cap);
+    int nc = 0;
+    cut[nc++] = s_in;
+    for (int a = 0; a < 3; ++a) {
+        if (f->d[a] == 0.0) continue;
+        for (int m = 0; m <= n[a]; ++m) {
+            double s = (lo[a] + m * del[a] - f->src[a]) / f->d[a];
+            if (s > s_in && s < s_out) cut[nc++] = s;
+        }
+    }
+    cut[nc++] = s_out;
+    qsort(cut, nc, sizeof(double), cmp_double);
+    /* segments with their voxel density */
+    double* seg_s = (double*)malloc(sizeof(double) * nc);
+    double* seg_r = (double*)malloc(sizeof(double) * nc);
+    int ns = 0;
+    for (int k = 0; k + 1 < nc; ++k) {
+        if (!(cut[k + 1] > cut[k])) continue;            /* zero-length: an edge or corner */
+        double mid = 0.5 * (cut[k] + cut[k + 1]);
+        int idx[3];
+        for (int a = 0; a < 3; ++a)
+            idx[a] = clampi((int)floor((f->src[a] + mid * f->d[a] - lo[a]) / del[a]), 0, n[a] - 1);
+        seg_s[ns] = cut[k];
+        seg_r[ns] = rho_at_voxel(g, idx[0], idx[1], idx[2]);
+        ++ns;
+    }
+    int e = -1;
+    for (int k = 0; k < ns && e < 0; ++k)
+        if (seg_r[k] >= c->opt.rho_surface) e = k;
+    if (e >= 0) {
+        int K = ns - e;
+        t->hit = 1;
+        t->s_entry = seg_s[e];
+        t->Ks = K;
+        t->st = (double*)malloc(sizeof(double) * K);
+        t->sT = (double*)malloc(sizeof(double) * K);
+        t->sW1 = (double*)malloc(sizeof(double) * K);
+        t->sW2 = (double*)malloc(sizeof(double) * K);
+        t->srho = (double*)malloc(sizeof(double) * K);
+        t->sb1 = (double*)malloc(sizeof(double) * K);
+        t->sb2 = (double*)malloc(sizeof(double) * K);
+        double T = 0.0, W1 = 0.0, W2 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double r = seg_r[e + k], rc = clampd(r, c->opt.rho_min, c->opt.rho_max);
+            t->st[k] = seg_s[e + k] - t->s_entry;
+            t->sT[k] = T;
+            t->sW1[k] = W1;
+            t->sW2[k] = W2;
+            t->srho[k] = r;
+            t->sb1[k] = lerp_table(&c->tab.b1, rc);
+            t->sb2[k] = lerp_table(&c->tab.b2, rc);
+            double len = (k + 1 < K ? seg_s[e + k + 1] : s_out) - seg_s[e + k];
+            T += r * len;
+            W1 += t->sb1[k] * len;
+            W2 += t->sb2[k] * len;
+        }
+    }
+    free(cut);
+    free(seg_s);
+    free(seg_r);
+}
+
+/* Integral at depth t >= 0 from Siddon segment tables: the last segment
+ * starting at or before t, then linear inside it. */
+static double siddon_at(const double* st, const double* v, const double* slope, int K, double t) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (st[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return v[lo] + slope[lo] * (t - st[lo]);
+}
+
+int orc_trace_siddon(const orc_ctx* c, int i, double* t, double* T, double* W1, double* W2,
+                     double* rho, int maxK) {
+    const trace_t* tr = &c->tr[i];
+    int n = tr->Ks < maxK ? tr->Ks : maxK;
+    for (int k = 0; k < n; ++k) {
+        if (t) t[k] = tr->st[k];
+        if (T) T[k] = tr->sT[k];
+        if (W1) W1[k] = tr->sW1[k];
+        if (W2) W2[k] = tr->sW2[k];
+        if (rho) rho[k] = tr->srho[k];
+    }
+    return tr->Ks;
+}
+
+/* ------------------------------------------------------------------ */
 /* Algorithm A1 step 1: smoothed density = density convolved with a 3D
  * Gaussian.  reading: width smooth_sigma, truncated to a cube of
  * ceil(3 sigma / delta) voxels per axis, weights normalised to sum 1,
@@ -351,7 +468,10 @@ orc_ctx* orc_create(const orc_grid* g, int n_beams, const orc_beam* beams,
     c->bm = (beam_t*)calloc(n_beams, sizeof(beam_t));
     build_frames(c, beams);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int i = 0; i < c->n_beamlets; ++i) trace_beamlet(c, i);
+    for (int i = 0; i < c->n_beamlets; ++i) {
+        trace_beamlet(c, i);
+        if (c->opt.siddon) trace_siddon(c, i);
+    }
     build_weights(c);
     return c;
 }
@@ -362,6 +482,13 @@ void orc_destroy(orc_ctx* c) {
         free(c->tr[i].T);
         free(c->tr[i].W1);
         free(c->tr[i].W2);
+        free(c->tr[i].st);
+        free(c->tr[i].sT);
+        free(c->tr[i].sW1);
+        free(c->tr[i].sW2);
+        free(c->tr[i].srho);
+        free(c->tr[i].sb1);
+        free(c->tr[i].sb2);
     }
     free(c->tr);
     free(c->fr);
@@ -440,7 +567,8 @@ static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c,
     double x = xp * mag, y = yp * mag;
     double isq = mag * mag;
     double ci = depth / t->step;
-    double teq = lerp_array(t->T, t->K, ci);
+    const int sid = c->opt.siddon;
+    double teq = sid ? siddon_at(t->st, t->sT, t->srho, t->Ks, depth) : lerp_array(t->T, t->K, ci);
     double A = lookup_A(tb, teq, f->theta);
     double u1x = lerp_table(&tb->u1x, depth), u1y = lerp_table(&tb->u1y, depth);
     double u2x = lerp_table(&tb->u2x, depth), u2y = lerp_table(&tb->u2y, depth);
@@ -453,8 +581,10 @@ static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c,
         u1y *= fu1;
         u2x *= fu2;
         u2y *= fu2;
-        w1 = fw1 * (w1 + lerp_array(t->W1, t->K, ci));
-        w2 = fw2 * (w2 + lerp_array(t->W2, t->K, ci));
+        w1 = fw1 * (w1 + (sid ? siddon_at(t->st, t->sW1, t->sb1, t->Ks, depth)
+                              : lerp_array(t->W1, t->K, ci)));
+        w2 = fw2 * (w2 + (sid ? siddon_at(t->st, t->sW2, t->sb2, t->Ks, depth)
+                              : lerp_array(t->W2, t->K, ci)));
         if (w1 < 0.0) w1 = 0.0;   /* reading: weights cannot go negative */
         if (w2 < 0.0) w2 = 0.0;
     }

@@ -61,6 +61,8 @@ typedef struct {
 typedef struct {
     double roi_radius, rho_surface, smooth_sigma, rho_min, rho_max, sample_step;
     int dc_enabled;
+    int siddon;           /* 1: exact radiological path (Siddon) instead of the
+                             uniform samples of Section 2.2, see orc_trace_siddon */
 } orc_options;
 
 /* Ambiguity tolerances: a pair whose ROI or depth test lies this close to
@@ -94,6 +96,17 @@ void orc_frame(const orc_ctx* c, int i, double out[16]);
 int orc_trace(const orc_ctx* c, int i, double info[10], double* T,
               double* W1, double* W2, int maxK);
 
+/* Siddon tables of beamlet i (when the context was built with siddon = 1).
+ * The density is constant inside each voxel; the axis is cut at every voxel
+ * boundary between the grid-box entry and exit.  Segment m covers depths
+ * [t[m], t[m+1]) below the entrance (the last one runs on past the box) in
+ * a voxel of density rho[m]; T[m], W1[m], W2[m] are the integrals of rho and
+ * b_c(clamped rho) from the entrance to t[m].  The entrance is the start of
+ * the first segment whose voxel density reaches rho_surface.  Copies
+ * min(K, maxK) entries to the non-NULL arrays; returns K (0 if the beamlet
+ * misses the body). */
+int orc_trace_siddon(const orc_ctx* c, int i, double* t, double* T, double* W1, double* W2,
+                     double* rho, int maxK);
 /* Smoothed density at one voxel (direct, non-separable 3D sum). */
 double orc_smoothed_at(const orc_ctx* c, long vox);
 /* Smoothed density of the whole grid into out[n_vox]. */
