@@ -117,8 +117,19 @@ typedef struct {
     float rho_max;       /*                            [2.0] */
     float sample_step;   /* ray sampling step [min(dx,dy,dz)/2] (Section 2.2) */
     int dc_enabled;      /* 1: 3D density correction, 0: plain FSPB (A1 without step 11) */
-    int flags;           /* reserved, must be 0 */
+    int flags;           /* 0, or FSPB_FLAG_SIDDON */
 } fspb_options;
+
+/* fspb_options.flags: build exact radiological-depth tables (Siddon's
+ * path through voxel-constant density, the alternative Section 2.2 sets
+ * aside) instead of the uniform samples.  Each voxel segment past the
+ * entrance is a record; the entrance is the start of the first segment whose
+ * voxel density reaches rho_surface; the forward searches the records per
+ * pair.  Such a geometry supports fspb_forward, fspb_count_pairs,
+ * fspb_update_density, the tiling calls and the inspection calls (without
+ * the sampled tables); the adjoint, batches and the surrogate return
+ * FSPB_E_STATE. */
+#define FSPB_FLAG_SIDDON 1
 
 typedef struct {
     int n_beams, n_beamlets;

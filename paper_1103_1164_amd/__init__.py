@@ -73,7 +73,8 @@ class Geometry:
             o = options
             opt = _lib.fspb_options(float(o.roi_radius), float(o.rho_surface),
                                     float(o.smooth_sigma), float(o.rho_min), float(o.rho_max),
-                                    float(o.sample_step), int(o.dc_enabled), 0)
+                                    float(o.sample_step), int(o.dc_enabled),
+                                    _lib.FSPB_FLAG_SIDDON if getattr(o, "siddon", 0) else 0)
             opt_p = C.byref(opt)
         h = C.c_void_p()
         with torch.cuda.device(self.device):

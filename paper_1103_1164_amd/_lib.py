@@ -93,6 +93,7 @@ class fspb_gamma_stats(C.Structure):
                 ("pass_rate_iso", C.c_double), ("dose_max", C.c_double), ("n_iso", C.c_longlong)]
 
 
+FSPB_FLAG_SIDDON = 1
 FSPB_MLP_IN, FSPB_MLP_IN_PAD, FSPB_MLP_HIDDEN, FSPB_MLP_OUT = 202, 224, 64, 6
 FSPB_MLP_PARAMS = 17542
 FSPB_MLP_MAX_ROWS = 1 << 22

@@ -50,7 +50,8 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 //           log2 e, (w1, w2, fallback, 0)); a row whose fallback flag is set
 //           takes the density-corrected pair instead
 // A brick is BX x BY x BZ = 64 voxels, one per lane.
-enum { kDose = 0, kCount = 1, kCost = 2, kSurr = 3 };
+//   kSid    the dose with the exact (Siddon) depth tables
+enum { kDose = 0, kCount = 1, kCost = 2, kSurr = 3, kSid = 4 };
 
 template <int BX, int BY, int BZ>
 __device__ __forceinline__ int bricks_x(const PlanConst& P) { return (P.nx + BX - 1) / BX; }
@@ -76,6 +77,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     const FSPB_GLOBAL float4* __restrict__ atab = as_global(a.atab);
     const FSPB_GLOBAL float2* __restrict__ tT = as_global(a.tT);
     const FSPB_GLOBAL float4* __restrict__ tTW = as_global(a.tTW);
+    const FSPB_GLOBAL float4* __restrict__ sid = as_global(a.sid);
     const FSPB_GLOBAL float* __restrict__ fluence = as_global(fluence_);
     FSPB_GLOBAL float* __restrict__ dose = as_global_rw(dose_);
     FSPB_GLOBAL int* __restrict__ out_int = as_global_rw(out_int_);
@@ -91,7 +93,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     float qx, qy, qz;
     voxel_q(P, i, j, k, qx, qy, qz);
     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-    if (DC && (MODE == kDose || MODE == kSurr) && valid) fac = facs[v];
+    if (DC && (MODE == kDose || MODE == kSurr || MODE == kSid) && valid) fac = facs[v];
     // bounding sphere of the brick's voxel centres
     float cqx, cqy, cqz;
     voxel_q(P, bx * BX, by * BY, bz * BZ, cqx, cqy, cqz);
@@ -200,6 +202,10 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                     accb);
                     else if (act)
                         accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
+                                    accb);
+                } else if (MODE == kSid) {
+                    if (act)
+                        accb = fmaf(fe, pair_dose_siddon<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, sid),
                                     accb);
                 } else if (act) {
                     accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
@@ -504,6 +510,14 @@ void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
         launch_mode<true, kDose>(a, cfg, order, fluence, dose, nullptr, s);
     else
         launch_mode<false, kDose>(a, cfg, order, fluence, dose, nullptr, s);
+}
+
+void launch_forward_siddon(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
+                           const float* fluence, float* dose, hipStream_t s) {
+    if (dc)
+        launch_mode<true, kSid>(a, cfg, order, fluence, dose, nullptr, s);
+    else
+        launch_mode<false, kSid>(a, cfg, order, fluence, dose, nullptr, s);
 }
 
 void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,

@@ -196,6 +196,8 @@ struct fspb_geometry {
     float* denstab = nullptr;
     float2* tT = nullptr;
     float4* tTW = nullptr;    // DC only: interleaved depth + weight-drift records
+    float4* sid = nullptr;    // exact (Siddon) depth tables, when the plan asks for them
+    int siddon = 0, sid_stride = 0;
     float* w3 = nullptr;
     int* counts = nullptr;
     int* order = nullptr;      // bricks in decreasing order of estimated work
@@ -239,6 +241,7 @@ struct fspb_geometry {
         a.atab = atab;
         a.tT = tT;
         a.tTW = tTW;
+        a.sid = sid;
         return a;
     }
 
@@ -299,7 +302,7 @@ int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_
         if (d->start != t->u1x.start || d->n != t->u1x.n || (d->n > 1 && d->step != t->u1x.step))
             return fail(FSPB_E_ARG, "the water tables u1x..w2 must share one depth grid");
     if (o) {
-        if (o->flags != 0) return fail(FSPB_E_ARG, "options.flags must be 0");
+        if (o->flags & ~FSPB_FLAG_SIDDON) return fail(FSPB_E_ARG, "options.flags: unknown bits");
         if (o->dc_enabled != 0 && o->dc_enabled != 1)
             return fail(FSPB_E_ARG, "options.dc_enabled must be 0 or 1");
         if (o->roi_radius < 0 || o->smooth_sigma < 0 || o->sample_step < 0 ||
@@ -545,6 +548,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     const long nv = (long)nx * ny * nz;
     G->n_beams = n_beams;
     G->dc_created = G->dc_enabled = o.dc_enabled;
+    G->siddon = (o.flags & FSPB_FLAG_SIDDON) ? 1 : 0;
     int nbl = 0;
     for (int b = 0; b < n_beams; ++b) nbl += beams[b].nbx * beams[b].nby;
     G->n_beamlets = nbl;
@@ -719,6 +723,9 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     tg.n[0] = nx;
     tg.n[1] = ny;
     tg.n[2] = nz;
+    tg.del[0] = ct->dx;
+    tg.del[1] = ct->dy;
+    tg.del[2] = ct->dz;
     TraceParams& tp = G->tp;
     tp.step = step;
     tp.rho_surface = o.rho_surface;
@@ -729,6 +736,18 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->desc,
                  G->tinfo, s);
     HIP_TRY(hipGetLastError());
+    if (G->siddon) {
+        // exact tables replace the uniform samples (records, entrance, K)
+        G->sid_stride = nx + ny + nz + 2;
+        if ((long long)G->sid_stride * nbl > (1LL << 27) - 1)
+            return fail(FSPB_E_ARG, "exact depth tables of %d x %d records are too large", nbl,
+                        G->sid_stride);
+        if ((rc = G->alloc((void**)&G->sid, 2 * sizeof(float4) * (size_t)nbl * G->sid_stride)) != FSPB_OK)
+            return rc;
+        launch_siddon(G->frames, nbl, ct->density, tg, tp, G->sid_stride, G->denstab, G->dens,
+                      G->sid, G->desc, G->tinfo, s);
+        HIP_TRY(hipGetLastError());
+    }
 
     if ((rc = build_order(G, s)) != FSPB_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s));   // the caller may free ct->density now
@@ -760,16 +779,24 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     return FSPB_OK;
 }
 
+// The forward of a handle, with its depth tables' kind.
+static void enqueue_forward(fspb_geometry* g, const float* fluence, float* dose, hipStream_t s) {
+    if (g->siddon)
+        launch_forward_siddon(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
+    else
+        launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
+}
+
 int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream) {
     if (!g || !fluence || !dose) return fail(FSPB_E_ARG, "forward: NULL argument");
-    launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose,
-                   (hipStream_t)stream);
+    enqueue_forward(g, fluence, dose, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
 
 int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream) {
     if (!g || !voxel_weight || !grad) return fail(FSPB_E_ARG, "adjoint: NULL argument");
+    if (g->siddon) return fail(FSPB_E_STATE, "adjoint: not available with exact depth tables");
     launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad,
                    (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
@@ -869,6 +896,8 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
         info->entry_margin = ti.margin;
     }
     int n = std::min(max_k, d.K);
+    if (n > 0 && (T || W1 || W2) && g->siddon)
+        return fail(FSPB_E_STATE, "beamlet: the sampled tables are not kept with exact depth tables");
     if (n > 0 && (T || W1 || W2)) {
         std::vector<float2> tt(n);
         HIP_TRY(hipMemcpy(tt.data(), g->tT + d.tab_off, sizeof(float2) * n, hipMemcpyDeviceToHost));
@@ -962,11 +991,10 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
             rc = fspb_set_tile(g, sh, wpbs[w], stream);
             if (rc) break;
             std::vector<float> ms;
-            launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose_scratch, s);
+            enqueue_forward(g, fluence, dose_scratch, s);
             for (int r = 0; r < reps; ++r) {
                 (void)hipEventRecord(e0, s);
-                launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence,
-                               dose_scratch, s);
+                enqueue_forward(g, fluence, dose_scratch, s);
                 (void)hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) {
                     rc = fail(FSPB_E_HIP, "autotune: forward failed");
@@ -1011,6 +1039,11 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
     launch_trace(g->frames, g->n_beamlets, density, g->tg, g->tp, g->denstab, g->dens, g->tT,
                  g->tTW, g->desc, g->tinfo, s);
     HIP_TRY(hipGetLastError());
+    if (g->siddon) {
+        launch_siddon(g->frames, g->n_beamlets, density, g->tg, g->tp, g->sid_stride, g->denstab,
+                      g->dens, g->sid, g->desc, g->tinfo, s);
+        HIP_TRY(hipGetLastError());
+    }
     g->host_ready = false;
     return FSPB_OK;
 }
@@ -1090,6 +1123,8 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
         return fail(FSPB_E_ARG, "batch_create: unknown schedule policy %d", policy);
     for (int p = 0; p < n; ++p) {
         if (!geoms[p]) return fail(FSPB_E_ARG, "batch_create: geometry %d is NULL", p);
+        if (geoms[p]->siddon)
+            return fail(FSPB_E_STATE, "batch_create: geometry %d uses exact depth tables", p);
         if (geoms[p]->dc_enabled != geoms[0]->dc_enabled)
             return fail(FSPB_E_ARG, "batch_create: plans must share the density-correction mode");
     }
@@ -1536,6 +1571,7 @@ static int check_surrogate_geometry(const fspb_geometry* g, const char* what) {
     if (!g) return fail(FSPB_E_ARG, "%s: NULL geometry", what);
     if (!g->dc_created)
         return fail(FSPB_E_STATE, "%s: the geometry was created without density correction", what);
+    if (g->siddon) return fail(FSPB_E_STATE, "%s: not available with exact depth tables", what);
     return check_same_device(g->device, what);
 }
 

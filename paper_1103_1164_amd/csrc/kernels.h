@@ -14,6 +14,7 @@ struct BeamIn {
 struct TraceGrid {
     double o[3], inv[3];
     int n[3];
+    double del[3];   // voxel sizes (the plane positions of the exact path)
 };
 
 struct TraceParams {
@@ -37,6 +38,16 @@ void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const
                   const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
                   float4* tTW, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
 
+// Exact (Siddon) depth tables instead of the uniform samples: per beamlet,
+// one 32-byte record per voxel segment past the entrance,
+//   sid[2(off + m)]     = (t_m, T_m, rho_m, W1_m)   depth and integrals at
+//                                                  the segment start, T slope
+//   sid[2(off + m) + 1] = (b1_m, W2_m, b2_m, 0)     weight-drift slopes
+// with off = beamlet * stride; the descriptor's K counts the records.
+void launch_siddon(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
+                   const TraceParams& tp, int stride, const float* dtabs, const DensTabs& dt,
+                   float4* sid, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
+
 // Dose kernels (dose.hip).
 struct DoseArgs {
     PlanConst P;
@@ -47,6 +58,7 @@ struct DoseArgs {
     const float4* atab;
     const float2* tT;
     const float4* tTW;
+    const float4* sid;     // exact depth tables (null unless the plan uses them)
 };
 
 // Forward-kernel tile configuration: brick shape (index into the built
@@ -63,6 +75,9 @@ void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
                     const float* fluence, float* dose, hipStream_t s);
 // Dose with the learned surrogate's per-(voxel, beam) parameters (see
 // dose.hip, mode kSurr); needs a density-corrected geometry.
+// Forward with the exact (Siddon) depth tables.
+void launch_forward_siddon(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
+                           const float* fluence, float* dose, hipStream_t s);
 void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
                               const float* fluence, const float4* prm, float* dose, hipStream_t s);
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,

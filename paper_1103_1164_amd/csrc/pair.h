@@ -177,6 +177,67 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     return F * A * isq;
 }
 
+// pair_dose with the exact (Siddon) depth tables: the radiological depth and
+// weight drift come from the beamlet's voxel-segment records (see
+// kernels.h), found by a binary search on the segment start depths -- the
+// search the uniform samples of Section 2.2 avoid.  Everything else is
+// pair_dose's.
+template <bool DC, class BD>
+__device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, float k, const BD& b,
+                                                  float4 fac, const PlanConst& P,
+                                                  const FSPB_GLOBAL float4* __restrict__ dtab,
+                                                  const FSPB_GLOBAL float4* __restrict__ atab,
+                                                  const FSPB_GLOBAL float4* __restrict__ sid) {
+    float x = xp * k, y = yp * k;
+    float isq = k * (0.25f * k);
+    const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
+    const unsigned od = 48u * (unsigned)cd;
+    const float fd = fract(cd);
+    const float4 u0 = load_at(dtab, od), us = load_at(dtab, od + 16u), wv = load_at(dtab, od + 32u);
+    const FSPB_GLOBAL float4* rec = sid + 2 * (long)b.tab_off;
+    int lo = 0, hi = b.K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rec[2 * mid].x <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const float4 r0 = rec[2 * lo];
+    const float dt = t - r0.x;
+    const float teq = fmaf(dt, r0.z, r0.y);
+    float W1 = 0.0f, W2 = 0.0f;
+    if (DC) {
+        const float4 r1 = rec[2 * lo + 1];
+        W1 = fmaf(dt, r1.x, r0.w);
+        W2 = fmaf(dt, r1.z, r1.y);
+    }
+    const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
+    const float fa = fract(ca);
+    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
+                                        16u * (unsigned)b.th_col);
+    float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
+    float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
+    float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
+    if (DC) {
+        u1x *= fac.x;
+        u1y *= fac.x;
+        u2x *= fac.y;
+        u2y *= fac.y;
+        w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
+        w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
+    }
+    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
+    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+    float ax = fabsf(x), ay = fabsf(y);
+    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
+    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
+    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
+    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
+    float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
+    float F = fmaf(w1, p1, w2 * p2);
+    return F * A * isq;
+}
+
 // The six Section 2.1 parameters a pair uses, in the units of the tables
 // (u in 1/cm, weights dimensionless): out = (u1x, u1y, u2x, u2y, w1, w2).
 // Same arithmetic as pair_dose<true>; exported as training targets of the

@@ -1,0 +1,97 @@
+"""The exact (Siddon) depth tables on an MI355X against the oracle's Siddon
+mode, under the dose bar of the method (1e-4 of max dose plus the
+ambiguity allowance)."""
+import copy
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import fspb_synth as S
+from gpu_helpers import assert_dose_parity, gpu_dose, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _siddon(plan, dc=1):
+    p = copy.copy(plan)
+    p.options = copy.copy(plan.options)
+    p.options.siddon = 1
+    p.options.dc_enabled = dc
+    return p
+
+
+def _geometry(plan):
+    from paper_1103_1164_amd import Geometry
+    return Geometry.from_plan(plan, device="cuda")
+
+
+def _plans():
+    rng = np.random.default_rng(31)
+    n = (23, 19, 13)
+    rho = rng.uniform(0.05, 2.3, size=(n[2], n[1], n[0])).astype(np.float32)
+    a = S.plan_small(n=n, density=rho, seed=1, name="noise", beams=[
+        S.Beam(gantry=0.3, nbx=5, nby=3, wx=0.4, wy=0.6, cx=0.2, cy=-0.1),
+        S.Beam(gantry=3.9, couch=0.25, nbx=4, nby=4, wx=0.5, wy=0.5)])
+    n, sp = (30, 26, 17), (0.3, 0.25, 0.4)
+
+    def body(Z, Y, X):
+        r = (X / 3.2) ** 2 + (Y / 2.6) ** 2 + (Z / 3.0) ** 2
+        return np.where(r <= 1.0, 1.0 + 0.3 * np.sin(2 * X) * np.cos(Y), 0.001)
+    b = S.plan_small(n=n, spacing=sp, density=body, seed=2, name="body_couch", beams=[
+        S.Beam(gantry=1.2, couch=0.35, nbx=6, nby=5, wx=0.5, wy=0.5, iso=(0.2, -0.3, 0.1)),
+        S.Beam(gantry=math.pi / 2, nbx=3, nby=7, wx=0.7, wy=0.3)])
+    return [a, b]
+
+
+@pytest.mark.parametrize("dc", [1, 0])
+@pytest.mark.parametrize("k", [0, 1])
+def test_siddon_full_grid(oracle_mod, k, dc):
+    plan = _siddon(_plans()[k], dc)
+    say(f"siddon {plan.name} dc={dc}")
+    d_o, amb, _ = oracle_mod.Oracle(plan).dose()
+    geo = _geometry(plan)
+    d = gpu_dose(geo, plan.fluence)
+    assert d_o.max() > 0
+    assert_dose_parity(d, d_o, amb, what=f"siddon {plan.name}")
+
+
+def test_siddon_c2_sampled(oracle_mod):
+    plan = _siddon(S.plan_c2())
+    geo = _geometry(plan)
+    d = gpu_dose(geo, plan.fluence)
+    rng = np.random.default_rng(4)
+    vox = np.unique(np.concatenate([rng.choice(plan.n_vox, 2000, replace=False),
+                                    np.argsort(d.reshape(-1))[-500:]]))
+    say(f"siddon c2: oracle at {vox.size} voxels")
+    o = oracle_mod.Oracle(plan)
+    d_o, amb, _ = o.dose(vox=vox)
+    assert_dose_parity(d.reshape(-1)[vox], d_o, amb, what="siddon c2")
+    hits = sum(o.trace(i)["hit"] for i in range(plan.n_beamlets))
+    assert geo.info()["n_hit"] == hits
+    # the uniform samples differ from the exact path by a little
+    uni = gpu_dose(_geometry(S.plan_c2()), plan.fluence)
+    rel = np.abs(uni - d).max() / d.max()
+    say(f"siddon c2: max |uniform - exact| / max = {rel:.3e}")
+    assert 0.0 < rel < 0.05
+
+
+def test_siddon_update_density_and_limits():
+    from paper_1103_1164_amd import FspbError
+    plans = _plans()
+    p0 = _siddon(plans[0])
+    geo = _geometry(p0)
+    rho2 = np.random.default_rng(9).uniform(0.05, 2.2, size=p0.density.shape).astype(np.float32)
+    p1 = copy.copy(p0)
+    p1.density = rho2
+    geo.update_density(torch.as_tensor(rho2, device="cuda"))
+    assert np.array_equal(gpu_dose(geo, p0.fluence), gpu_dose(_geometry(p1), p0.fluence))
+    with pytest.raises(FspbError) as e:
+        geo.adjoint(torch.ones(p0.n_vox, device="cuda"))
+    assert e.value.code == -4
+    # counts and tiles work; tile choice does not change the dose
+    ref = gpu_dose(geo, p0.fluence)
+    geo.set_tile(1, 2)
+    assert np.array_equal(gpu_dose(geo, p0.fluence), ref)
+    assert geo.count_pairs(torch.as_tensor(p0.fluence, device="cuda")) > 0
