@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training and timing the learned surrogate (config 5)")
+    ap.add_argument("--no-siddon", action="store_true",
+                    help="skip the exact (Siddon) depth-table comparison")
     ap.add_argument("--no-paper-cases", action="store_true",
                     help="skip the paper-shaped head-and-neck and lung plans")
     ap.add_argument("--surrogate-plans", type=int, default=200,
@@ -178,6 +180,9 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(plan, a.cpu_sample)
+    sid = None
+    if not a.no_siddon:
+        sid = siddon_c2(plan, dens, flu, time_loop)
     paper = None
     if not a.no_paper_cases:
         paper = paper_cases(time_loop)
@@ -228,6 +233,7 @@ def main():
         "cpu_baseline": cpu,
         "batch_c4": batch,
         "surrogate_c5": surr,
+        "siddon_c2": sid,
         "paper_cases": paper,
         "paper_context": "Tesla C1060, real H&N/lung IMRT plans (Table 4): median T_gpu "
                          "0.37 s DC (0.33 s plain), T_tr 0.20 s; different hardware and workload",
@@ -240,6 +246,51 @@ def _opts(o, dc):
     o = copy.copy(o)
     o.dc_enabled = int(dc)
     return o
+
+
+def siddon_c2(plan, dens, flu, time_loop, n=10):
+    """The exact (Siddon) depth tables against the paper's uniform samples on
+    the benchmark plan: forward and per-plan times, and the dose difference
+    (max and the 3%/3 mm gamma of the uniform-sample dose against the exact
+    one)."""
+    import numpy as np
+    import torch
+
+    from paper_1103_1164_amd import Geometry, gamma_index
+
+    def make(siddon):
+        o = _opts(plan.options, 1)
+        o.siddon = siddon
+        return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables, o)
+
+    res = {}
+    doses = {}
+    for name, sd in (("uniform", 0), ("siddon", 1)):
+        per = []
+        for k in range(n + 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = make(sd)
+            g.forward(flu)
+            g.close()
+            if k >= 2:
+                per.append((time.perf_counter() - t0) * 1e3)
+        geo = make(sd)
+        out = torch.empty(plan.shape, device="cuda")
+        fwd = time_loop(lambda: geo.forward(flu, out=out), n)
+        doses[name] = out.clone()
+        res[name] = {"ms_per_plan_median": round(float(np.median(per)), 4),
+                     "ms_per_plan_max": round(float(np.max(per)), 4), "forward_ms": round(fwd, 4),
+                     "n_hit": geo.info()["n_hit"]}
+        geo.close()
+    u, e = doses["uniform"], doses["siddon"]
+    _, gs = gamma_index(e, u, plan.spacing)
+    res["max_abs_diff_over_max"] = round(float((u - e).abs().max() / e.max()), 5)
+    res["gamma_uniform_vs_siddon"] = {k: (round(v, 5) if isinstance(v, float) else v)
+                                      for k, v in gs.items()}
+    res["forward_ratio_siddon_over_uniform"] = round(res["siddon"]["forward_ms"] /
+                                                     res["uniform"]["forward_ms"], 4)
+    return res
 
 
 def paper_cases(time_loop, n=10):
