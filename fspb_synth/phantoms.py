@@ -208,6 +208,26 @@ def plan_c5(seed: int, tables: Tables | None = None) -> Plan:
     return p
 
 
+def commissioning_plans(tables: Tables | None = None, scale: int = 1) -> List[Plan]:
+    """Measurement set for fitting the commissioned tables: a water tank
+    (depth doses, profiles and the off-axis horn of a 14 cm field of 1 cm
+    beamlets) and a slab phantom (lung and bone slabs: the density factors
+    and the weight drift).  scale = 2 halves the voxel size."""
+    t = tables or make_tables(0)
+    sp = (0.5 / scale,) * 3
+    n_w = (40 * scale, 40 * scale, 30 * scale)
+    water = Plan("tank", np.ones((n_w[2], n_w[1], n_w[0]), np.float32), sp,
+                 grid_origin_centered(n_w, sp), [Beam(gantry=0.0, nbx=14, nby=14, wx=1.0, wy=1.0)],
+                 np.ones(196, np.float32), t, Options())
+    n_s = (32 * scale, 40 * scale, 32 * scale)
+    o_s = grid_origin_centered(n_s, sp)
+    slab = Plan("slabs", slab_density(n_s, sp, slabs=((-6.0, -3.0, 0.25), (1.0, 2.0, 1.8)),
+                                      origin=o_s), sp, o_s,
+                [Beam(gantry=0.0, nbx=8, nby=8, wx=0.5, wy=0.5)], np.ones(64, np.float32), t,
+                Options())
+    return [water, slab]
+
+
 # Paper-shaped plans (Table 1 scales): CT down-sampled to 0.4 x 0.4 x 0.25 cm,
 # beamlets of 0.2 x 0.5 cm (0.2 along the beam's x axis, the leaf motion).
 PAPER_SPACING = (0.4, 0.4, 0.25)

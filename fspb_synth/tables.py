@@ -81,12 +81,26 @@ def _f32(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
 
 
+TABLE_COEFFS = ("mu_a", "dmax", "s0", "s1", "w_slope", "f_slope", "b_slope", "horn")
+
+
+def table_coeffs(seed: int = 0) -> np.ndarray:
+    """Coefficient multipliers of a machine: ones (seed 0) or U(0.9, 1.1)."""
+    if seed == 0:
+        return np.ones(8)
+    return np.random.default_rng(seed).uniform(0.9, 1.1, size=8)
+
+
 def make_tables(seed: int = 0) -> Tables:
     """Tables for the nominal machine (seed 0) or a perturbed one (seed > 0)."""
-    if seed == 0:
-        c = np.ones(8)
-    else:
-        c = np.random.default_rng(seed).uniform(0.9, 1.1, size=8)
+    return make_tables_coeffs(table_coeffs(seed))
+
+
+def make_tables_coeffs(c) -> Tables:
+    """Tables from the 8 coefficient multipliers c (TABLE_COEFFS order) of
+    the nominal machine's attenuation, build-up depth, lateral-width offset
+    and slope, weight slope, weight-factor slope, drift slope and horn."""
+    c = np.asarray(c, dtype=np.float64)
     mu_a, dmax, s0, s1, w_slope, f_slope, b_slope, horn = (
         0.05 * c[0], 1.5 * c[1], 0.3 * c[2], 0.02 * c[3],
         0.005 * c[4], 0.2 * c[5], 0.02 * c[6], 0.5 * c[7])
