@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training and timing the learned surrogate (config 5)")
+    ap.add_argument("--no-commission", action="store_true",
+                    help="skip the commissioning fit")
     ap.add_argument("--no-siddon", action="store_true",
                     help="skip the exact (Siddon) depth-table comparison")
     ap.add_argument("--no-paper-cases", action="store_true",
@@ -183,6 +185,9 @@ def main():
     sid = None
     if not a.no_siddon:
         sid = siddon_c2(plan, dens, flu, time_loop)
+    comm = None
+    if not a.no_commission:
+        comm = commission_fit()
     paper = None
     if not a.no_paper_cases:
         paper = paper_cases(time_loop)
@@ -234,6 +239,7 @@ def main():
         "batch_c4": batch,
         "surrogate_c5": surr,
         "siddon_c2": sid,
+        "commissioning": comm,
         "paper_cases": paper,
         "paper_context": "Tesla C1060, real H&N/lung IMRT plans (Table 4): median T_gpu "
                          "0.37 s DC (0.33 s plain), T_tr 0.20 s; different hardware and workload",
@@ -246,6 +252,35 @@ def _opts(o, dc):
     o = copy.copy(o)
     o.dc_enabled = int(dc)
     return o
+
+
+def commission_fit():
+    """The commissioning fitter on the water-tank and slab measurement set:
+    recover a perturbed machine's 8 table parameters from its doses (made by
+    the library with that machine's tables), starting from the nominal one."""
+    import numpy as np
+    import torch
+
+    import fspb_synth as S
+    from paper_1103_1164_amd import Geometry
+    from paper_1103_1164_amd.commission import fit_tables
+
+    truth = S.table_coeffs(7)
+    plans = S.commissioning_plans()
+    refs = []
+    for p in plans:
+        g = Geometry(torch.as_tensor(p.density, device="cuda"), p.spacing, p.origin, p.beams,
+                     S.make_tables_coeffs(truth), p.options)
+        refs.append(g.forward(torch.as_tensor(p.fluence, device="cuda")).clone())
+        g.close()
+    res = fit_tables(plans, refs, S.make_tables_coeffs, np.ones(8))
+    err = np.abs(res["c"] - truth) / truth
+    return {"parameters": 8, "measurement_voxels": int(sum(p.n_vox for p in plans)),
+            "iterations": len(res["cost"]) - 1, "plan_evaluations": res["evaluations"],
+            "seconds": round(res["seconds"], 3),
+            "ms_per_evaluation": round(1e3 * res["seconds"] / res["evaluations"], 3),
+            "max_rel_param_error": float(err.max()),
+            "cost_first": res["cost"][0], "cost_last": res["cost"][-1]}
 
 
 def siddon_c2(plan, dens, flu, time_loop, n=10):
