@@ -35,8 +35,40 @@ METRIC = "voxel·beamlet evals/s + ms/plan, plain DC-FSPB vs surrogate at ≤1% 
 # the design notes.  Plain FSPB skips the 14 density-correction operations.
 FLOPS_PER_PAIR_DC = 109
 FLOPS_PER_PAIR_PLAIN = 95
-PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published, packed FP32)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+
+
+FORWARD_SOURCES = ("dose.hip", "pair.h", "kernels.h", "fspb_internal.h")
+PMC_SUMMARY = ROOT / "profiles" / "dose_forward_c2_pmc.md"
+
+
+def forward_source_hash() -> str:
+    """SHA-256 over the forward kernel's sources: HBM counters taken on
+    another version of the kernel do not describe this one."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in FORWARD_SOURCES:
+        h.update((ROOT / "paper_1103_1164_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
+def pmc_record(tile) -> dict:
+    """The committed PMC summary's record, if it was taken on these sources
+    with this tile configuration; else an empty dict."""
+    if not PMC_SUMMARY.exists():
+        return {}
+    rec = {}
+    for line in PMC_SUMMARY.read_text().splitlines():
+        if line.startswith("    ") and ":" in line:
+            k, v = line.strip().split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != forward_source_hash():
+        return {}
+    if rec.get("tile") != f"{tile[0]},{tile[1]}":
+        return {}
+    return rec
 
 
 def parse():
@@ -94,6 +126,7 @@ def main():
                         _opts(plan.options, dc))
 
     geo = make()
+    geo_tile = geo.get_tile()
     pairs_fwd = geo.count_pairs(flu)
     pairs_all = geo.count_pairs(None)
     info = geo.info()
@@ -102,9 +135,10 @@ def main():
         for _ in range(a.forward_only):
             geo.forward(flu, out=dose)
         if a.copy_mib:
+            # a kernel of known traffic (reads and writes copy_mib MiB once)
             src = torch.ones(a.copy_mib * (1 << 18), device=dev)
             dst = torch.empty_like(src)
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"forward_launches": a.forward_only, "pairs": pairs_fwd}))
         return
@@ -171,10 +205,17 @@ def main():
     d2h_ms = time_loop(lambda: h_dose.copy_(dose, non_blocking=True), n_side)
 
     achieved_tf = pairs_fwd * FLOPS_PER_PAIR_DC / (fwd_ms * 1e-3) / 1e12
+    pmc = pmc_record(geo_tile)
     roofline = {
         "bound": "alu", "kernel": "dose_forward<DC>",
         "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
+        "traffic": int(pmc["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in pmc else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, PMC run "
+                        "recorded in profiles/dose_forward_c2_pmc.md)",
+        "valu_busy": float(pmc["valu_busy_at_2.4GHz"]) if "valu_busy_at_2.4GHz" in pmc else None,
+        "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+        "frac_nonpacked": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
         "flops_per_pair": FLOPS_PER_PAIR_DC, "pairs_per_launch": pairs_fwd,
         "launch_ms": round(fwd_ms, 4),
     }
