@@ -35,6 +35,37 @@ def _dev_f32(x, device) -> torch.Tensor:
     return t.contiguous()
 
 
+_TABLE_NAMES = ("A", "u1x", "u1y", "u2x", "u2y", "w1", "w2", "fu1", "fu2", "fw1", "fw2", "b1", "b2")
+_table_cache: dict = {}
+
+
+def _marshal_tables(tables):
+    """The ctypes view of a tables object.  Views are cached per identity of
+    every table and value array (and the scalar fields), so a replaced table
+    or array is marshalled afresh; the library compares table contents
+    itself before reusing packed tables."""
+    key = (int(tables.n_theta), float(tables.theta_step)) + tuple(
+        (id(t), id(t.values), float(t.start), float(t.step))
+        for t in (getattr(tables, n) for n in _TABLE_NAMES))
+    hit = _table_cache.get(key)
+    if hit is not None:
+        return hit[0]
+    keep = [tables]
+
+    def tab(t):
+        v = np.ascontiguousarray(t.values, dtype=np.float32)
+        keep.append((t, t.values, v))
+        return _lib.fspb_table1d(float(t.start), float(t.step), int(v.shape[-1]),
+                                 v.ctypes.data_as(C.POINTER(C.c_float)))
+
+    tabs = _lib.fspb_tables(tab(tables.A), int(tables.n_theta), float(tables.theta_step),
+                            *[tab(getattr(tables, n)) for n in _TABLE_NAMES[1:]])
+    if len(_table_cache) >= 16:
+        _table_cache.pop(next(iter(_table_cache)))
+    _table_cache[key] = (tabs, keep)      # keep: the objects whose ids form the key stay alive
+    return tabs
+
+
 class Geometry:
     """A plan's geometry on the GPU (owning handle of libfspb)."""
 
@@ -56,18 +87,7 @@ class Geometry:
                                    (C.c_float * 3)(*map(float, b.iso)), float(b.sad),
                                    int(b.nbx), int(b.nby), float(b.wx), float(b.wy),
                                    float(b.cx), float(b.cy))
-        keep = []
-
-        def tab(t):
-            v = np.ascontiguousarray(t.values, dtype=np.float32)
-            keep.append(v)
-            return _lib.fspb_table1d(float(t.start), float(t.step), int(v.shape[-1]),
-                                     v.ctypes.data_as(C.POINTER(C.c_float)))
-
-        tabs = _lib.fspb_tables(tab(tables.A), int(tables.n_theta), float(tables.theta_step),
-                                *[tab(getattr(tables, n)) for n in (
-                                    "u1x", "u1y", "u2x", "u2y", "w1", "w2",
-                                    "fu1", "fu2", "fw1", "fw2", "b1", "b2")])
+        tabs = _marshal_tables(tables)
         opt_p = None
         if options is not None:
             o = options

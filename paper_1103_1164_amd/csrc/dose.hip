@@ -43,15 +43,13 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // Forward pass over one brick, three modes sharing the candidate search:
 //   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
 //   kCount  number of evaluated pairs per voxel
-//   kCost   number of beamlets in the brick's candidate rectangles
-//           (scheduling estimate)
 //   kSurr   the dose with the learned surrogate's parameters: per (voxel,
 //           beam) row prm[2 (b n_vox + v) + 0..1] = ((u1x, u1y, u2x, u2y)
 //           log2 e, (w1, w2, fallback, 0)); a row whose fallback flag is set
 //           takes the density-corrected pair instead
 // A brick is BX x BY x BZ = 64 voxels, one per lane.
 //   kSid    the dose with the exact (Siddon) depth tables
-enum { kDose = 0, kCount = 1, kCost = 2, kSurr = 3, kSid = 4 };
+enum { kDose = 0, kCount = 1, kSurr = 3, kSid = 4 };
 
 template <int BX, int BY, int BZ>
 __device__ __forceinline__ int bricks_x(const PlanConst& P) { return (P.nx + BX - 1) / BX; }
@@ -106,7 +104,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     const float Rc2 = Rc * Rc;
 
     float acc = 0.0f;
-    int cnt = 0, cost = 0;
+    int cnt = 0;
     const FSPB_GLOBAL float4* __restrict__ prm = as_global(prm_);
     const long n_vox = (long)P.nx * P.ny * P.nz;
     for (int b = 0; b < P.n_beams; ++b) {
@@ -144,12 +142,6 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
         const int first = uniform(B.first), nbl_x = uniform(B.nbx);
         const int nm = m_hi - m_lo + 1;
         const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
-        if (MODE == kCost) {
-            // scheduling estimate: the size of the candidate rectangle (the
-            // sphere filter below is left out; it only sharpens the count)
-            cost += total;
-            continue;
-        }
         float accb = 0.0f;
         for (int base = 0; base < total; base += kWave) {
             // 64 candidates at once: one per lane, tested against the brick's
@@ -215,9 +207,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
         }
         acc += accb;
     }
-    if (MODE == kCost) {
-        if (lane == 0) out_int[brick] = cost;
-    } else if (valid) {
+    if (valid) {
         if (MODE == kCount)
             out_int[v] = cnt;
         else
@@ -530,8 +520,52 @@ void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float*
     launch_mode<false, kCount>(a, cfg, order, fluence, nullptr, counts, s);
 }
 
+// Scheduling estimate, one thread per brick: the brick's bounding sphere is
+// projected onto each beam's isocentre plane (at its nearest depth, so the
+// projection is not too small) and padded by the ROI reach; the estimate is
+// the number of beamlet centres in the padded square.  Only the order of
+// the bricks depends on it.
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void brick_cost_kernel(DoseArgs a, int* __restrict__ cost) {
+    const PlanConst& P = a.P;
+    const int brick = blockIdx.x * blockDim.x + threadIdx.x;
+    if (brick >= bricks_total<BX, BY, BZ>(P)) return;
+    const int nbx = bricks_x<BX, BY, BZ>(P), nby = bricks_y<BX, BY, BZ>(P);
+    const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
+    float cqx, cqy, cqz;
+    voxel_q(P, bx * BX, by * BY, bz * BZ, cqx, cqy, cqz);
+    const float hx = 0.5f * (BX - 1) * P.dx, hy = 0.5f * (BY - 1) * P.dy, hz = 0.5f * (BZ - 1) * P.dz;
+    cqx += hx;
+    cqy += hy;
+    cqz += hz;
+    const float rb = sqrtf(hx * hx + hy * hy + hz * hz);
+    int c = 0;
+    for (int b = 0; b < P.n_beams; ++b) {
+        const BeamDesc& B = a.beams[b];
+        const float vx = cqx - B.src[0], vy = cqy - B.src[1], vz = cqz - B.src[2];
+        const float z = vx * B.cax[0] + vy * B.cax[1] + vz * B.cax[2];
+        const float zn = fmaxf(z - rb, 1e-3f);
+        const float pa = (vx * B.ex[0] + vy * B.ex[1] + vz * B.ex[2]) * B.sad / z;
+        const float pb = (vx * B.ey[0] + vy * B.ey[1] + vz * B.ey[2]) * B.sad / z;
+        const float half = (rb * B.sad + B.pad_scale) / zn;
+        const int m_lo = max((int)ceilf((pa - half - B.a0) / B.wx), 0);
+        const int m_hi = min((int)floorf((pa + half - B.a0) / B.wx), B.nbx - 1);
+        const int n_lo = max((int)ceilf((pb - half - B.b0) / B.wy), 0);
+        const int n_hi = min((int)floorf((pb + half - B.b0) / B.wy), B.nby - 1);
+        if (m_hi >= m_lo && n_hi >= n_lo) c += (m_hi - m_lo + 1) * (n_hi - n_lo + 1);
+    }
+    cost[brick] = c;
+}
+
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s) {
-    launch_mode<false, kCost>(a, cfg, nullptr, nullptr, nullptr, cost, s);
+    const long nb = brick_count(a.P, cfg.shape);
+    const dim3 grid((unsigned)((nb + 255) / 256)), block(256);
+    switch (cfg.shape) {
+        case 0: hipLaunchKernelGGL((brick_cost_kernel<4, 4, 4>), grid, block, 0, s, a, cost); break;
+        case 1: hipLaunchKernelGGL((brick_cost_kernel<8, 4, 2>), grid, block, 0, s, a, cost); break;
+        case 2: hipLaunchKernelGGL((brick_cost_kernel<4, 8, 2>), grid, block, 0, s, a, cost); break;
+        case 3: hipLaunchKernelGGL((brick_cost_kernel<8, 2, 4>), grid, block, 0, s, a, cost); break;
+    }
 }
 
 void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
