@@ -66,7 +66,11 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                            const float4* prm_ = nullptr) {
     static_assert(MODE != kSurr || DC, "the surrogate replaces the density-corrected parameters");
     static_assert(BX * BY * BZ == kWave, "a brick holds one voxel per lane");
-    const PlanConst& P = a.P;
+    // The table offsets are held in vector registers: an FMA may read only one
+    // scalar operand, and t * inv + off with both scalars would cost a move
+    // per pair.
+    PlanConst P = a.P;
+    asm volatile("" : "+v"(P.dt_off), "+v"(P.at_off));
     const FSPB_CONST BeamDesc* __restrict__ beams = as_const(a.beams);
     const FSPB_CONST BeamletDesc* __restrict__ bl = as_const(a.bl);
     const FSPB_GLOBAL float4* __restrict__ bl4 = as_global(reinterpret_cast<const float4*>(a.bl));
@@ -75,6 +79,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     const FSPB_GLOBAL float4* __restrict__ atab = as_global(a.atab);
     const FSPB_GLOBAL float2* __restrict__ tT = as_global(a.tT);
     const FSPB_GLOBAL float4* __restrict__ tTW = as_global(a.tTW);
+    const FSPB_GLOBAL float2* __restrict__ tW2 = as_global(a.tW2);
     const FSPB_GLOBAL float4* __restrict__ sid = as_global(a.sid);
     const FSPB_GLOBAL float* __restrict__ fluence = as_global(fluence_);
     FSPB_GLOBAL float* __restrict__ dose = as_global_rw(dose_);
@@ -172,7 +177,9 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
             const int pk_ib = __builtin_amdgcn_ds_permute(dst << 2, ib);
             const int pk_f = __builtin_amdgcn_ds_permute(dst << 2, __float_as_int(fi));
             // software pipeline: the next candidate's descriptor is fetched
-            // (scalar loads) while the current one is evaluated
+            // (scalar loads) while the current one is evaluated; the fluences
+            // travel in a vector register (a scalar load per candidate would
+            // add to the descriptor stream through the shared scalar cache)
             BeamletDesc dn = bl[__builtin_amdgcn_readlane(pk_ib, 0)];
             for (int e = 0; e < ncand; ++e) {
                 const BeamletDesc d = dn;
@@ -193,14 +200,14 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                         accb = fmaf(fe, pair_dose_given(t, xp, yp, kmag, d, s_ul, s_w, P, atab, tTW),
                                     accb);
                     else if (act)
-                        accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
+                        accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW, tW2),
                                     accb);
                 } else if (MODE == kSid) {
                     if (act)
                         accb = fmaf(fe, pair_dose_siddon<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, sid),
                                     accb);
                 } else if (act) {
-                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW),
+                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW, tW2),
                                 accb);
                 }
             }
@@ -379,7 +386,8 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                     if (DC) fac = facs[v];
                     acc = fmaf(wv[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
                                                     as_global(a.dtab), as_global(a.atab),
-                                                    as_global(a.tT), as_global(a.tTW)),
+                                                    as_global(a.tT), as_global(a.tTW),
+                                                    as_global(a.tW2)),
                                acc);
                 }
             }

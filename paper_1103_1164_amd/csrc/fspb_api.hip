@@ -195,7 +195,8 @@ struct fspb_geometry {
     float4* atab = nullptr;
     float* denstab = nullptr;
     float2* tT = nullptr;
-    float4* tTW = nullptr;    // DC only: interleaved depth + weight-drift records
+    float4* tTW = nullptr;    // DC only: depth + first weight-drift table (16-byte entries)
+    float2* tW2 = nullptr;    // DC only: second weight-drift table (8-byte entries, same index)
     float4* sid = nullptr;    // exact (Siddon) depth tables, when the plan asks for them
     int siddon = 0, sid_stride = 0;
     float* w3 = nullptr;
@@ -241,6 +242,7 @@ struct fspb_geometry {
         a.atab = atab;
         a.tT = tT;
         a.tTW = tTW;
+        a.tW2 = tW2;
         a.sid = sid;
         return a;
     }
@@ -412,9 +414,13 @@ static int fetch_cost(fspb_geometry* G, hipStream_t s) {
 
 // Packs the commissioned tables into the kernels' layouts (once per
 // distinct set and device):
-//   dtab[3j..3j+2]: (u1x, u1y, u2x, u2y) log2 e at depth sample j, their
-//                   slopes to sample j+1, and (w1, w2, w1', w2')
-//   atab[j a_cols + r]: (A[r][j], A[r+1][j], A[r][j+1]-A[r][j], A[r+1][j+1]-A[r+1][j])
+//   dtab[j], dtab[n + j], dtab[2n + j] (n samples): (u1x, u1y, u2x, u2y) log2 e
+//                   at depth sample j, their slopes to sample j+1, and
+//                   (w1, w2, w1', w2') -- three planes, 16-byte stride
+//   atab[r n_A + j]: (a, b, c, e) / 4 with a = A[r][j], b = A[r+1][j] - a,
+//                   c = A[r][j+1] - a, e = A[r+1][j+1] - A[r+1][j] - c, for
+//                   theta rows r < a_cols and depth samples j < n_A; the 1/4
+//                   is the product of the two factors 1/2 of Eq. 4's profiles
 //   denstab: the six density tables back to back (offsets in dens)
 static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** out) {
     std::vector<uint32_t> key;
@@ -458,9 +464,9 @@ static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** 
             u[q] = (float)(at(*U[q], j) * 1.4426950408889634);
             du[q] = (float)((at(*U[q], j + 1) - at(*U[q], j)) * 1.4426950408889634);
         }
-        dtab[3 * j + 0] = make_float4(u[0], u[1], u[2], u[3]);
-        dtab[3 * j + 1] = make_float4(du[0], du[1], du[2], du[3]);
-        dtab[3 * j + 2] = make_float4(t->w1.v[j], t->w2.v[j], (float)(at(t->w1, j + 1) - at(t->w1, j)),
+        dtab[j] = make_float4(u[0], u[1], u[2], u[3]);
+        dtab[dn + j] = make_float4(du[0], du[1], du[2], du[3]);
+        dtab[2 * dn + j] = make_float4(t->w1.v[j], t->w2.v[j], (float)(at(t->w1, j + 1) - at(t->w1, j)),
                                       (float)(at(t->w2, j + 1) - at(t->w2, j)));
     }
     const int an = t->A.n, nth = t->n_theta, ac = a_cols;
@@ -468,11 +474,13 @@ static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** 
     auto A = [&](int r, int j) {
         return (double)t->A.v[(size_t)std::min(r, nth - 1) * an + std::min(j, an - 1)];
     };
-    for (int j = 0; j < an; ++j)
-        for (int r = 0; r < ac; ++r)
-            atab[(size_t)j * ac + r] = make_float4((float)A(r, j), (float)A(r + 1, j),
-                                                   (float)(A(r, j + 1) - A(r, j)),
-                                                   (float)(A(r + 1, j + 1) - A(r + 1, j)));
+    // each entry is formed in FP64 and rounded to FP32 once
+    for (int r = 0; r < ac; ++r)
+        for (int j = 0; j < an; ++j)
+            atab[(size_t)r * an + j] = make_float4(
+                (float)(0.25 * A(r, j)), (float)(0.25 * (A(r + 1, j) - A(r, j))),
+                (float)(0.25 * (A(r, j + 1) - A(r, j))),
+                (float)(0.25 * ((A(r + 1, j + 1) - A(r + 1, j)) - (A(r, j + 1) - A(r, j)))));
     TableSet* ts = new (std::nothrow) TableSet();
     if (!ts) return fail(FSPB_E_NOMEM, "host allocation failed");
     ts->device = dev;
@@ -685,7 +693,9 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     ALLOC(G->order, sizeof(int) * max_bricks);
     ALLOC(G->cost, sizeof(int) * max_bricks);
     if (o.dc_enabled) {
-        ALLOC(G->tTW, 2 * sizeof(float4) * (size_t)nbl * G->k_stride);
+        // one block: the 16-byte plane, then the 8-byte plane
+        ALLOC(G->tTW, (sizeof(float4) + sizeof(float2)) * (size_t)nbl * G->k_stride);
+        G->tW2 = reinterpret_cast<float2*>(G->tTW + (size_t)nbl * G->k_stride);
         ALLOC(G->rhohat, sizeof(float) * nv);
         ALLOC(G->fac, sizeof(float4) * nv);
     }
@@ -732,9 +742,10 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     tp.theta_step = t->n_theta > 1 ? (double)t->theta_step : 1.0;
     for (int q = 0; q < 3; ++q) tp.p0[q] = P0[q];
     tp.n_theta = t->n_theta;
+    tp.n_A = t->A.n;
     tp.k_stride = G->k_stride;
-    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->desc,
-                 G->tinfo, s);
+    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->tW2,
+                 G->desc, G->tinfo, s);
     HIP_TRY(hipGetLastError());
     if (G->siddon) {
         // exact tables replace the uniform samples (records, entrance, K)
@@ -904,12 +915,13 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
         if (T)
             for (int j = 0; j < n; ++j) T[j] = tt[j].x;
         if ((W1 || W2) && g->tTW) {
-            std::vector<float4> tw(2 * (size_t)n);
-            HIP_TRY(hipMemcpy(tw.data(), g->tTW + 2 * (size_t)d.tab_off, 2 * sizeof(float4) * n,
-                              hipMemcpyDeviceToHost));
+            std::vector<float4> tw(n);
+            std::vector<float2> tw2(n);
+            HIP_TRY(hipMemcpy(tw.data(), g->tTW + d.tab_off, sizeof(float4) * n, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(tw2.data(), g->tW2 + d.tab_off, sizeof(float2) * n, hipMemcpyDeviceToHost));
             for (int j = 0; j < n; ++j) {
-                if (W1) W1[j] = tw[2 * j].z;
-                if (W2) W2[j] = tw[2 * j + 1].x;
+                if (W1) W1[j] = tw[j].z;
+                if (W2) W2[j] = tw2[j].x;
             }
         }
     }
@@ -1037,7 +1049,7 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
         HIP_TRY(hipGetLastError());
     }
     launch_trace(g->frames, g->n_beamlets, density, g->tg, g->tp, g->denstab, g->dens, g->tT,
-                 g->tTW, g->desc, g->tinfo, s);
+                 g->tTW, g->tW2, g->desc, g->tinfo, s);
     HIP_TRY(hipGetLastError());
     if (g->siddon) {
         launch_siddon(g->frames, g->n_beamlets, density, g->tg, g->tp, g->sid_stride, g->denstab,

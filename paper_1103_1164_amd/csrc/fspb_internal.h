@@ -30,7 +30,9 @@ struct Frame64 {
 //   t  = q.d  + c_t   depth below the entrance (s - s_entry)
 //   xp = q.ex + c_x   lateral offsets from the axis
 //   yp = q.ey + c_y
-// with q = r - P0.  96 bytes, read with scalar loads (wave-uniform index).
+// with q = r - P0.  96 bytes, read with scalar loads (wave-uniform index);
+// everything the uniform-table pair arithmetic reads sits in the first 80
+// bytes (one 64-byte and one 16-byte scalar load).
 struct alignas(16) BeamletDesc {
     float d[3];
     float c_t;
@@ -42,13 +44,13 @@ struct alignas(16) BeamletDesc {
     float sad;
     float x0, y0;      // beamlet half widths at the isocentre plane (Eq. 4)
     float th_frac;     // A-table theta interpolation weight
-    int th_col;        // A-table column (theta row r, r+1 interleaved)
+    int a_off;         // first A-table record of the beamlet's theta rows (r, r+1): r n_A
     int tab_off;       // first sample of this beamlet's depth tables
-    int K;             // depth-table length (0 if the beamlet misses the body)
+    int j_last;        // last usable depth-table interval, max(K - 2, 0)
     int hit;
     float theta;       // angle to the beam's central axis
     int beam;          // index of the beam the beamlet belongs to
-    int pad;
+    int K;             // depth-table length (0 if the beamlet misses the body)
 };
 static_assert(sizeof(BeamletDesc) == 96, "BeamletDesc layout");
 

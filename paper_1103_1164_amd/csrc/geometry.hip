@@ -214,6 +214,7 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
                                                  TraceGrid g, TraceParams tp,
                                                  const float* __restrict__ dtabs, DensTabs dt,
                                                  float2* __restrict__ tT, float4* __restrict__ tTW,
+                                                 float2* __restrict__ tW2,
                                                  BeamletDesc* __restrict__ desc,
                                                  TraceInfo* __restrict__ info) {
     int lane = threadIdx.x & (kWave - 1);
@@ -260,14 +261,14 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
     o.sad = (float)f.sad;
     o.theta = (float)f.theta;
     o.beam = f.beam;
-    o.pad = 0;
+    o.j_last = 0;
     o.x0 = (float)f.x0;
     o.y0 = (float)f.y0;
     {
         double c = f.theta / tp.theta_step;
         c = fmin(fmax(c, 0.0), (double)(tp.n_theta - 1));
         int r = (tp.n_theta > 1) ? min((int)floor(c), tp.n_theta - 2) : 0;
-        o.th_col = r;
+        o.a_off = r * tp.n_A;
         o.th_frac = (tp.n_theta > 1) ? (float)(c - r) : 0.0f;
     }
     o.tab_off = ib * tp.k_stride;
@@ -285,6 +286,7 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
     const double s_entry = f.s_in + ke * d;
     o.hit = 1;
     o.K = K;
+    o.j_last = max(K - 2, 0);
     o.s_entry = (float)s_entry;
     o.c_t = (float)(v0[0] * f.d[0] + v0[1] * f.d[1] + v0[2] * f.d[2] - s_entry);
     ti.s_entry = s_entry;
@@ -309,8 +311,8 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
         if (j < K) {
             tT[o.tab_off + j] = make_float2((float)T, (float)iT);
             if (tTW) {
-                tTW[2 * (o.tab_off + j)] = make_float4((float)T, (float)iT, (float)W1, (float)i1);
-                tTW[2 * (o.tab_off + j) + 1] = make_float4((float)W2, (float)i2, 0.0f, 0.0f);
+                tTW[o.tab_off + j] = make_float4((float)T, (float)iT, (float)W1, (float)i1);
+                tW2[o.tab_off + j] = make_float2((float)W2, (float)i2);
             }
         }
         cT += __shfl(sT, kWave - 1, kWave);
@@ -391,6 +393,7 @@ __global__ __launch_bounds__(256) void siddon_trace(const Frame64* __restrict__ 
     s_in = fmax(s_in, 0.0);
     o.hit = 0;
     o.K = 0;
+    o.j_last = 0;
     o.c_t = -1e30f;
     o.tab_off = ib * stride;
     if (!miss && s_in < s_out) {
@@ -450,6 +453,7 @@ __global__ __launch_bounds__(256) void siddon_trace(const Frame64* __restrict__ 
             for (int a = 0; a < 3; ++a) v0[a] = tp.p0[a] - f.src[a];
             o.hit = 1;
             o.K = K;
+            o.j_last = max(K - 2, 0);
             o.s_entry = (float)s_entry;
             o.c_t = (float)(v0[0] * f.d[0] + v0[1] * f.d[1] + v0[2] * f.d[2] - s_entry);
             ti.s_entry = s_entry;
@@ -468,11 +472,11 @@ void launch_siddon(const Frame64* frames, int n_beamlets, const float* rho, cons
 
 void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
                   const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
-                  float4* tTW, BeamletDesc* desc, TraceInfo* info, hipStream_t s) {
+                  float4* tTW, float2* tW2, BeamletDesc* desc, TraceInfo* info, hipStream_t s) {
     int waves_per_block = 4;
     int blocks = (n_beamlets + waves_per_block - 1) / waves_per_block;
     hipLaunchKernelGGL(ray_trace, dim3(blocks), dim3(waves_per_block * kWave), 0, s, frames,
-                       n_beamlets, rho, g, tp, dtabs, dt, tT, tTW, desc, info);
+                       n_beamlets, rho, g, tp, dtabs, dt, tT, tTW, tW2, desc, info);
 }
 
 }  // namespace fspb

@@ -20,7 +20,7 @@ struct TraceGrid {
 struct TraceParams {
     double step, rho_surface, theta_step;
     double p0[3];
-    int n_theta, k_stride;
+    int n_theta, n_A, k_stride;
 };
 
 // Per-beamlet ray-trace results kept for inspection.
@@ -36,7 +36,7 @@ void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double
                   const double hi[3], double step, Frame64* out, hipStream_t s);
 void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
                   const TraceParams& tp, const float* dtabs, const DensTabs& dt, float2* tT,
-                  float4* tTW, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
+                  float4* tTW, float2* tW2, BeamletDesc* desc, TraceInfo* info, hipStream_t s);
 
 // Exact (Siddon) depth tables instead of the uniform samples: per beamlet,
 // one 32-byte record per voxel segment past the entrance,
@@ -58,6 +58,7 @@ struct DoseArgs {
     const float4* atab;
     const float2* tT;
     const float4* tTW;
+    const float2* tW2;
     const float4* sid;     // exact depth tables (null unless the plan uses them)
 };
 

@@ -517,7 +517,7 @@ __global__ __launch_bounds__(256) void surrogate_samples_kernel(DoseArgs a,
         float out[kMlpOut] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (r.valid) {
             const BeamletDesc& d = a.bl[r.ib];
-            dc_params(r.t, d, a.fac[r.v], a.P, a.dtab, a.tTW, out);
+            dc_params(r.t, d, a.fac[r.v], a.P, a.dtab, a.tTW, a.tW2, out);
         }
 #pragma unroll
         for (int c = 0; c < kMlpOut; ++c) T[row * kMlpOut + c] = out[c];

@@ -2,14 +2,24 @@
 // density corrections, in FP32 VALU arithmetic for gfx950.
 //
 // Table layouts (built by the host, see fspb_api.hip):
-//   dtab[3*j + 0] = (u1x, u1y, u2x, u2y)(t_j) * log2(e)     water steepness
-//   dtab[3*j + 1] = slopes of the above to sample j+1
-//   dtab[3*j + 2] = (w1, w2, w1', w2')                      water weights + slopes
-//   atab[j*a_cols + r] = (A[r][j], A[r+1][j], A[r][j+1]-A[r][j], A[r+1][j+1]-A[r+1][j])
-//   tT[off + j] = (T_j, T_{j+1} - T_j)                       radiological depth
-//   tTW[2(off + j)]     = (T_j, T_{j+1} - T_j, W1_j, W1_{j+1} - W1_j)
-//   tTW[2(off + j) + 1] = (W2_j, W2_{j+1} - W2_j, 0, 0)      depth + weight drift,
-//                         one 32-byte record so both halves share a cache line
+//   dtab[j]          = (u1x, u1y, u2x, u2y)(t_j) * log2(e)  water steepness
+//   dtab[n + j]      = slopes of the above to sample j+1
+//   dtab[2n + j]     = (w1, w2, w1', w2')                   water weights + slopes
+//                      (n = dt_n; three planes with a 16-byte stride: lanes
+//                      at nearby depths read neighbouring 16-byte words, where
+//                      a 64-byte record stride makes every lane's read start
+//                      at the same offset of a 64-byte block and measured
+//                      about 1.45x slower)
+//   atab[r*n_A + j] = (a, b, c, e) / 4 with a = A[r][j], b = A[r+1][j] - a,
+//                   c = A[r][j+1] - a, e = A[r+1][j+1] - A[r+1][j] - c: the
+//                   bilinear A(j + fa, r + fr) = a + fr b + fa (c + fr e)
+//                   (theta rows r, r+1; the 1/4 is the product of the
+//                   factors 1/2 of both Eq. 4 profiles)
+//   tT[off + j]  = (T_j, T_{j+1} - T_j)                      radiological depth
+//   tTW[off + j] = (T_j, T_{j+1} - T_j, W1_j, W1_{j+1} - W1_j) depth + weight drift
+//   tW2[off + j] = (W2_j, W2_{j+1} - W2_j)                    second weight drift
+//                  (two planes, 16- and 8-byte strides, rather than one
+//                  32-byte record)
 #pragma once
 
 #include "fspb_internal.h"
@@ -59,7 +69,8 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // non-positive, so nothing overflows.  ul = u * log2(e); dm = | |x| - x0 |,
 // dp = |x| + x0, outer = (|x| > x0).
 // Returns 2 p = sg e1 + (o2 - e2) with (sg, o2) = (1, 0) outside the box and
-// (-1, 2) inside; the factors 1/2 of both axes are applied once per pair.
+// (-1, 2) inside (at |x| = x0 both forms agree); the factors 1/2 of both axes
+// are folded into the A table.
 __device__ __forceinline__ float penumbra2(float ul, float dm, float dp, float sg, float o2) {
     float e1 = fast_exp2(-ul * dm);
     float e2 = fast_exp2(-ul * dp);
@@ -107,10 +118,11 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
                                            const FSPB_GLOBAL float4* __restrict__ dtab,
                                            const FSPB_GLOBAL float4* __restrict__ atab,
                                            const FSPB_GLOBAL float2* __restrict__ tT,
-                                           const FSPB_GLOBAL float4* __restrict__ tTW) {
+                                           const FSPB_GLOBAL float4* __restrict__ tTW,
+                                           const FSPB_GLOBAL float2* __restrict__ tW2) {
     // magnification to the isocentre plane and inverse square (Eq. 2)
     float x = xp * k, y = yp * k;
-    float isq = k * (0.25f * k);   // (SAD/|r_a|)^2 times the 1/4 of the two 2p factors
+    float isq = k * k;   // (SAD/|r_a|)^2; the 1/4 of the two 2p factors is in A
 
     // Every lookup below except A's depends on t only: issue those loads
     // first so that they share one memory latency, then A's (which needs t_eq).
@@ -119,20 +131,22 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     // end value.
     // water parameters at geometric depth t
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
-    const unsigned od = 48u * (unsigned)cd;             // 3 float4 per depth sample
+    const unsigned od = (unsigned)cd << 4;              // 16-byte entries, three planes
     const float fd = fract(cd);
-    const float4 u0 = load_at(dtab, od), us = load_at(dtab, od + 16u), wv = load_at(dtab, od + 32u);
+    const float4 u0 = load_at(dtab, od), us = load_at(dtab + P.dt_n, od),
+                 wv = load_at(dtab + 2 * P.dt_n, od);
 
     // per-beamlet radiological depth and weight drift at depth t (Section 2.2);
-    // t >= 0 and voxel centres never reach the last table interval
+    // t >= 0 (the pair test), so the sample index needs no lower clamp, and
+    // voxel centres never reach the last table interval (j_last = max(K - 2, 0))
     const float c = t * P.inv_d;
-    const int j = max(min((int)c, b.K - 2), 0);
+    const int j = min((int)c, b.j_last);
     const float f = fract(c);
     float teq, W1 = 0.0f, W2 = 0.0f;
     if (DC) {
-        const unsigned ot = 32u * (unsigned)(b.tab_off + j);   // one 32-byte record
-        const float4 r0 = load_at(tTW, ot);
-        const float2 r1 = load_at(reinterpret_cast<const FSPB_GLOBAL float2*>(tTW), ot + 16u);
+        const unsigned ot = (unsigned)(b.tab_off + j);
+        const float4 r0 = load_at(tTW, 16u * ot);
+        const float2 r1 = load_at(tW2, 8u * ot);
         teq = fmaf(f, r0.y, r0.x);
         W1 = fmaf(f, r0.w, r0.z);
         W2 = fmaf(f, r1.y, r1.x);
@@ -141,11 +155,10 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
         teq = fmaf(f, te.y, te.x);
     }
 
-    // A(t_eq, theta): bilinear, theta column fixed per beamlet
+    // A(t_eq, theta) / 4: bilinear, theta rows fixed per beamlet
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
     const float fa = fract(ca);
-    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
-                                        16u * (unsigned)b.th_col);
+    const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
 
     float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
     float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
@@ -162,15 +175,15 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
         w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
     }
 
-    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
-    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
+    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
 
     // Eq. 3 with the Eq. 4 profiles
-    float ax = fabsf(x), ay = fabsf(y);
-    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
-    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
-    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
-    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
+    const float dmx = fabsf(ox), dpx = ax + b.x0;
+    const float dmy = fabsf(oy), dpy = ay + b.y0;
+    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
+    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
     float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
     float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
     float F = fmaf(w1, p1, w2 * p2);
@@ -189,11 +202,12 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
                                                   const FSPB_GLOBAL float4* __restrict__ atab,
                                                   const FSPB_GLOBAL float4* __restrict__ sid) {
     float x = xp * k, y = yp * k;
-    float isq = k * (0.25f * k);
+    float isq = k * k;
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
-    const unsigned od = 48u * (unsigned)cd;
+    const unsigned od = (unsigned)cd << 4;
     const float fd = fract(cd);
-    const float4 u0 = load_at(dtab, od), us = load_at(dtab, od + 16u), wv = load_at(dtab, od + 32u);
+    const float4 u0 = load_at(dtab, od), us = load_at(dtab + P.dt_n, od),
+                 wv = load_at(dtab + 2 * P.dt_n, od);
     const FSPB_GLOBAL float4* rec = sid + 2 * (long)b.tab_off;
     int lo = 0, hi = b.K - 1;
     while (lo < hi) {
@@ -212,8 +226,7 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
     }
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
     const float fa = fract(ca);
-    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
-                                        16u * (unsigned)b.th_col);
+    const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
     float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
     float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
     float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
@@ -225,13 +238,13 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
         w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
         w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
     }
-    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
-    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
-    float ax = fabsf(x), ay = fabsf(y);
-    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
-    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
-    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
-    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
+    const float dmx = fabsf(ox), dpx = ax + b.x0;
+    const float dmy = fabsf(oy), dpy = ay + b.y0;
+    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
+    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
     float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
     float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
     float F = fmaf(w1, p1, w2 * p2);
@@ -245,16 +258,17 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
 template <class BD>
 __device__ __forceinline__ void dc_params(float t, const BD& b, float4 fac, const PlanConst& P,
                                           const float4* __restrict__ dtab,
-                                          const float4* __restrict__ tTW, float out[6]) {
+                                          const float4* __restrict__ tTW,
+                                          const float2* __restrict__ tW2, float out[6]) {
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
     const int jd = (int)cd;
     const float fd = fract(cd);
-    const float4 u0 = dtab[3 * jd], us = dtab[3 * jd + 1], wv = dtab[3 * jd + 2];
+    const float4 u0 = dtab[jd], us = dtab[P.dt_n + jd], wv = dtab[2 * P.dt_n + jd];
     const float c = t * P.inv_d;
     const int j = max(min((int)c, b.K - 2), 0);
     const float f = fract(c);
-    const float4 r0 = tTW[2 * (b.tab_off + j)];
-    const float4 r1 = tTW[2 * (b.tab_off + j) + 1];
+    const float4 r0 = tTW[b.tab_off + j];
+    const float2 r1 = tW2[b.tab_off + j];
     const float W1 = fmaf(f, r0.w, r0.z), W2 = fmaf(f, r1.y, r1.x);
     const float inv_l2e = 1.0f / kLog2e;
     out[0] = fmaf(fd, us.x, u0.x) * fac.x * inv_l2e;
@@ -276,23 +290,22 @@ __device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, fl
                                                  const FSPB_GLOBAL float4* __restrict__ atab,
                                                  const FSPB_GLOBAL float4* __restrict__ tTW) {
     float x = xp * k, y = yp * k;
-    float isq = k * (0.25f * k);
+    float isq = k * k;
     const float c = t * P.inv_d;
-    const int j = max(min((int)c, b.K - 2), 0);
+    const int j = min((int)c, b.j_last);   // t >= 0 (the pair test)
     const float f = fract(c);
-    const float4 r0 = load_at(tTW, 32u * (unsigned)(b.tab_off + j));
+    const float4 r0 = load_at(tTW, 16u * (unsigned)(b.tab_off + j));
     const float teq = fmaf(f, r0.y, r0.x);
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
     const float fa = fract(ca);
-    const float4 ae = load_at(atab, 16u * __umul24((unsigned)ca, (unsigned)P.a_cols) +
-                                        16u * (unsigned)b.th_col);
-    float a_lo = fmaf(fa, ae.z, ae.x), a_hi = fmaf(fa, ae.w, ae.y);
-    float A = fmaf(b.th_frac, a_hi - a_lo, a_lo);
-    float ax = fabsf(x), ay = fabsf(y);
-    float dmx = fabsf(ax - b.x0), dpx = ax + b.x0;
-    float dmy = fabsf(ay - b.y0), dpy = ay + b.y0;
-    const float sgx = ax > b.x0 ? 1.0f : -1.0f, o2x = 1.0f - sgx;
-    const float sgy = ay > b.y0 ? 1.0f : -1.0f, o2y = 1.0f - sgy;
+    const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
+    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
+    const float dmx = fabsf(ox), dpx = ax + b.x0;
+    const float dmy = fabsf(oy), dpy = ay + b.y0;
+    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
+    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
     float p1 = penumbra2(ul.x, dmx, dpx, sgx, o2x) * penumbra2(ul.y, dmy, dpy, sgy, o2y);
     float p2 = penumbra2(ul.z, dmx, dpx, sgx, o2x) * penumbra2(ul.w, dmy, dpy, sgy, o2y);
     float F = fmaf(wv.x, p1, wv.y * p2);
