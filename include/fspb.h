@@ -229,10 +229,13 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream);
 /* ---- forward-kernel tiling and autotuning -------------------------------
  * The forward kernel assigns one 64-voxel brick to each wavefront.  Brick
  * shapes (voxels along x, y, z) are listed by fspb_tile_shapes; a tile
- * configuration is a shape index and 1, 2 or 4 waves per workgroup (a new
- * handle starts with shape 0, 4 x 4 x 4 voxels, and 4 waves).  Results do
- * not depend on the configuration (each voxel sums its pairs in the same
- * order). */
+ * configuration is a shape index and 1, 2, 4 or 8 waves per workgroup.  With
+ * 8, each workgroup stages the water (depth) table in LDS when it fits in
+ * 64 KB, i.e. up to 1365 depth samples (else that launch uses 4 waves and
+ * reads the table from global memory).  A new handle starts with shape 0,
+ * 4 x 4 x 4 voxels, and 8 waves.  Results do not depend on the
+ * configuration (each voxel sums its pairs in the same order, from the same
+ * table values). */
 typedef struct {
     int shape;            /* shape index */
     int dims[3];          /* brick voxels along x, y, z */
@@ -270,7 +273,10 @@ typedef struct fspb_batch fspb_batch;
 
 /* geoms: host array [n] of handles.  shape / waves_per_block: tile
  * configuration of the persistent kernel (plans are re-scheduled for that
- * shape).  policy: FSPB_SCHEDULE_THROUGHPUT minimises the whole launch;
+ * shape); with 8 waves per workgroup the water table is staged in LDS when
+ * every plan uses the same commissioned tables and it fits (as for
+ * fspb_set_tile), else the launch uses 4 waves per workgroup.  policy:
+ * FSPB_SCHEDULE_THROUGHPUT minimises the whole launch;
  * FSPB_SCHEDULE_LATENCY lets small plans complete first.  Synchronises the
  * stream. */
 int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_per_block,

@@ -307,7 +307,7 @@ class Batch:
     """Many plans in one persistent launch (static longest-first schedule),
     with per-plan completion times and optional HIP-graph capture."""
 
-    def __init__(self, geometries, shape: int = 0, waves_per_block: int = 4,
+    def __init__(self, geometries, shape: int = 0, waves_per_block: int = 8,
                  waves_per_cu: int = 32, policy: str = "latency", stream=None):
         self.geometries = list(geometries)
         n = len(self.geometries)

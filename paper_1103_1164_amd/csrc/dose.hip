@@ -60,10 +60,10 @@ __device__ __forceinline__ int bricks_total(const PlanConst& P) {
     return bricks_x<BX, BY, BZ>(P) * bricks_y<BX, BY, BZ>(P) * ((P.nz + BZ - 1) / BZ);
 }
 
-template <bool DC, int MODE, int BX, int BY, int BZ>
+template <bool DC, int MODE, int BX, int BY, int BZ, class WT>
 __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                            const float* fluence_, float* dose_, int* out_int_,
-                                           const float4* prm_ = nullptr) {
+                                           const WT& water, const float4* prm_ = nullptr) {
     static_assert(MODE != kSurr || DC, "the surrogate replaces the density-corrected parameters");
     static_assert(BX * BY * BZ == kWave, "a brick holds one voxel per lane");
     // The table offsets are held in vector registers: an FMA may read only one
@@ -75,7 +75,6 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     const FSPB_CONST BeamletDesc* __restrict__ bl = as_const(a.bl);
     const FSPB_GLOBAL float4* __restrict__ bl4 = as_global(reinterpret_cast<const float4*>(a.bl));
     const FSPB_GLOBAL float4* __restrict__ facs = as_global(a.fac);
-    const FSPB_GLOBAL float4* __restrict__ dtab = as_global(a.dtab);
     const FSPB_GLOBAL float4* __restrict__ atab = as_global(a.atab);
     const FSPB_GLOBAL float2* __restrict__ tT = as_global(a.tT);
     const FSPB_GLOBAL float4* __restrict__ tTW = as_global(a.tTW);
@@ -200,14 +199,14 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                         accb = fmaf(fe, pair_dose_given(t, xp, yp, kmag, d, s_ul, s_w, P, atab, tTW),
                                     accb);
                     else if (act)
-                        accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW, tW2),
+                        accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, water, atab, tT, tTW, tW2),
                                     accb);
                 } else if (MODE == kSid) {
                     if (act)
-                        accb = fmaf(fe, pair_dose_siddon<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, sid),
+                        accb = fmaf(fe, pair_dose_siddon<DC>(t, xp, yp, kmag, d, fac, P, water, atab, sid),
                                     accb);
                 } else if (act) {
-                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, dtab, atab, tT, tTW, tW2),
+                    accb = fmaf(fe, pair_dose<DC>(t, xp, yp, kmag, d, fac, P, water, atab, tT, tTW, tW2),
                                 accb);
                 }
             }
@@ -225,28 +224,58 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
 // One plan: wave w of the grid takes the brick in slot w of `order` (bricks in
 // decreasing order of estimated work, so expensive bricks start early and
 // cheap ones fill the tail; consecutive workgroups are dealt round-robin to
-// the 8 XCDs).
-template <bool DC, int MODE, int BX, int BY, int BZ>
-__global__ __launch_bounds__(256) void dose_forward(DoseArgs a, const int* __restrict__ order,
-                                                    const float* __restrict__ fluence,
-                                                    float* __restrict__ dose,
-                                                    int* __restrict__ out_int,
-                                                    const float4* __restrict__ prm) {
+// the 8 XCDs).  With LW the workgroup (kLdsWaves waves) first copies the
+// water table into LDS as 48-byte records: the pairs then read it there and
+// the vector-memory data path carries only the per-beamlet and A lookups
+// (with 8 waves per workgroup four workgroups, a full CU, fit in LDS for
+// tables up to 853 samples).
+
+template <bool DC, int MODE, int BX, int BY, int BZ, bool LW>
+__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256) void dose_forward(
+    DoseArgs a, const int* __restrict__ order, const float* __restrict__ fluence,
+    float* __restrict__ dose, int* __restrict__ out_int, const float4* __restrict__ prm) {
+    extern __shared__ float4 s_water[];
+    if (LW) {
+        const int n = a.P.dt_n;
+        const FSPB_GLOBAL float4* __restrict__ g = as_global(a.dtab);
+        for (int q = threadIdx.x; q < 3 * n; q += blockDim.x) {
+            const int plane = q / n, j = q - plane * n;
+            s_water[3 * j + plane] = g[q];
+        }
+        __syncthreads();
+    }
     const int slot = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (slot >= bricks_total<BX, BY, BZ>(a.P)) return;
     const int brick = order ? order[slot] : slot;
-    brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int, prm);
+    if (LW)
+        brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int,
+                                         WaterLds{(const FSPB_LDS float4*)s_water}, prm);
+    else
+        brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int,
+                                         WaterGlobal{as_global(a.dtab), a.P.dt_n}, prm);
 }
 
 // Many plans in one persistent launch: wave q walks its own static list of
 // (plan, brick) items, built on the host by longest-processing-time-first
 // assignment.  ts_done[plan * n_waves + q] receives the wall clock after the
 // wave's last item of that plan; ts_start[q] the wave's start.  No atomics.
-template <bool DC, int BX, int BY, int BZ>
-__global__ __launch_bounds__(256) void dose_forward_batch(
+// With LW every plan uses the same water table (water, n samples), which
+// the workgroup stages in LDS as dose_forward does.
+template <bool DC, int BX, int BY, int BZ, bool LW>
+__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256) void dose_forward_batch(
     const DoseArgs* __restrict__ plans, const int2* __restrict__ items,
     const int* __restrict__ wave_begin, int n_waves, BatchPtrs ptrs,
-    unsigned long long* __restrict__ ts_done, unsigned long long* __restrict__ ts_start) {
+    unsigned long long* __restrict__ ts_done, unsigned long long* __restrict__ ts_start,
+    const float4* __restrict__ water, int water_n) {
+    extern __shared__ float4 s_water[];
+    if (LW) {
+        const FSPB_GLOBAL float4* __restrict__ g = as_global(water);
+        for (int r = threadIdx.x; r < 3 * water_n; r += blockDim.x) {
+            const int plane = r / water_n, j = r - plane * water_n;
+            s_water[3 * j + plane] = g[r];
+        }
+        __syncthreads();
+    }
     const int q = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (q >= n_waves) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -254,7 +283,13 @@ __global__ __launch_bounds__(256) void dose_forward_batch(
     const int it0 = uniform(wave_begin[q]), it1 = uniform(wave_begin[q + 1]);
     for (int it = it0; it < it1; ++it) {
         const int p = uniform(items[it].x), brick = uniform(items[it].y);
-        brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p], nullptr);
+        if (LW)
+            brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p],
+                                              nullptr, WaterLds{(const FSPB_LDS float4*)s_water});
+        else
+            brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p],
+                                              nullptr,
+                                              WaterGlobal{as_global(plans[p].dtab), plans[p].P.dt_n});
         if (ts_done && lane == 0) ts_done[(long)p * n_waves + q] = wall_clock64();
     }
 }
@@ -385,7 +420,8 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                     if (DC) fac = facs[v];
                     acc = fmaf(wv[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
-                                                    as_global(a.dtab), as_global(a.atab),
+                                                    WaterGlobal{as_global(a.dtab), P.dt_n},
+                                                    as_global(a.atab),
                                                     as_global(a.tT), as_global(a.tTW),
                                                     as_global(a.tW2)),
                                acc);
@@ -485,13 +521,20 @@ void shape_dims(int shape, int d[3]) {
 template <bool DC, int MODE>
 static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                         float* dose, int* out_int, hipStream_t s, const float4* prm = nullptr) {
-    const int wpb = cfg.waves_per_block;
+    const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
+    const bool lds = cfg.waves_per_block == kLdsWaves;
+    const bool lw = lds && MODE != kCount && water_bytes <= (size_t)kLdsWaterMax;
+    const int wpb = lds && !lw ? 4 : cfg.waves_per_block;
     const long nb = brick_count(a.P, cfg.shape);
     dim3 grid((unsigned)((nb + wpb - 1) / wpb)), block(kWave * wpb);
 #define FSPB_SHAPE(ID, X, Y, Z)                                                                \
     case ID:                                                                                   \
-        hipLaunchKernelGGL((dose_forward<DC, MODE, X, Y, Z>), grid, block, 0, s, a, order,     \
-                           fluence, dose, out_int, prm);                                       \
+        if (lw)                                                                                \
+            hipLaunchKernelGGL((dose_forward<DC, MODE, X, Y, Z, true>), grid, block,           \
+                               water_bytes, s, a, order, fluence, dose, out_int, prm);         \
+        else                                                                                   \
+            hipLaunchKernelGGL((dose_forward<DC, MODE, X, Y, Z, false>), grid, block, 0, s, a, \
+                               order, fluence, dose, out_int, prm);                            \
         break;
     switch (cfg.shape) {
         FSPB_SHAPE(0, 4, 4, 4)
@@ -579,17 +622,26 @@ void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s)
 void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
                           const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
                           unsigned long long* ts_done, unsigned long long* ts_start,
-                          hipStream_t s) {
-    const int wpb = cfg.waves_per_block;
+                          const float4* water, int water_n, hipStream_t s) {
+    const size_t water_bytes = sizeof(float4) * 3 * (size_t)water_n;
+    const bool lds = cfg.waves_per_block == kLdsWaves;
+    const bool lw = lds && water && water_bytes <= (size_t)kLdsWaterMax;
+    const int wpb = lds && !lw ? 4 : cfg.waves_per_block;
+    const size_t sh = lw ? water_bytes : 0;
     dim3 grid((unsigned)((n_waves + wpb - 1) / wpb)), block(kWave * wpb);
-#define FSPB_SHAPE(ID, X, Y, Z)                                                                 \
-    case ID:                                                                                    \
-        if (dc)                                                                                 \
-            hipLaunchKernelGGL((dose_forward_batch<true, X, Y, Z>), grid, block, 0, s, plans,   \
-                               items, wave_begin, n_waves, ptrs, ts_done, ts_start);            \
-        else                                                                                    \
-            hipLaunchKernelGGL((dose_forward_batch<false, X, Y, Z>), grid, block, 0, s, plans,  \
-                               items, wave_begin, n_waves, ptrs, ts_done, ts_start);            \
+#define FSPB_BATCH(DCV, LWV, X, Y, Z)                                                         \
+    hipLaunchKernelGGL((dose_forward_batch<DCV, X, Y, Z, LWV>), grid, block, sh, s, plans,    \
+                       items, wave_begin, n_waves, ptrs, ts_done, ts_start, water, water_n)
+#define FSPB_SHAPE(ID, X, Y, Z)                                                               \
+    case ID:                                                                                  \
+        if (dc && lw)                                                                         \
+            FSPB_BATCH(true, true, X, Y, Z);                                                  \
+        else if (dc)                                                                          \
+            FSPB_BATCH(true, false, X, Y, Z);                                                 \
+        else if (lw)                                                                          \
+            FSPB_BATCH(false, true, X, Y, Z);                                                 \
+        else                                                                                  \
+            FSPB_BATCH(false, false, X, Y, Z);                                                \
         break;
     switch (cfg.shape) {
         FSPB_SHAPE(0, 4, 4, 4)
@@ -598,6 +650,7 @@ void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int
         FSPB_SHAPE(3, 8, 2, 4)
     }
 #undef FSPB_SHAPE
+#undef FSPB_BATCH
 }
 
 void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStream_t s) {

@@ -971,8 +971,9 @@ int fspb_tile_shapes(int* dims, int max_shapes) {
 int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream) {
     if (!g) return fail(FSPB_E_ARG, "set_tile: NULL handle");
     if (shape < 0 || shape >= kNumShapes) return fail(FSPB_E_ARG, "set_tile: shape %d out of range", shape);
-    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-        return fail(FSPB_E_ARG, "set_tile: waves_per_block must be 1, 2 or 4");
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
+        waves_per_block != kLdsWaves)
+        return fail(FSPB_E_ARG, "set_tile: waves_per_block must be 1, 2, 4 or 8");
     const bool rebuild = shape != g->tile.shape;
     g->tile.shape = shape;
     g->tile.waves_per_block = waves_per_block;
@@ -994,12 +995,12 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int wpbs[3] = {1, 2, 4};
+    const int wpbs[4] = {1, 2, 4, kLdsWaves};
     TileCfg best = g->tile;
     float best_ms = 1e30f;
     int n = 0, rc = FSPB_OK;
     for (int sh = 0; sh < kNumShapes && rc == FSPB_OK; ++sh) {
-        for (int w = 0; w < 3 && rc == FSPB_OK; ++w) {
+        for (int w = 0; w < 4 && rc == FSPB_OK; ++w) {
             rc = fspb_set_tile(g, sh, wpbs[w], stream);
             if (rc) break;
             std::vector<float> ms;
@@ -1070,6 +1071,8 @@ struct fspb_batch {
     TileCfg tile;
     std::vector<fspb_geometry*> plans;
     std::vector<std::pair<void*, size_t>> blocks;
+    const float4* water = nullptr;   // the water table all plans share, else null
+    int water_n = 0;
     DoseArgs* d_args = nullptr;
     int2* d_items = nullptr;
     int* d_begin = nullptr;
@@ -1113,7 +1116,7 @@ static int batch_enqueue(fspb_batch* b, const float* const* fluence, float* cons
     launch_fill_u64(b->ts_done, (long)b->n_plans * b->n_waves, 0ULL, s);
     HIP_TRY(hipGetLastError());
     launch_forward_batch(b->dc != 0, b->tile, b->d_args, b->d_items, b->d_begin, b->n_waves, ptrs,
-                         b->ts_done, b->ts_start, s);
+                         b->ts_done, b->ts_start, b->water, b->water_n, s);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
@@ -1127,8 +1130,9 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
     if (n < 1 || !geoms) return fail(FSPB_E_ARG, "batch_create: need n >= 1 geometries");
     if (n > kMaxBatchPlans) return fail(FSPB_E_ARG, "batch_create: at most %d plans", kMaxBatchPlans);
     if (shape < 0 || shape >= kNumShapes) return fail(FSPB_E_ARG, "batch_create: bad shape");
-    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-        return fail(FSPB_E_ARG, "batch_create: waves_per_block must be 1, 2 or 4");
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
+        waves_per_block != kLdsWaves)
+        return fail(FSPB_E_ARG, "batch_create: waves_per_block must be 1, 2, 4 or 8");
     if (waves_per_cu < 1 || waves_per_cu > 32)
         return fail(FSPB_E_ARG, "batch_create: waves_per_cu must be 1..32");
     if (policy != FSPB_SCHEDULE_THROUGHPUT && policy != FSPB_SCHEDULE_LATENCY)
@@ -1149,6 +1153,12 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
     B->tile.shape = shape;
     B->tile.waves_per_block = waves_per_block;
     B->plans.assign(geoms, geoms + n);
+    // one shared water table (plans built from the same commissioned tables
+    // share the device copy) can be staged in LDS by the persistent kernel
+    B->water = geoms[0]->dtab;
+    B->water_n = geoms[0]->P.dt_n;
+    for (int p = 1; p < n; ++p)
+        if (geoms[p]->dtab != B->water) B->water = nullptr;
     auto bail = [&](int rc) {
         (void)hipStreamSynchronize(s);
         B->release();

@@ -63,11 +63,15 @@ struct DoseArgs {
 };
 
 // Forward-kernel tile configuration: brick shape (index into the built
-// shapes) and waves per workgroup.
+// shapes) and waves per workgroup: 1, 2 or 4 read the water table from
+// global memory; kLdsWaves stages it in LDS once per workgroup when it fits
+// in kLdsWaterMax bytes (else the launch uses 4 waves and global reads).
 constexpr int kNumShapes = 4;
+constexpr int kLdsWaves = 8;
+constexpr int kLdsWaterMax = 65536;
 struct TileCfg {
     int shape = 0;            // 4 x 4 x 4 bricks
-    int waves_per_block = 4;
+    int waves_per_block = kLdsWaves;
 };
 long brick_count(const PlanConst& P, int shape);
 void shape_dims(int shape, int d[3]);
@@ -93,10 +97,12 @@ struct BatchPtrs {
     const float* fluence[kMaxBatchPlans];
     float* dose[kMaxBatchPlans];
 };
+// water: the water table every plan of the batch uses (n samples per plane),
+// or null when the plans' tables differ (then no LDS staging)
 void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
                           const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
                           unsigned long long* ts_done, unsigned long long* ts_start,
-                          hipStream_t s);
+                          const float4* water, int water_n, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStream_t s);
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     hipStream_t s);

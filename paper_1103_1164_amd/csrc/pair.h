@@ -33,9 +33,11 @@ namespace fspb {
 #if defined(__HIP_DEVICE_COMPILE__)
 #define FSPB_GLOBAL __attribute__((address_space(1)))
 #define FSPB_CONST __attribute__((address_space(4)))
+#define FSPB_LDS __attribute__((address_space(3)))
 #else
 #define FSPB_GLOBAL
 #define FSPB_CONST
+#define FSPB_LDS
 #endif
 template <class T>
 __device__ __forceinline__ const FSPB_GLOBAL T* as_global(const T* p) {
@@ -58,6 +60,29 @@ __device__ __forceinline__ T load_at(const FSPB_GLOBAL T* base, unsigned byte_of
     return *reinterpret_cast<const FSPB_GLOBAL T*>(reinterpret_cast<const FSPB_GLOBAL char*>(base) +
                                                    byte_off);
 }
+
+// Water-table readers for pair_dose: sample j of the three planes
+// (steepness, slopes, weights) from global memory, or from a workgroup's LDS
+// copy laid out as 48-byte records (one address, immediate offsets).
+struct WaterGlobal {
+    const FSPB_GLOBAL float4* p;
+    int n;   // samples per plane
+    __device__ __forceinline__ void get(unsigned j, float4& u0, float4& us, float4& wv) const {
+        const unsigned o = j << 4;
+        u0 = load_at(p, o);
+        us = load_at(p + n, o);
+        wv = load_at(p + 2 * n, o);
+    }
+};
+struct WaterLds {
+    const FSPB_LDS float4* p;
+    __device__ __forceinline__ void get(unsigned j, float4& u0, float4& us, float4& wv) const {
+        const FSPB_LDS float4* r = p + 3 * j;
+        u0 = r[0];
+        us = r[1];
+        wv = r[2];
+    }
+};
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -112,10 +137,9 @@ __device__ __forceinline__ float magnification(float t, const BD& b) {
 // below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
 // fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
 // k = SAD / |r_a| (see magnification()) is computed by the caller.
-template <bool DC, class BD>
+template <bool DC, class BD, class WT>
 __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k, const BD& b,
-                                           float4 fac, const PlanConst& P,
-                                           const FSPB_GLOBAL float4* __restrict__ dtab,
+                                           float4 fac, const PlanConst& P, const WT& water,
                                            const FSPB_GLOBAL float4* __restrict__ atab,
                                            const FSPB_GLOBAL float2* __restrict__ tT,
                                            const FSPB_GLOBAL float4* __restrict__ tTW,
@@ -131,10 +155,9 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     // end value.
     // water parameters at geometric depth t
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
-    const unsigned od = (unsigned)cd << 4;              // 16-byte entries, three planes
     const float fd = fract(cd);
-    const float4 u0 = load_at(dtab, od), us = load_at(dtab + P.dt_n, od),
-                 wv = load_at(dtab + 2 * P.dt_n, od);
+    float4 u0, us, wv;
+    water.get((unsigned)cd, u0, us, wv);
 
     // per-beamlet radiological depth and weight drift at depth t (Section 2.2);
     // t >= 0 (the pair test), so the sample index needs no lower clamp, and
@@ -195,19 +218,17 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
 // kernels.h), found by a binary search on the segment start depths -- the
 // search the uniform samples of Section 2.2 avoid.  Everything else is
 // pair_dose's.
-template <bool DC, class BD>
+template <bool DC, class BD, class WT>
 __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, float k, const BD& b,
-                                                  float4 fac, const PlanConst& P,
-                                                  const FSPB_GLOBAL float4* __restrict__ dtab,
+                                                  float4 fac, const PlanConst& P, const WT& water,
                                                   const FSPB_GLOBAL float4* __restrict__ atab,
                                                   const FSPB_GLOBAL float4* __restrict__ sid) {
     float x = xp * k, y = yp * k;
     float isq = k * k;
     const float cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
-    const unsigned od = (unsigned)cd << 4;
     const float fd = fract(cd);
-    const float4 u0 = load_at(dtab, od), us = load_at(dtab + P.dt_n, od),
-                 wv = load_at(dtab + 2 * P.dt_n, od);
+    float4 u0, us, wv;
+    water.get((unsigned)cd, u0, us, wv);
     const FSPB_GLOBAL float4* rec = sid + 2 * (long)b.tab_off;
     int lo = 0, hi = b.K - 1;
     while (lo < hi) {

@@ -36,7 +36,7 @@ def test_tile_configurations_agree(dc):
     shapes = Geometry.tile_shapes()
     assert len(shapes) >= 2 and all(int(np.prod(s)) == 64 for s in shapes)
     for sh in range(len(shapes)):
-        for wpb in (1, 2, 4):
+        for wpb in (1, 2, 4, 8):          # 8: water table staged in LDS
             geo.set_tile(sh, wpb)
             assert geo.get_tile() == (sh, wpb)
             assert np.array_equal(gpu_dose(geo, plan.fluence), ref), (sh, wpb)
@@ -54,7 +54,8 @@ def test_batch_equals_single_plan(dc):
     refs = [gpu_dose(g, p.fluence) for g, p in zip(geos, plans)]
     fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
     for shape, wpb, wpc, pol in ((0, 4, 32, "throughput"), (1, 2, 8, "latency"),
-                                 (0, 1, 1, "throughput"), (2, 4, 16, "latency")):
+                                 (0, 1, 1, "throughput"), (2, 4, 16, "latency"),
+                                 (0, 8, 32, "latency"), (3, 8, 8, "throughput")):
         b = Batch(geos, shape=shape, waves_per_block=wpb, waves_per_cu=wpc, policy=pol)
         out = [torch.full(p.shape, -1.0, device="cuda") for p in plans]
         b.forward(fl, out)
@@ -68,6 +69,50 @@ def test_batch_equals_single_plan(dc):
                        for p in plans)
         assert b.info()["n_items"] == n_bricks
         b.close()
+
+
+def _fine_water_tables():
+    """The nominal tables with the water (depth) tables resampled every 0.04
+    cm: 2001 samples, 96 KB as the kernels hold them, more than the 64 KB
+    the forward stages in LDS."""
+    import dataclasses
+    tab = S.make_tables(0)
+    t_new = 0.04 * np.arange(2001)
+    def fine(tb):
+        t_old = tb.start + tb.step * np.arange(tb.n)
+        return S.Table1D(0.0, 0.04, np.interp(t_new, t_old, tb.values).astype(np.float32))
+    return dataclasses.replace(tab, **{k: fine(getattr(tab, k))
+                                       for k in ("u1x", "u1y", "u2x", "u2y", "w1", "w2")})
+
+
+@pytest.mark.parametrize("dc", [1, 0])
+def test_water_table_too_large_for_lds(oracle_mod, dc):
+    """8 waves per workgroup with a water table over 64 KB reads it from
+    global memory (4 waves): same dose as the other configurations, and the
+    oracle's.  A batch of plans with different tables has no shared table to
+    stage and takes the same path."""
+    from paper_1103_1164_amd import Batch
+    p0 = _plans()[0]
+    plan = S.plan_small(n=p0.shape[::-1], density=p0.density, beams=p0.beams,
+                        fluence=p0.fluence, tables=_fine_water_tables(), seed=9)
+    geo = geometry(plan, dc)
+    geo.set_tile(0, 8)
+    d8 = gpu_dose(geo, plan.fluence)
+    geo.set_tile(0, 4)
+    assert np.array_equal(gpu_dose(geo, plan.fluence), d8)
+    d_o, amb, _ = oracle_mod.Oracle(plan, dc_enabled=dc).dose()
+    assert_dose_parity(d8, d_o, amb, what="fine water tables")
+    other = _plans()[1]
+    g1 = geometry(other, dc)
+    ref1 = gpu_dose(g1, other.fluence)
+    b = Batch([geo, g1], shape=0, waves_per_block=8, policy="latency")
+    fl = [torch.as_tensor(p.fluence, device="cuda") for p in (plan, other)]
+    out = [torch.full(p.shape, -1.0, device="cuda") for p in (plan, other)]
+    b.forward(fl, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out[0].cpu().numpy().astype(np.float64), d8)
+    assert np.array_equal(out[1].cpu().numpy().astype(np.float64), ref1)
+    b.close()
 
 
 def test_update_density_matches_fresh_geometry():
@@ -128,7 +173,7 @@ def test_autotune_and_cache(tmp_path):
     f = torch.as_tensor(plan.fluence, device="cuda")
     cache = tmp_path / "tune.json"
     r1 = tune(geo, f, cache=cache, reps=2)
-    assert not r1["cached"] and len(r1["all"]) == 3 * len(geo.tile_shapes())
+    assert not r1["cached"] and len(r1["all"]) == 4 * len(geo.tile_shapes())
     assert geo.get_tile() == (r1["shape"], r1["waves_per_block"])
     assert np.array_equal(gpu_dose(geo, plan.fluence), ref)
     geo2 = geometry(plan, 1)
