@@ -161,8 +161,12 @@ typedef struct {
 /* Builds the per-plan geometry on the device (Algorithm A2 steps 2-5):
  * smoothed density and per-voxel correction factors (DC only), beamlet
  * frames and angles, entrance points, and radiological-depth and
- * weight-drift tables.  Synchronises the stream before returning, so the
- * caller may free ct->density afterwards.
+ * weight-drift tables.  The handle takes its own device copy of the CT and
+ * returns once that copy is complete, so the caller may free or overwrite
+ * ct->density afterwards; the geometry kernels may still be running on
+ * stream.  Later calls on the same stream are ordered after them; a call on
+ * another stream, or one that reads results on the host, first waits for
+ * them.
  *   ct      host struct; ct->density device.
  *   beams   host array [n_beams].
  *   tables  host struct with host arrays (copied).

@@ -449,9 +449,22 @@ __global__ __launch_bounds__(1024) void order_bricks(const int* __restrict__ cos
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     for (int b = tid; b < kOrderBins; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    // bin 0 holds the most expensive bricks
+    // bin 0 holds the most expensive bricks; costs are read eight at a time
+    // so that their loads overlap (a single workgroup does all the work)
     auto bin = [&](int q) { return kOrderBins - 1 - min(max(cost[q], 0), kOrderBins - 1); };
-    for (int q = tid; q < n; q += blockDim.x) atomicAdd(&hist[bin(q)], 1);
+    constexpr int kBatch = 8;
+    const int span = kBatch * blockDim.x;
+    for (int q0 = tid; q0 < n; q0 += span) {
+        int bq[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int q = q0 + u * (int)blockDim.x;
+            bq[u] = q < n ? bin(q) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (bq[u] >= 0) atomicAdd(&hist[bq[u]], 1);
+    }
     __syncthreads();
     // exclusive scan of the 4096 bins, 4 consecutive bins a thread
     const int b0 = 4 * tid;
@@ -468,7 +481,17 @@ __global__ __launch_bounds__(1024) void order_bricks(const int* __restrict__ cos
     hist[b0 + 2] = ex + c0 + c1;
     hist[b0 + 3] = ex + c0 + c1 + c2;
     __syncthreads();
-    for (int q = tid; q < n; q += blockDim.x) order[atomicAdd(&hist[bin(q)], 1)] = q;
+    for (int q0 = tid; q0 < n; q0 += span) {
+        int bq[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int q = q0 + u * (int)blockDim.x;
+            bq[u] = q < n ? bin(q) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (bq[u] >= 0) order[atomicAdd(&hist[bq[u]], 1)] = q0 + u * (int)blockDim.x;
+    }
 }
 
 void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s) {

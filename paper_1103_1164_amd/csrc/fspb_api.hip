@@ -17,6 +17,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <functional>
 #include <cmath>
 #include <map>
 #include <new>
@@ -205,6 +207,12 @@ struct fspb_geometry {
     int* cost = nullptr;       // estimated work per brick (candidate beamlets)
     float* tmp0 = nullptr;     // smoothing intermediates (alias the depth tables when they fit)
     float* tmp1 = nullptr;
+    float* rho = nullptr;      // the handle's copy of the CT it was created from
+    // creation work is asynchronous: `ready` is recorded on `ready_stream`
+    // after it; first use on another stream (or from the host) waits for it
+    hipEvent_t ready = nullptr;
+    hipStream_t ready_stream = nullptr;
+    bool pending = false;
     TileCfg tile;
     std::vector<int> h_cost;   // host copy of cost (fetched when a batch needs it)
     bool h_cost_valid = false;
@@ -250,6 +258,9 @@ struct fspb_geometry {
     TableSet* tabs = nullptr;      // shared commissioned tables (not owned)
 
     void release() {
+        if (ready) (void)hipEventDestroy(ready);
+        ready = nullptr;
+        pending = false;
         for (auto& b : blocks) pool_free(device, b.first, b.second);
         blocks.clear();
         if (tabs) {
@@ -337,6 +348,10 @@ int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_
 }
 
 int check_device(int* dev) {
+    // the architecture of each device is looked up once (the property query
+    // is slow compared with creating a plan)
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> verdict[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || n < 1) {
@@ -344,9 +359,13 @@ int check_device(int* dev) {
         return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
     }
     HIP_TRY(hipGetDevice(dev));
+    const int v = (*dev >= 0 && *dev < kMaxDevices) ? verdict[*dev].load() : 0;
+    if (v == 1) return FSPB_OK;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, *dev));
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (*dev >= 0 && *dev < kMaxDevices) verdict[*dev].store(ok ? 1 : -1);
+    if (!ok)
         return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
                     prop.gcnArchName);
     return FSPB_OK;
@@ -354,9 +373,24 @@ int check_device(int* dev) {
 
 }  // namespace
 
+// Waits (on the host) for the handle's creation work.
+static int settle_host(fspb_geometry* g) {
+    if (!g->pending) return FSPB_OK;
+    if (hipEventQuery(g->ready) != hipSuccess) HIP_TRY(hipEventSynchronize(g->ready));
+    g->pending = false;
+    return FSPB_OK;
+}
+
+// Orders work on stream s after the handle's creation work (on the creation
+// stream that order holds already).
+static int settle(fspb_geometry* g, hipStream_t s) {
+    return (!g->pending || s == g->ready_stream) ? FSPB_OK : settle_host(g);
+}
+
 int fspb_geometry::fetch_host() const {
     fspb_geometry* G = const_cast<fspb_geometry*>(this);
     if (G->host_ready) return FSPB_OK;
+    if (int rc = settle_host(G)) return rc;
     const int nbl = n_beamlets;
     G->h_desc.resize(nbl);
     G->h_frames.resize(nbl);
@@ -422,37 +456,54 @@ static int fetch_cost(fspb_geometry* G, hipStream_t s) {
 //                   theta rows r < a_cols and depth samples j < n_A; the 1/4
 //                   is the product of the two factors 1/2 of Eq. 4's profiles
 //   denstab: the six density tables back to back (offsets in dens)
-static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** out) {
-    std::vector<uint32_t> key;
-    auto put_f = [&](float v) {
-        uint32_t u;
-        memcpy(&u, &v, 4);
-        key.push_back(u);
-    };
+// The key of a table set: every parameter and value, bitwise, in a fixed
+// order.  A lookup compares the cached keys with the tables in place; the
+// key is only built for a new set.
+static void table_key_walk(const fspb_tables* t,
+                           const std::function<bool(const void*, size_t)>& part) {
     auto put_tab = [&](const fspb_table1d& tb, size_t count) {
-        key.push_back((uint32_t)tb.n);
-        put_f(tb.start);
-        put_f(tb.step);
-        const size_t k0 = key.size();
-        key.resize(k0 + count);
-        memcpy(key.data() + k0, tb.v, sizeof(float) * count);
+        const uint32_t n = (uint32_t)tb.n;
+        return part(&n, 4) && part(&tb.start, 4) && part(&tb.step, 4) &&
+               part(tb.v, sizeof(float) * count);
     };
-    key.push_back((uint32_t)t->n_theta);
-    put_f(t->theta_step);
-    put_tab(t->A, (size_t)t->n_theta * t->A.n);
+    const uint32_t nth = (uint32_t)t->n_theta;
+    if (!part(&nth, 4) || !part(&t->theta_step, 4)) return;
+    if (!put_tab(t->A, (size_t)t->n_theta * t->A.n)) return;
     const fspb_table1d* all[12] = {&t->u1x, &t->u1y, &t->u2x, &t->u2y, &t->w1, &t->w2,
                                    &t->fu1, &t->fu2, &t->fw1, &t->fw2, &t->b1, &t->b2};
-    for (const fspb_table1d* tb : all) put_tab(*tb, (size_t)tb->n);
+    for (const fspb_table1d* tb : all)
+        if (!put_tab(*tb, (size_t)tb->n)) return;
+}
 
+static bool table_key_equals(const std::vector<uint32_t>& key, const fspb_tables* t) {
+    size_t pos = 0;
+    bool eq = true;
+    table_key_walk(t, [&](const void* p, size_t bytes) {
+        const size_t words = bytes / 4;
+        eq = pos + words <= key.size() && memcmp(key.data() + pos, p, bytes) == 0;
+        pos += words;
+        return eq;
+    });
+    return eq && pos == key.size();
+}
+
+static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** out) {
     std::lock_guard<std::mutex> lk(g_tables_mu);
     auto& sets = table_sets();
     for (TableSet* ts : sets)
-        if (ts->device == dev && ts->key == key) {
+        if (ts->device == dev && table_key_equals(ts->key, t)) {
             ++ts->refs;
             ts->last_use = ++g_tables_clock;
             *out = ts;
             return FSPB_OK;
         }
+    std::vector<uint32_t> key;
+    table_key_walk(t, [&](const void* p, size_t bytes) {
+        const size_t k0 = key.size();
+        key.resize(k0 + bytes / 4);
+        memcpy(key.data() + k0, p, bytes);
+        return true;
+    });
 
     const int dn = t->u1x.n;
     std::vector<float4> dtab(3 * (size_t)dn);
@@ -700,6 +751,12 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         ALLOC(G->fac, sizeof(float4) * nv);
     }
     HIP_TRY(hipMemcpyAsync(dsmall, small.data(), small_bytes, hipMemcpyHostToDevice, s));
+    // the handle reads its own copy of the CT: create returns once the copy is
+    // taken, while kernels 1-4 may still run
+    ALLOC(G->rho, sizeof(float) * nv);
+    HIP_TRY(hipMemcpyAsync(G->rho, ct->density, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipEventCreateWithFlags(&G->ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(G->ready, s));
 
     // ---- kernels 1-4 ---------------------------------------------------------
     if (o.dc_enabled) {
@@ -713,11 +770,11 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
             ALLOC(G->tmp0, sizeof(float) * nv);
             ALLOC(G->tmp1, sizeof(float) * nv);
         }
-        launch_smooth(ct->density, G->tmp0, G->tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3,
+        launch_smooth(G->rho, G->tmp0, G->tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3,
                       G->smooth_r, G->denstab, G->dens, s);
         HIP_TRY(hipGetLastError());
-#undef ALLOC
     }
+#undef ALLOC
     double lo[3] = {ct->ox - 0.5 * ct->dx, ct->oy - 0.5 * ct->dy, ct->oz - 0.5 * ct->dz};
     double hi[3] = {ct->ox + (nx - 0.5) * ct->dx, ct->oy + (ny - 0.5) * ct->dy,
                     ct->oz + (nz - 0.5) * ct->dz};
@@ -744,7 +801,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     tp.n_theta = t->n_theta;
     tp.n_A = t->A.n;
     tp.k_stride = G->k_stride;
-    launch_trace(G->frames, nbl, ct->density, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->tW2,
+    launch_trace(G->frames, nbl, G->rho, tg, tp, G->denstab, G->dens, G->tT, G->tTW, G->tW2,
                  G->desc, G->tinfo, s);
     HIP_TRY(hipGetLastError());
     if (G->siddon) {
@@ -755,13 +812,16 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
                         G->sid_stride);
         if ((rc = G->alloc((void**)&G->sid, 2 * sizeof(float4) * (size_t)nbl * G->sid_stride)) != FSPB_OK)
             return rc;
-        launch_siddon(G->frames, nbl, ct->density, tg, tp, G->sid_stride, G->denstab, G->dens,
+        launch_siddon(G->frames, nbl, G->rho, tg, tp, G->sid_stride, G->denstab, G->dens,
                       G->sid, G->desc, G->tinfo, s);
         HIP_TRY(hipGetLastError());
     }
 
     if ((rc = build_order(G, s)) != FSPB_OK) return rc;
-    HIP_TRY(hipStreamSynchronize(s));   // the caller may free ct->density now
+    HIP_TRY(hipEventSynchronize(G->ready));   // the copy of ct->density is taken
+    HIP_TRY(hipEventRecord(G->ready, s));     // end of the creation work
+    G->ready_stream = s;
+    G->pending = true;
     return FSPB_OK;
 }
 
@@ -800,6 +860,8 @@ static void enqueue_forward(fspb_geometry* g, const float* fluence, float* dose,
 
 int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream) {
     if (!g || !fluence || !dose) return fail(FSPB_E_ARG, "forward: NULL argument");
+    int rc = settle(g, (hipStream_t)stream);
+    if (rc) return rc;
     enqueue_forward(g, fluence, dose, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
@@ -808,6 +870,8 @@ int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stre
 int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream) {
     if (!g || !voxel_weight || !grad) return fail(FSPB_E_ARG, "adjoint: NULL argument");
     if (g->siddon) return fail(FSPB_E_STATE, "adjoint: not available with exact depth tables");
+    int rc = settle(g, (hipStream_t)stream);
+    if (rc) return rc;
     launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad,
                    (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
@@ -820,7 +884,8 @@ int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
     hipStream_t s = (hipStream_t)stream;
     const long nv = (long)g->P.nx * g->P.ny * g->P.nz;
     const int n_part = 256;
-    int rc;
+    int rc = settle(g, s);
+    if (rc) return rc;
     if (!counts && !g->counts)
         if ((rc = g->alloc((void**)&g->counts, sizeof(int) * nv)) != FSPB_OK) return rc;
     if (!g->partial) {
@@ -874,6 +939,8 @@ int fspb_geometry_info(const fspb_geometry* g, fspb_info* info) {
 int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream) {
     if (!g || !out) return fail(FSPB_E_ARG, "smoothed_density: NULL argument");
     if (!g->rhohat) return fail(FSPB_E_STATE, "smoothed_density: handle has no density correction");
+    int rc = settle(const_cast<fspb_geometry*>(g), (hipStream_t)stream);
+    if (rc) return rc;
     const long nv = (long)g->P.nx * g->P.ny * g->P.nz;
     HIP_TRY(hipMemcpyAsync(out, g->rhohat, sizeof(float) * nv, hipMemcpyDeviceToDevice,
                            (hipStream_t)stream));
@@ -974,6 +1041,8 @@ int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
         waves_per_block != kLdsWaves)
         return fail(FSPB_E_ARG, "set_tile: waves_per_block must be 1, 2, 4 or 8");
+    int rc = settle(g, (hipStream_t)stream);
+    if (rc) return rc;
     const bool rebuild = shape != g->tile.shape;
     g->tile.shape = shape;
     g->tile.waves_per_block = waves_per_block;
@@ -992,6 +1061,7 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     if (!g || !fluence || !dose_scratch || reps < 1)
         return fail(FSPB_E_ARG, "autotune: NULL argument or reps < 1");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc0 = settle(g, s)) return rc0;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1043,6 +1113,7 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
 int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
     if (!g || !density) return fail(FSPB_E_ARG, "update_density: NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc0 = settle(g, s)) return rc0;
     const PlanConst& P = g->P;
     if (g->dc_created) {
         launch_smooth(density, g->tmp0, g->tmp1, g->rhohat, g->fac, P.nx, P.ny, P.nz, g->w3,
@@ -1139,6 +1210,7 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
         return fail(FSPB_E_ARG, "batch_create: unknown schedule policy %d", policy);
     for (int p = 0; p < n; ++p) {
         if (!geoms[p]) return fail(FSPB_E_ARG, "batch_create: geometry %d is NULL", p);
+        if (int rc = settle_host(geoms[p])) return rc;   // the batch may run on any stream
         if (geoms[p]->siddon)
             return fail(FSPB_E_STATE, "batch_create: geometry %d uses exact depth tables", p);
         if (geoms[p]->dc_enabled != geoms[0]->dc_enabled)
@@ -1601,6 +1673,7 @@ int fspb_surrogate_samples(fspb_geometry* g, const float* density, const int* ro
                            uint16_t* x, float* t, int* valid, void* stream) {
     int rc;
     if ((rc = check_surrogate_geometry(g, "surrogate_samples")) != FSPB_OK) return rc;
+    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
     if (n < 0 || n > (1LL << 30)) return fail(FSPB_E_ARG, "surrogate_samples: bad row count %lld", n);
     if (n == 0) return FSPB_OK;
     if (!density || !rows || !x || !t || !valid)
@@ -1615,6 +1688,7 @@ int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* densi
                          void* stream) {
     int rc;
     if ((rc = check_surrogate_geometry(g, "surrogate_infer")) != FSPB_OK) return rc;
+    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
     if (!m || !density || !prm) return fail(FSPB_E_ARG, "surrogate_infer: NULL argument");
     if (m->device != g->device) return fail(FSPB_E_STATE, "surrogate_infer: handles on different devices");
     launch_surrogate_infer(g->args(), density, g->rhohat, m->weights(), m->sc, m->gd,
@@ -1627,6 +1701,7 @@ int fspb_forward_surrogate(fspb_geometry* g, const float* fluence, const float* 
                            void* stream) {
     int rc;
     if ((rc = check_surrogate_geometry(g, "forward_surrogate")) != FSPB_OK) return rc;
+    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
     if (!fluence || !prm || !dose) return fail(FSPB_E_ARG, "forward_surrogate: NULL argument");
     launch_forward_surrogate(g->args(), g->tile, g->order, fluence, (const float4*)prm, dose,
                              (hipStream_t)stream);

@@ -17,31 +17,43 @@ namespace fspb {
 // normalised 3D cube-truncated Gaussian is the product of three normalised
 // 1D kernels, so three 1D passes give the same sums.  Each thread produces
 // one voxel; the 64 lanes of a wave read consecutive x, so every tap load is
-// coalesced whatever the pass axis.
+// coalesced whatever the pass axis.  Grids hold fewer than 2^31 voxels
+// (checked at creation), so indices are 32-bit; taps are taken eight at a
+// time so that their loads are in flight together.
+__device__ __forceinline__ float smooth_taps(const float* __restrict__ base, int c, int n, int stride,
+                                            const float* __restrict__ w, int r) {
+    float acc = 0.0f;
+    for (int d0 = -r; d0 <= r; d0 += 8) {
+        float x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int d = min(d0 + q, r);   // past the last tap: a repeat with weight 0
+            x[q] = base[min(max(c + d, 0), n - 1) * stride];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (d0 + q <= r) acc = fmaf(w[d0 + q + r], x[q], acc);
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(256) void smooth_pass(const float* __restrict__ in,
                                                    float* __restrict__ out, int nx, int ny,
                                                    int nz, int axis,
                                                    const float* __restrict__ w, int r) {
-    long n = (long)nx * ny * nz;
-    long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = nx * ny * nz;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    int i = (int)(v % nx);
-    int j = (int)((v / nx) % ny);
-    int k = (int)(v / ((long)nx * ny));
-    float acc = 0.0f;
-    if (axis == 0) {
-        const float* row = in + (v - i);
-        for (int d = -r; d <= r; ++d) acc = fmaf(w[d + r], row[min(max(i + d, 0), nx - 1)], acc);
-    } else if (axis == 1) {
-        const float* col = in + ((long)k * ny) * nx + i;
-        for (int d = -r; d <= r; ++d)
-            acc = fmaf(w[d + r], col[(long)min(max(j + d, 0), ny - 1) * nx], acc);
-    } else {
-        const float* col = in + (long)j * nx + i;
-        long plane = (long)nx * ny;
-        for (int d = -r; d <= r; ++d)
-            acc = fmaf(w[d + r], col[(long)min(max(k + d, 0), nz - 1) * plane], acc);
-    }
+    const int i = v % nx;
+    const int j = (v / nx) % ny;
+    const int k = v / (nx * ny);
+    float acc;
+    if (axis == 0)
+        acc = smooth_taps(in + (v - i), i, nx, 1, w, r);
+    else if (axis == 1)
+        acc = smooth_taps(in + (k * ny * nx + i), j, ny, nx, w, r);
+    else
+        acc = smooth_taps(in + (j * nx + i), k, nz, nx * ny, w, r);
     out[v] = acc;
 }
 
@@ -52,17 +64,13 @@ __global__ __launch_bounds__(256) void smooth_last_factors(
     const float* __restrict__ in, const float* __restrict__ rho, float* __restrict__ rhohat,
     float4* __restrict__ fac, int nx, int ny, int nz, const float* __restrict__ w, int r,
     const float* __restrict__ tabs, DensTabs dt) {
-    long n = (long)nx * ny * nz;
-    long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = nx * ny * nz;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    int i = (int)(v % nx);
-    int j = (int)((v / nx) % ny);
-    int k = (int)(v / ((long)nx * ny));
-    const float* col = in + (long)j * nx + i;
-    long plane = (long)nx * ny;
-    float acc = 0.0f;
-    for (int d = -r; d <= r; ++d)
-        acc = fmaf(w[d + r], col[(long)min(max(k + d, 0), nz - 1) * plane], acc);
+    const int i = v % nx;
+    const int j = (v / nx) % ny;
+    const int k = v / (nx * ny);
+    const float acc = smooth_taps(in + (j * nx + i), k, nz, nx * ny, w, r);
     rhohat[v] = acc;
     float rc = fminf(fmaxf(rho[v], dt.rho_min), dt.rho_max);
     float hc = fminf(fmaxf(acc, dt.rho_min), dt.rho_max);
