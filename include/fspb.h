@@ -462,9 +462,12 @@ int fspb_gamma(const float* ref, const float* eval, int nx, int ny, int nz, floa
                float dz, const fspb_gamma_params* params, float* gamma, fspb_gamma_stats* stats,
                void* stream);
 
-/* Frees the handle.  NULL-safe.  Waits for queued device work to finish,
- * then returns the handle's device buffers to the library's per-device cache
- * (reused by later fspb_create_geometry calls). */
+/* Frees the handle.  NULL-safe.  Its device buffers return to the library's
+ * per-device cache (reused by later fspb_create_geometry calls) once the work
+ * queued with the handle has finished.  If all of that work went to one
+ * stream, the call does not wait for it (it waits only when more than two
+ * such releases are pending); if the handle was used on several streams or
+ * inside a graph capture, it waits for the whole device first. */
 void fspb_destroy(fspb_geometry* g);
 
 /* Returns every cached device buffer to the HIP runtime.  Buffers of live

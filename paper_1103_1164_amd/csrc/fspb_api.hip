@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <deque>
 #include <functional>
 #include <cmath>
 #include <map>
@@ -52,11 +53,19 @@ int fail(int code, const char* fmt, ...) {
 // Device memory comes from a per-device caching pool: blocks freed by
 // fspb_destroy are kept (by size class) and handed to the next geometry, so a
 // stream of plans does not pay hipMalloc/hipFree on every create.  Sizes are
-// rounded up to classes at most 1/8 above the request.
+// rounded up to classes at most 1/8 above the request.  A destroyed handle's
+// blocks rejoin the pool when an event recorded after its last queued work
+// has completed (pending releases are bounded; see fspb_destroy).
+struct Deferred {
+    int device;
+    hipEvent_t ev;
+    std::vector<std::pair<void*, size_t>> blocks;   // (pointer, class)
+};
 struct Pool {
     std::mutex mu;
     std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;  // (device, class) -> blocks
     size_t cached = 0;
+    std::deque<Deferred> deferred;   // oldest first
 };
 
 Pool& pool() {
@@ -69,6 +78,26 @@ size_t size_class(size_t bytes) {
     size_t top = (size_t)1 << (63 - __builtin_clzll(bytes));
     size_t q = std::max<size_t>(top / 8, 4096);
     return (bytes + q - 1) / q * q;
+}
+
+// Moves the blocks of completed releases into the free lists; while more than
+// `limit` releases are pending, waits for the oldest.  Caller holds pool().mu.
+void reap_locked(size_t limit) {
+    auto& d = pool().deferred;
+    while (!d.empty()) {
+        Deferred& x = d.front();
+        if (hipEventQuery(x.ev) == hipErrorNotReady) {
+            if (d.size() <= limit) break;
+            (void)hipEventSynchronize(x.ev);
+        }
+        (void)hipGetLastError();
+        for (auto& b : x.blocks) {
+            pool().free_blocks[{x.device, b.second}].push_back(b.first);
+            pool().cached += b.second;
+        }
+        (void)hipEventDestroy(x.ev);
+        d.pop_front();
+    }
 }
 
 // Test hook: FSPB_TEST_FAIL_ALLOC=n makes the n-th device allocation after the
@@ -94,6 +123,7 @@ int pool_alloc(int dev, void** p, size_t bytes, size_t* cls_out) {
     *cls_out = cls;
     {
         std::lock_guard<std::mutex> lk(pool().mu);
+        reap_locked((size_t)-1);
         auto it = pool().free_blocks.find({dev, cls});
         if (it != pool().free_blocks.end() && !it->second.empty()) {
             *p = it->second.back();
@@ -213,6 +243,10 @@ struct fspb_geometry {
     hipEvent_t ready = nullptr;
     hipStream_t ready_stream = nullptr;
     bool pending = false;
+    // the stream of the handle's queued work; several streams, or work
+    // captured into a graph, make fspb_destroy wait for the whole device
+    hipStream_t last_stream = nullptr;
+    bool stream_known = false, multi_stream = false;
     TileCfg tile;
     std::vector<int> h_cost;   // host copy of cost (fetched when a batch needs it)
     bool h_cost_valid = false;
@@ -381,9 +415,19 @@ static int settle_host(fspb_geometry* g) {
     return FSPB_OK;
 }
 
+static void note_stream(fspb_geometry* g, hipStream_t s) {
+    if (g->stream_known && g->last_stream != s) g->multi_stream = true;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) (void)hipGetLastError();
+    if (st != hipStreamCaptureStatusNone) g->multi_stream = true;
+    g->last_stream = s;
+    g->stream_known = true;
+}
+
 // Orders work on stream s after the handle's creation work (on the creation
-// stream that order holds already).
+// stream that order holds already) and notes the stream.
 static int settle(fspb_geometry* g, hipStream_t s) {
+    note_stream(g, s);
     return (!g->pending || s == g->ready_stream) ? FSPB_OK : settle_host(g);
 }
 
@@ -822,6 +866,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     HIP_TRY(hipEventRecord(G->ready, s));     // end of the creation work
     G->ready_stream = s;
     G->pending = true;
+    note_stream(G, s);
     return FSPB_OK;
 }
 
@@ -997,12 +1042,38 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
 
 void fspb_destroy(fspb_geometry* g) {
     if (!g) return;
-    (void)hipDeviceSynchronize();
+    // with all queued work on one stream, the buffers return to the pool
+    // once that work is done, without waiting here; at most
+    // kMaxPendingReleases handles wait so
+    constexpr size_t kMaxPendingReleases = 2;
+    hipEvent_t ev = nullptr;
+    bool deferred = false;
+    if (g->stream_known && !g->multi_stream &&
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+        if (hipEventRecord(ev, g->last_stream) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(pool().mu);
+            pool().deferred.push_back({g->device, ev, std::move(g->blocks)});
+            g->blocks.clear();
+            reap_locked(kMaxPendingReleases);
+            deferred = true;
+        } else {
+            (void)hipEventDestroy(ev);
+        }
+    }
+    if (!deferred) {
+        (void)hipGetLastError();
+        (void)hipDeviceSynchronize();
+    }
     g->release();
     delete g;
 }
 
 int fspb_release_cached_memory(void) {
+    HIP_TRY(hipDeviceSynchronize());
+    {
+        std::lock_guard<std::mutex> lk(pool().mu);
+        reap_locked(0);
+    }
     {
         std::lock_guard<std::mutex> lk(g_tables_mu);
         auto& sets = table_sets();
