@@ -795,12 +795,15 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         ALLOC(G->fac, sizeof(float4) * nv);
     }
     HIP_TRY(hipMemcpyAsync(dsmall, small.data(), small_bytes, hipMemcpyHostToDevice, s));
-    // the handle reads its own copy of the CT: create returns once the copy is
-    // taken, while kernels 1-4 may still run
+    // the handle reads its own copy of the CT (taken by the first smoothing
+    // pass, or by a copy without density correction): create returns once
+    // the copy is taken, while kernels 1-4 may still run
     ALLOC(G->rho, sizeof(float) * nv);
-    HIP_TRY(hipMemcpyAsync(G->rho, ct->density, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipEventCreateWithFlags(&G->ready, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(G->ready, s));
+    if (!o.dc_enabled) {
+        HIP_TRY(hipMemcpyAsync(G->rho, ct->density, sizeof(float) * nv, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipEventRecord(G->ready, s));
+    }
 
     // ---- kernels 1-4 ---------------------------------------------------------
     if (o.dc_enabled) {
@@ -814,8 +817,8 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
             ALLOC(G->tmp0, sizeof(float) * nv);
             ALLOC(G->tmp1, sizeof(float) * nv);
         }
-        launch_smooth(G->rho, G->tmp0, G->tmp1, G->rhohat, G->fac, nx, ny, nz, G->w3,
-                      G->smooth_r, G->denstab, G->dens, s);
+        launch_smooth(ct->density, G->rho, G->ready, G->tmp0, G->tmp1, G->rhohat, G->fac, nx, ny,
+                      nz, G->w3, G->smooth_r, G->denstab, G->dens, s);
         HIP_TRY(hipGetLastError());
     }
 #undef ALLOC
@@ -1187,8 +1190,8 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
     if (int rc0 = settle(g, s)) return rc0;
     const PlanConst& P = g->P;
     if (g->dc_created) {
-        launch_smooth(density, g->tmp0, g->tmp1, g->rhohat, g->fac, P.nx, P.ny, P.nz, g->w3,
-                      g->smooth_r, g->denstab, g->dens, s);
+        launch_smooth(density, nullptr, nullptr, g->tmp0, g->tmp1, g->rhohat, g->fac, P.nx, P.ny,
+                      P.nz, g->w3, g->smooth_r, g->denstab, g->dens, s);
         HIP_TRY(hipGetLastError());
     }
     launch_trace(g->frames, g->n_beamlets, density, g->tg, g->tp, g->denstab, g->dens, g->tT,

@@ -40,10 +40,12 @@ __device__ __forceinline__ float smooth_taps(const float* __restrict__ base, int
 __global__ __launch_bounds__(256) void smooth_pass(const float* __restrict__ in,
                                                    float* __restrict__ out, int nx, int ny,
                                                    int nz, int axis,
-                                                   const float* __restrict__ w, int r) {
+                                                   const float* __restrict__ w, int r,
+                                                   float* __restrict__ copy) {
     const int n = nx * ny * nz;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    if (copy) copy[v] = in[v];   // the input grid, copied on the way
     const int i = v % nx;
     const int j = (v / nx) % ny;
     const int k = v / (nx * ny);
@@ -334,18 +336,21 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
 }
 
 // ---------------------------------------------------------------------------
-void launch_smooth(const float* rho, float* tmp0, float* tmp1, float* rhohat, float4* fac,
-                   int nx, int ny, int nz, const float* w3, const int r[3],
-                   const float* dtabs, const DensTabs& dt, hipStream_t s) {
+void launch_smooth(const float* rho, float* copy, hipEvent_t after_copy, float* tmp0, float* tmp1,
+                   float* rhohat, float4* fac, int nx, int ny, int nz, const float* w3,
+                   const int r[3], const float* dtabs, const DensTabs& dt, hipStream_t s) {
     long n = (long)nx * ny * nz;
     int blocks = (int)((n + 255) / 256);
     const float* wx = w3;
     const float* wy = w3 + (2 * r[0] + 1);
     const float* wz = wy + (2 * r[1] + 1);
-    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, rho, tmp0, nx, ny, nz, 0, wx, r[0]);
-    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, (const float*)tmp0, tmp1, nx, ny, nz, 1, wy, r[1]);
-    hipLaunchKernelGGL(smooth_last_factors, dim3(blocks), dim3(256), 0, s, (const float*)tmp1, rho,
-                       rhohat, fac, nx, ny, nz, wz, r[2], dtabs, dt);
+    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, rho, tmp0, nx, ny, nz, 0, wx, r[0],
+                       copy);
+    if (after_copy) (void)hipEventRecord(after_copy, s);
+    hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, (const float*)tmp0, tmp1, nx, ny,
+                       nz, 1, wy, r[1], (float*)nullptr);
+    hipLaunchKernelGGL(smooth_last_factors, dim3(blocks), dim3(256), 0, s, (const float*)tmp1,
+                       copy ? (const float*)copy : rho, rhohat, fac, nx, ny, nz, wz, r[2], dtabs, dt);
 }
 
 void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double lo[3],

@@ -29,9 +29,12 @@ struct TraceInfo {
     double s_entry, margin;
 };
 
-void launch_smooth(const float* rho, float* tmp0, float* tmp1, float* rhohat, float4* fac,
-                   int nx, int ny, int nz, const float* w3, const int r[3],
-                   const float* dtabs, const DensTabs& dt, hipStream_t s);
+// Smoothed density and per-voxel factors from rho.  With copy non-null the
+// first pass also copies rho there (after_copy, if non-null, is recorded
+// once that pass is queued) and the factors read the copy.
+void launch_smooth(const float* rho, float* copy, hipEvent_t after_copy, float* tmp0, float* tmp1,
+                   float* rhohat, float4* fac, int nx, int ny, int nz, const float* w3,
+                   const int r[3], const float* dtabs, const DensTabs& dt, hipStream_t s);
 void launch_setup(const BeamIn* beams, int n_beams, int n_beamlets, const double lo[3],
                   const double hi[3], double step, Frame64* out, hipStream_t s);
 void launch_trace(const Frame64* frames, int n_beamlets, const float* rho, const TraceGrid& g,
