@@ -308,17 +308,30 @@ __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
     return x;
 }
 
-template <bool DC>
-__global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
-                                                    const float* __restrict__ w,
-                                                    float* __restrict__ grad) {
-    __shared__ int s_off[256];
-    __shared__ int s_lo[256];
-    __shared__ int s_vbase[256];     // voxel index of the row's first voxel
-    __shared__ float s_qy[256];      // the row's voxel-centre y and z (relative to P0)
-    __shared__ float s_qz[256];
-    __shared__ int s_wsum[4];
-    __shared__ float s_red[4];
+// NW waves per workgroup; with LW the water table is staged in LDS first,
+// as in dose_forward.
+template <bool DC, int NW, bool LW>
+__global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_beamlets,
+                                                          const float* __restrict__ w,
+                                                          float* __restrict__ grad) {
+    constexpr int NT = NW * kWave;
+    __shared__ int s_off[NT];
+    __shared__ int s_lo[NT];
+    __shared__ int s_vbase[NT];      // voxel index of the row's first voxel
+    __shared__ float s_qy[NT];       // the row's voxel-centre y and z (relative to P0)
+    __shared__ float s_qz[NT];
+    __shared__ int s_wsum[NW];
+    __shared__ float s_red[NW];
+    extern __shared__ float4 s_water[];
+    if (LW) {
+        const int n = a.P.dt_n;
+        const FSPB_GLOBAL float4* __restrict__ g = as_global(a.dtab);
+        for (int q = threadIdx.x; q < 3 * n; q += NT) {
+            const int plane = q / n, j = q - plane * n;
+            s_water[3 * j + plane] = g[q];
+        }
+        __syncthreads();
+    }
     const PlanConst& P = a.P;
     // each XCD (workgroups are dealt round-robin to the 8 XCDs) takes a
     // contiguous run of beamlets, whose ROI cylinders overlap, so that the
@@ -344,7 +357,7 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
         const FSPB_GLOBAL float4* __restrict__ facs = as_global(a.fac);
         const FSPB_GLOBAL float* __restrict__ wv = as_global(w);
         const int n_rows = P.ny * P.nz;
-        for (int r0 = 0; r0 < n_rows; r0 += 256) {
+        for (int r0 = 0; r0 < n_rows; r0 += NT) {
             const int row = r0 + tid;
             int lo = 0, len = 0;
             if (row < n_rows) {
@@ -390,25 +403,25 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
             if (lane == kWave - 1) s_wsum[wid] = incl;
             __syncthreads();
             int base = 0, total = 0;
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < NW; ++q) {
                 if (q < wid) base += s_wsum[q];
                 total += s_wsum[q];
             }
             s_off[tid] = base + incl - len;
             s_lo[tid] = lo;
             __syncthreads();
-            for (int e0 = wid * kWave; e0 < total; e0 += 256) {
+            for (int e0 = wid * kWave; e0 < total; e0 += NT) {
                 // a wave takes 64 consecutive items: the row of its first item
                 // is found once (same address on every lane), then each lane
                 // steps forward over the few rows its own item lies beyond
                 const int e = e0 + lane;
-                int rlo = 0, rhi = 255;
+                int rlo = 0, rhi = NT - 1;
                 while (rlo < rhi) {
                     int mid = (rlo + rhi + 1) >> 1;
                     if (s_off[mid] <= e0) rlo = mid;
                     else rhi = mid - 1;
                 }
-                while (rlo < 255 && s_off[rlo + 1] <= e) ++rlo;
+                while (rlo < NT - 1 && s_off[rlo + 1] <= e) ++rlo;
                 if (e >= total) continue;
                 const int i = s_lo[rlo] + (e - s_off[rlo]);
                 // the voxel centre as voxel_q computes it (same pair decisions
@@ -419,12 +432,16 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
                     const unsigned v = (unsigned)(s_vbase[rlo] + i);
                     float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                     if (DC) fac = facs[v];
-                    acc = fmaf(wv[v], pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
-                                                    WaterGlobal{as_global(a.dtab), P.dt_n},
-                                                    as_global(a.atab),
-                                                    as_global(a.tT), as_global(a.tTW),
-                                                    as_global(a.tW2)),
-                               acc);
+                    const float pd =
+                        LW ? pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                           WaterLds{(const FSPB_LDS float4*)s_water},
+                                           as_global(a.atab), as_global(a.tT), as_global(a.tTW),
+                                           as_global(a.tW2))
+                           : pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                           WaterGlobal{as_global(a.dtab), P.dt_n},
+                                           as_global(a.atab), as_global(a.tT), as_global(a.tTW),
+                                           as_global(a.tW2));
+                    acc = fmaf(wv[v], pd, acc);
                 }
             }
             __syncthreads();
@@ -433,7 +450,16 @@ __global__ __launch_bounds__(256) void dose_adjoint(DoseArgs a, int n_beamlets,
     acc = wave_sum(acc);
     if (lane == 0) s_red[wid] = acc;
     __syncthreads();
-    if (tid == 0) grad[ib] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    if (tid == 0) {
+        float sum[NW];   // fixed pairwise tree over the waves
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum[q] = s_red[q];
+#pragma unroll
+        for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+            for (int q = 0; q < h; ++q) sum[q] = sum[q] + sum[q + h];
+        grad[ib] = sum[0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -684,11 +710,23 @@ void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStr
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     hipStream_t s) {
-    dim3 grid(8 * ((n_beamlets + 7) / 8)), block(256);
-    if (dc)
-        hipLaunchKernelGGL((dose_adjoint<true>), grid, block, 0, s, a, n_beamlets, w, grad);
+    // with the water table in LDS, 8-wave workgroups (three per CU fit in
+    // registers and LDS); else 4-wave workgroups reading it from global memory
+    const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
+    const bool lw = water_bytes <= (size_t)kLdsWaterMax;
+    dim3 grid(8 * ((n_beamlets + 7) / 8));
+    if (lw && dc)
+        hipLaunchKernelGGL((dose_adjoint<true, 8, true>), grid, dim3(8 * kWave), water_bytes, s, a,
+                           n_beamlets, w, grad);
+    else if (lw)
+        hipLaunchKernelGGL((dose_adjoint<false, 8, true>), grid, dim3(8 * kWave), water_bytes, s, a,
+                           n_beamlets, w, grad);
+    else if (dc)
+        hipLaunchKernelGGL((dose_adjoint<true, 4, false>), grid, dim3(4 * kWave), 0, s, a,
+                           n_beamlets, w, grad);
     else
-        hipLaunchKernelGGL((dose_adjoint<false>), grid, block, 0, s, a, n_beamlets, w, grad);
+        hipLaunchKernelGGL((dose_adjoint<false, 4, false>), grid, dim3(4 * kWave), 0, s, a,
+                           n_beamlets, w, grad);
 }
 
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,
