@@ -349,6 +349,7 @@ def siddon_c2(plan, dens, flu, time_loop, n=10):
             g = make(sd)
             g.forward(flu)
             g.close()
+            torch.cuda.synchronize()     # the plan's latency: geometry + forward done
             if k >= 2:
                 per.append((time.perf_counter() - t0) * 1e3)
         geo = make(sd)
@@ -402,7 +403,8 @@ def paper_cases(time_loop, n=10):
             t0 = time.perf_counter()
             g = make()
             g.forward(flu, out=dose)
-            g.close()                    # waits for the forward
+            g.close()
+            torch.cuda.synchronize()     # the plan's latency: geometry + forward done
             per.append((time.perf_counter() - t0) * 1e3)
         step_ms = float(np.mean(per))
         geo = make()
