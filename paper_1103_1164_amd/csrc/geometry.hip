@@ -303,12 +303,17 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
 
     // tables: T_j = sum_{l<j} d (rho_l + rho_{l+1}) / 2 from the entrance,
     // W_c likewise with b_c(clamped rho); exclusive wave scans in FP64.
+    // The samples of the next 64 are gathered while the current ones are
+    // scanned; the first of them is the last lane's right neighbour.
     double cT = 0.0, c1 = 0.0, c2 = 0.0;
+    double r_next = (lane < K) ? sample(ke + lane) : 0.0;
     for (int base = 0; base < K; base += kWave) {
-        int j = base + lane;
-        double r = (j < K) ? sample(ke + j) : 0.0;
+        const int j = base + lane;
+        const double r = r_next;
+        r_next = (j + kWave < K) ? sample(ke + j + kWave) : 0.0;
         double rn = __shfl_down(r, 1, kWave);
-        if (lane == kWave - 1) rn = (j + 1 < K) ? sample(ke + j + 1) : 0.0;
+        const double first_next = __shfl(r_next, 0, kWave);
+        if (lane == kWave - 1) rn = first_next;
         double rc = fmin(fmax(r, (double)dt.rho_min), (double)dt.rho_max);
         double rcn = fmin(fmax(rn, (double)dt.rho_min), (double)dt.rho_max);
         bool has_next = j + 1 < K;
