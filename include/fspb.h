@@ -165,8 +165,9 @@ typedef struct {
  * returns once that copy is complete, so the caller may free or overwrite
  * ct->density afterwards; the geometry kernels may still be running on
  * stream.  Later calls on the same stream are ordered after them; a call on
- * another stream, or one that reads results on the host, first waits for
- * them.
+ * another stream makes that stream wait for them on the device (on the host
+ * while the stream captures a graph), and a call that reads results on the
+ * host waits for them on the host.
  *   ct      host struct; ct->density device.
  *   beams   host array [n_beams].
  *   tables  host struct with host arrays (copied).
@@ -229,6 +230,13 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info,
  * [n_vox]) must stay valid until the work has run.  The brick schedule of the
  * forward kernel is kept from the previous density. */
 int fspb_update_density(fspb_geometry* g, const float* density, void* stream);
+
+/* Makes stream wait, on the device, for the handle's creation work (a no-op
+ * on the creation stream or once that work is known to be done).  For
+ * callers that create plans on one stream and use them on another and want
+ * their own work on that stream -- or a timing event -- ordered after the
+ * geometry; the library's own calls order themselves.  Asynchronous. */
+int fspb_wait_ready(fspb_geometry* g, void* stream);
 
 /* ---- forward-kernel tiling and autotuning -------------------------------
  * The forward kernel assigns one 64-voxel brick to each wavefront.  Brick
@@ -464,9 +472,9 @@ int fspb_gamma(const float* ref, const float* eval, int nx, int ny, int nz, floa
 
 /* Frees the handle.  NULL-safe.  Its device buffers return to the library's
  * per-device cache (reused by later fspb_create_geometry calls) once the work
- * queued with the handle has finished.  If all of that work went to one
- * stream, the call does not wait for it (it waits only when more than two
- * such releases are pending); if the handle was used on several streams or
+ * queued with the handle has finished.  If that work went to at most four
+ * streams, the call does not wait for it (it waits only when more than two
+ * such releases are pending); if the handle was used on more streams or
  * inside a graph capture, it waits for the whole device first. */
 void fspb_destroy(fspb_geometry* g);
 

@@ -172,6 +172,11 @@ class Geometry:
               "fspb_count_pairs")
         return (int(tot.value), counts) if per_voxel else int(tot.value)
 
+    def wait_ready(self, stream=None) -> None:
+        """Makes stream (default: the current one) wait on the device for this
+        plan's creation work, e.g. before recording a timing event there."""
+        check(load().fspb_wait_ready(self._handle(), _stream(stream)), "fspb_wait_ready")
+
     def update_density(self, density: torch.Tensor, stream=None) -> None:
         """Re-runs the density-dependent geometry (smoothing, entrances, depth
         tables) for a new CT of the same grid; asynchronous, graph-capturable.

@@ -114,6 +114,7 @@ SIGNATURES = {
                                C.POINTER(C.c_float), C.POINTER(C.c_float),
                                C.POINTER(C.c_float), C.c_int]),
     "fspb_update_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_wait_ready": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fspb_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.c_int]),
     "fspb_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "fspb_get_tile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),

@@ -58,7 +58,7 @@ int fail(int code, const char* fmt, ...) {
 // has completed (pending releases are bounded; see fspb_destroy).
 struct Deferred {
     int device;
-    hipEvent_t ev;
+    std::vector<hipEvent_t> evs;                    // one per stream the handle used
     std::vector<std::pair<void*, size_t>> blocks;   // (pointer, class)
 };
 struct Pool {
@@ -86,16 +86,19 @@ void reap_locked(size_t limit) {
     auto& d = pool().deferred;
     while (!d.empty()) {
         Deferred& x = d.front();
-        if (hipEventQuery(x.ev) == hipErrorNotReady) {
+        bool done = true;
+        for (hipEvent_t ev : x.evs)
+            if (hipEventQuery(ev) == hipErrorNotReady) done = false;
+        if (!done) {
             if (d.size() <= limit) break;
-            (void)hipEventSynchronize(x.ev);
+            for (hipEvent_t ev : x.evs) (void)hipEventSynchronize(ev);
         }
         (void)hipGetLastError();
         for (auto& b : x.blocks) {
             pool().free_blocks[{x.device, b.second}].push_back(b.first);
             pool().cached += b.second;
         }
-        (void)hipEventDestroy(x.ev);
+        for (hipEvent_t ev : x.evs) (void)hipEventDestroy(ev);
         d.pop_front();
     }
 }
@@ -243,10 +246,11 @@ struct fspb_geometry {
     hipEvent_t ready = nullptr;
     hipStream_t ready_stream = nullptr;
     bool pending = false;
-    // the stream of the handle's queued work; several streams, or work
-    // captured into a graph, make fspb_destroy wait for the whole device
-    hipStream_t last_stream = nullptr;
-    bool stream_known = false, multi_stream = false;
+    // the streams of the handle's queued work (release waits for each); more
+    // than kMaxHandleStreams, or work captured into a graph, make
+    // fspb_destroy wait for the whole device
+    std::vector<hipStream_t> streams;
+    bool many_streams = false;
     TileCfg tile;
     std::vector<int> h_cost;   // host copy of cost (fetched when a batch needs it)
     bool h_cost_valid = false;
@@ -415,20 +419,42 @@ static int settle_host(fspb_geometry* g) {
     return FSPB_OK;
 }
 
-static void note_stream(fspb_geometry* g, hipStream_t s) {
-    if (g->stream_known && g->last_stream != s) g->multi_stream = true;
+constexpr size_t kMaxHandleStreams = 4;
+
+static bool capturing(hipStream_t s) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &st) != hipSuccess) (void)hipGetLastError();
-    if (st != hipStreamCaptureStatusNone) g->multi_stream = true;
-    g->last_stream = s;
-    g->stream_known = true;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st != hipStreamCaptureStatusNone;
 }
 
-// Orders work on stream s after the handle's creation work (on the creation
-// stream that order holds already) and notes the stream.
+// Notes a stream the handle's work goes to; returns whether s is capturing.
+static bool note_stream(fspb_geometry* g, hipStream_t s) {
+    const bool cap = capturing(s);
+    if (cap) g->many_streams = true;
+    if (std::find(g->streams.begin(), g->streams.end(), s) == g->streams.end()) {
+        if (g->streams.size() < kMaxHandleStreams) g->streams.push_back(s);
+        else g->many_streams = true;
+    }
+    return cap;
+}
+
+// Orders work on stream s after the handle's creation work: on the creation
+// stream that order holds already; another stream waits for the ready event
+// on the device (or, while capturing a graph, on the host).
 static int settle(fspb_geometry* g, hipStream_t s) {
-    note_stream(g, s);
-    return (!g->pending || s == g->ready_stream) ? FSPB_OK : settle_host(g);
+    const bool cap = note_stream(g, s);
+    if (!g->pending || s == g->ready_stream) return FSPB_OK;
+    if (hipEventQuery(g->ready) == hipSuccess) {
+        g->pending = false;
+        return FSPB_OK;
+    }
+    (void)hipGetLastError();
+    if (cap) return settle_host(g);
+    HIP_TRY(hipStreamWaitEvent(s, g->ready, 0));
+    return FSPB_OK;
 }
 
 int fspb_geometry::fetch_host() const {
@@ -1045,22 +1071,34 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
 
 void fspb_destroy(fspb_geometry* g) {
     if (!g) return;
-    // with all queued work on one stream, the buffers return to the pool
-    // once that work is done, without waiting here; at most
+    // with the queued work on a few known streams, the buffers return to the
+    // pool once the work on each is done, without waiting here; at most
     // kMaxPendingReleases handles wait so
     constexpr size_t kMaxPendingReleases = 2;
-    hipEvent_t ev = nullptr;
     bool deferred = false;
-    if (g->stream_known && !g->multi_stream &&
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-        if (hipEventRecord(ev, g->last_stream) == hipSuccess) {
+    if (!g->streams.empty() && !g->many_streams) {
+        std::vector<hipEvent_t> evs;
+        bool ok = true;
+        for (hipStream_t st : g->streams) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            evs.push_back(ev);
+            if (hipEventRecord(ev, st) != hipSuccess) {
+                ok = false;
+                break;
+            }
+        }
+        if (ok) {
             std::lock_guard<std::mutex> lk(pool().mu);
-            pool().deferred.push_back({g->device, ev, std::move(g->blocks)});
+            pool().deferred.push_back({g->device, std::move(evs), std::move(g->blocks)});
             g->blocks.clear();
             reap_locked(kMaxPendingReleases);
             deferred = true;
         } else {
-            (void)hipEventDestroy(ev);
+            for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
         }
     }
     if (!deferred) {
@@ -1182,6 +1220,11 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     if (rc) return rc;
     if (n_results) *n_results = n;
     return fspb_set_tile(g, best.shape, best.waves_per_block, stream);
+}
+
+int fspb_wait_ready(fspb_geometry* g, void* stream) {
+    if (!g) return fail(FSPB_E_ARG, "wait_ready: NULL handle");
+    return settle(g, (hipStream_t)stream);
 }
 
 int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {

@@ -49,6 +49,8 @@ def test_other_stream_and_overwritten_ct_right_after_create(dc):
     geo = _make(plan, dens, dc, stream=s1)
     with torch.cuda.stream(s2):
         dens.fill_(7.0)
+    if dc:
+        geo.wait_ready(s2)                 # explicit wait (the forward also orders itself)
     geo.forward(f, out=out, stream=s2)
     s2.synchronize()
     assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
