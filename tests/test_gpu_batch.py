@@ -100,8 +100,15 @@ def test_water_table_too_large_for_lds(oracle_mod, dc):
     d8 = gpu_dose(geo, plan.fluence)
     geo.set_tile(0, 4)
     assert np.array_equal(gpu_dose(geo, plan.fluence), d8)
-    d_o, amb, _ = oracle_mod.Oracle(plan, dc_enabled=dc).dose()
+    orc = oracle_mod.Oracle(plan, dc_enabled=dc)
+    d_o, amb, _ = orc.dose()
     assert_dose_parity(d8, d_o, amb, what="fine water tables")
+    # the adjoint's global-memory path (4-wave workgroups) on the same tables
+    w = np.random.default_rng(3).uniform(0.0, 1.0, plan.n_vox).astype(np.float32)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    g_o, g_amb = orc.adjoint(w)
+    scale = float(np.max(np.abs(g_o)))
+    assert np.all(np.abs(g - g_o) <= 1e-4 * scale + g_amb), float(np.max(np.abs(g - g_o)) / scale)
     other = _plans()[1]
     g1 = geometry(other, dc)
     ref1 = gpu_dose(g1, other.fluence)
