@@ -231,7 +231,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
 // tables up to 853 samples).
 
 template <bool DC, int MODE, int BX, int BY, int BZ, bool LW>
-__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256) void dose_forward(
+__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward(
     DoseArgs a, const int* __restrict__ order, const float* __restrict__ fluence,
     float* __restrict__ dose, int* __restrict__ out_int, const float4* __restrict__ prm) {
     extern __shared__ float4 s_water[];
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256) void dose_forward(
 // With LW every plan uses the same water table (water, n samples), which
 // the workgroup stages in LDS as dose_forward does.
 template <bool DC, int BX, int BY, int BZ, bool LW>
-__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256) void dose_forward_batch(
+__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward_batch(
     const DoseArgs* __restrict__ plans, const int2* __restrict__ items,
     const int* __restrict__ wave_begin, int n_waves, BatchPtrs ptrs,
     unsigned long long* __restrict__ ts_done, unsigned long long* __restrict__ ts_start,

@@ -102,6 +102,37 @@ __device__ __forceinline__ float penumbra2(float ul, float dm, float dp, float s
     return fmaf(sg, e1, o2 - e2);
 }
 
+// The two Eq. 3 profile products, 2 p_x(u_ax) 2 p_y(u_ay) for the steepness
+// pairs (u1x, u1y) and (u2x, u2y) (times log2 e), at isocentre-plane offsets
+// (x, y) from the axis of a beamlet of half widths (x0, y0).  Outside the box
+// along both axes, 2 p_x = e^{-u_x(|x| - x0)} (1 - e^{-2 u_x x0}), so
+//   2 p_x 2 p_y = e^{-u_x(|x| - x0) - u_y(|y| - y0)} (1 - e^{-2 u_x x0}) (1 - e^{-2 u_y y0}):
+// three exponentials per product instead of four.  That form is taken when
+// every active lane of the wave lies outside the box along both axes (most
+// pairs: the box is a beamlet wide, the ROI ten times wider); otherwise the
+// general form of penumbra2.
+__device__ __forceinline__ void profile_products(float x, float y, float x0, float y0, float u1x,
+                                                 float u1y, float u2x, float u2y, float& p1,
+                                                 float& p2) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float ox = ax - x0, oy = ay - y0;   // signed distances past the box edge
+    const bool outer = (ox > 0.0f) & (oy > 0.0f);
+    if (__ballot(!outer) == 0) {              // wave-uniform branch
+        const float x2 = x0 + x0, y2 = y0 + y0;
+        p1 = fast_exp2(-fmaf(u1x, ox, u1y * oy)) * (1.0f - fast_exp2(-u1x * x2)) *
+             (1.0f - fast_exp2(-u1y * y2));
+        p2 = fast_exp2(-fmaf(u2x, ox, u2y * oy)) * (1.0f - fast_exp2(-u2x * x2)) *
+             (1.0f - fast_exp2(-u2y * y2));
+    } else {
+        const float dmx = fabsf(ox), dpx = ax + x0;
+        const float dmy = fabsf(oy), dpy = ay + y0;
+        const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
+        const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
+        p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
+        p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
+    }
+}
+
 __device__ __forceinline__ float fract(float x) { return __builtin_amdgcn_fractf(x); }
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {
     return __builtin_amdgcn_fmed3f(x, lo, hi);
@@ -201,14 +232,8 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
 
     // Eq. 3 with the Eq. 4 profiles
-    const float ax = fabsf(x), ay = fabsf(y);
-    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
-    const float dmx = fabsf(ox), dpx = ax + b.x0;
-    const float dmy = fabsf(oy), dpy = ay + b.y0;
-    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
-    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
-    float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
-    float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
+    float p1, p2;
+    profile_products(x, y, b.x0, b.y0, u1x, u1y, u2x, u2y, p1, p2);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
@@ -260,14 +285,8 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
         w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
     }
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
-    const float ax = fabsf(x), ay = fabsf(y);
-    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
-    const float dmx = fabsf(ox), dpx = ax + b.x0;
-    const float dmy = fabsf(oy), dpy = ay + b.y0;
-    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
-    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
-    float p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
-    float p2 = penumbra2(u2x, dmx, dpx, sgx, o2x) * penumbra2(u2y, dmy, dpy, sgy, o2y);
+    float p1, p2;
+    profile_products(x, y, b.x0, b.y0, u1x, u1y, u2x, u2y, p1, p2);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
@@ -321,14 +340,8 @@ __device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, fl
     const float fa = fract(ca);
     const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
-    const float ax = fabsf(x), ay = fabsf(y);
-    const float ox = ax - b.x0, oy = ay - b.y0;   // signed distances past the box edge
-    const float dmx = fabsf(ox), dpx = ax + b.x0;
-    const float dmy = fabsf(oy), dpy = ay + b.y0;
-    const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
-    const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
-    float p1 = penumbra2(ul.x, dmx, dpx, sgx, o2x) * penumbra2(ul.y, dmy, dpy, sgy, o2y);
-    float p2 = penumbra2(ul.z, dmx, dpx, sgx, o2x) * penumbra2(ul.w, dmy, dpy, sgy, o2y);
+    float p1, p2;
+    profile_products(x, y, b.x0, b.y0, ul.x, ul.y, ul.z, ul.w, p1, p2);
     float F = fmaf(wv.x, p1, wv.y * p2);
     return F * A * isq;
 }

@@ -1,9 +1,14 @@
 """Batched persistent launch, HIP-graph replay, density updates and tile
 configurations (run on an MI355X).
 
-Every voxel sums its pairs in the same order whatever the tile shape, the
-schedule or the launch path, so these tests demand bitwise equality with the
-single-plan forward, which test_gpu_parity.py checks against the oracle."""
+Every voxel sums its pairs in the same order whatever the schedule, the
+launch path or the number of waves per workgroup, and a wave evaluates the
+same pairs for a given brick shape, so these tests demand bitwise equality
+with the single-plan forward of the same brick shape (test_gpu_parity.py
+checks that against the oracle).  Across brick shapes a pair may be
+evaluated by a different one of the two exact forms of its Eq. 4 profile
+product (the form is chosen per wave), so doses agree to rounding: within
+SHAPE_TOL of the maximum dose."""
 import json
 
 import numpy as np
@@ -14,6 +19,8 @@ import fspb_synth as S
 from gpu_helpers import assert_dose_parity, geometry, gpu_dose, say
 
 pytestmark = pytest.mark.gpu
+
+SHAPE_TOL = 2e-6    # relative to max dose: a few FP32 ulps per pair, summed
 
 
 def _plans():
@@ -35,11 +42,17 @@ def test_tile_configurations_agree(dc):
     ref = gpu_dose(geo, plan.fluence)
     shapes = Geometry.tile_shapes()
     assert len(shapes) >= 2 and all(int(np.prod(s)) == 64 for s in shapes)
+    scale = float(np.max(np.abs(ref)))
     for sh in range(len(shapes)):
+        first = None
         for wpb in (1, 2, 4, 8):          # 8: water table staged in LDS
             geo.set_tile(sh, wpb)
             assert geo.get_tile() == (sh, wpb)
-            assert np.array_equal(gpu_dose(geo, plan.fluence), ref), (sh, wpb)
+            d = gpu_dose(geo, plan.fluence)
+            if first is None:
+                first = d
+            assert np.array_equal(d, first), (sh, wpb)       # same shape: bitwise
+            assert np.max(np.abs(d - ref)) <= SHAPE_TOL * scale, (sh, wpb)
             n = geo.count_pairs(torch.as_tensor(plan.fluence, device="cuda"))
             if sh == 0 and wpb == 1:
                 n0 = n
@@ -51,11 +64,14 @@ def test_batch_equals_single_plan(dc):
     from paper_1103_1164_amd import Batch
     plans = _plans()
     geos = [geometry(p, dc) for p in plans]
-    refs = [gpu_dose(g, p.fluence) for g, p in zip(geos, plans)]
     fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
     for shape, wpb, wpc, pol in ((0, 4, 32, "throughput"), (1, 2, 8, "latency"),
                                  (0, 1, 1, "throughput"), (2, 4, 16, "latency"),
                                  (0, 8, 32, "latency"), (3, 8, 8, "throughput")):
+        refs = []                          # single-plan forwards with the batch's shape
+        for g, p in zip(geos, plans):
+            g.set_tile(shape, 4)
+            refs.append(gpu_dose(g, p.fluence))
         b = Batch(geos, shape=shape, waves_per_block=wpb, waves_per_cu=wpc, policy=pol)
         out = [torch.full(p.shape, -1.0, device="cuda") for p in plans]
         b.forward(fl, out)
@@ -182,7 +198,8 @@ def test_autotune_and_cache(tmp_path):
     r1 = tune(geo, f, cache=cache, reps=2)
     assert not r1["cached"] and len(r1["all"]) == 4 * len(geo.tile_shapes())
     assert geo.get_tile() == (r1["shape"], r1["waves_per_block"])
-    assert np.array_equal(gpu_dose(geo, plan.fluence), ref)
+    got = gpu_dose(geo, plan.fluence)
+    assert np.max(np.abs(got - ref)) <= SHAPE_TOL * float(np.max(np.abs(ref)))
     geo2 = geometry(plan, 1)
     r2 = tune(geo2, f, cache=cache)
     assert r2["cached"] and geo2.get_tile() == geo.get_tile()

@@ -92,8 +92,9 @@ def test_siddon_update_density_and_limits():
     with pytest.raises(FspbError) as e:
         geo.adjoint(torch.ones(p0.n_vox, device="cuda"))
     assert e.value.code == -4
-    # counts and tiles work; tile choice does not change the dose
+    # counts and tiles work; another brick shape changes the dose by rounding
+    # only (a pair's Eq. 4 form is chosen per wave)
     ref = gpu_dose(geo, p0.fluence)
     geo.set_tile(1, 2)
-    assert np.array_equal(gpu_dose(geo, p0.fluence), ref)
+    assert np.max(np.abs(gpu_dose(geo, p0.fluence) - ref)) <= 2e-6 * float(np.max(ref))
     assert geo.count_pairs(torch.as_tensor(p0.fluence, device="cuda")) > 0
