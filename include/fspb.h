@@ -262,7 +262,8 @@ typedef struct {
 int fspb_tile_shapes(int* dims, int max_shapes);
 
 /* Selects the tile configuration of a handle (recomputes its brick schedule
- * on the stream when the shape changes). */
+ * on the stream when the shape changes; calls on other streams then wait for
+ * that work on the device, as after fspb_create_geometry). */
 int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream);
 int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block);
 

@@ -1153,12 +1153,22 @@ int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream
     if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
         waves_per_block != kLdsWaves)
         return fail(FSPB_E_ARG, "set_tile: waves_per_block must be 1, 2, 4 or 8");
-    int rc = settle(g, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = settle(g, s);
     if (rc) return rc;
     const bool rebuild = shape != g->tile.shape;
     g->tile.shape = shape;
     g->tile.waves_per_block = waves_per_block;
-    return rebuild ? build_order(g, (hipStream_t)stream) : FSPB_OK;
+    if (!rebuild) return FSPB_OK;
+    if ((rc = build_order(g, s)) != FSPB_OK) return rc;
+    // like the creation work, the new schedule is awaited by other streams
+    // (outside graph capture; a captured rebuild is ordered by its graph)
+    if (g->ready && !capturing(s)) {
+        HIP_TRY(hipEventRecord(g->ready, s));
+        g->ready_stream = s;
+        g->pending = true;
+    }
+    return FSPB_OK;
 }
 
 int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block) {
