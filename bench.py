@@ -50,13 +50,24 @@ FORWARD_SOURCES = ("dose.hip", "pair.h", "kernels.h", "fspb_internal.h")
 PMC_SUMMARY = ROOT / "profiles" / "dose_forward_c2_pmc.md"
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed (string
+    literals in these files hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def forward_source_hash() -> str:
-    """SHA-256 over the forward kernel's sources: HBM counters taken on
-    another version of the kernel do not describe this one."""
+    """SHA-256 over the code of the forward kernel's sources (comments and
+    layout excluded): HBM counters taken on another version of the kernel do
+    not describe this one."""
     import hashlib
     h = hashlib.sha256()
     for name in FORWARD_SOURCES:
-        h.update((ROOT / "paper_1103_1164_amd" / "csrc" / name).read_bytes())
+        h.update(name.encode())
+        h.update(_code_only((ROOT / "paper_1103_1164_amd" / "csrc" / name).read_text()).encode())
     return h.hexdigest()
 
 

@@ -1,20 +1,23 @@
 // dose.hip -- the dose superposition (Eq. 1 over Eqs. 2-4; Algorithm A2
 // kernel 5), its transpose, and the evaluated-pair count, for gfx950.
 //
-// Forward: voxel-major.  A wavefront owns a 4x4x4 brick of voxels (one per
-// lane).  For each beam it projects its voxels onto the isocentre plane and
+// Forward: voxel-major.  A wavefront owns a 64-voxel brick (4x4x4 by default,
+// one voxel per lane); with 8-wave workgroups the commissioned water table is
+// first staged in LDS.  For each beam it projects its voxels onto the isocentre plane and
 // reduces the projections across the wave to a rectangle of beamlets whose
 // 5 cm ROI cylinder can reach the brick.  The rectangle is filtered 64
 // beamlets at a time (one per lane) against the brick's bounding sphere and
 // the survivors are compacted; the wave then walks them with wave-uniform
 // beamlet descriptors (scalar loads), each lane testing its own voxel exactly
-// and evaluating the pair in FP32.  Each voxel is written once: no atomics,
-// and the result does not depend on scheduling.
+// and evaluating the pair in FP32 (with one of two exact forms of the Eq. 4
+// profile product, chosen per wave; see pair.h).  Each voxel is written once:
+// no atomics, and the result does not depend on scheduling.
 //
 // Adjoint: beamlet-major.  A workgroup owns one beamlet.  It walks the grid
 // row by row (rows along x); for each row it solves for the x-interval that
-// can lie inside the ROI past the entrance, compacts the intervals of 256 rows
-// with a block scan, and spreads the voxels of those intervals over its lanes.
+// can lie inside the ROI past the entrance, compacts the intervals of a batch
+// of rows (one per thread) with a block scan, and spreads the voxels of those
+// intervals over its lanes.
 // Partial sums are reduced in a fixed order, so the gradient is deterministic.
 #include "kernels.h"
 #include "pair.h"
