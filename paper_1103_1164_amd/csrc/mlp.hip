@@ -554,6 +554,14 @@ __device__ __forceinline__ void copy_rows16(__bf16* dst, int dst_stride, const _
     }
 }
 
+// Orders a wave's LDS writes before its later LDS reads (by other lanes of
+// the same wave) without waiting for the other waves of the workgroup.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                                                               const float* __restrict__ rho,
                                                               const float* __restrict__ rhohat,
@@ -637,7 +645,7 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                     h1[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[nt][j] + L.b1[col]);
             }
         }
-        __syncthreads();
+        wave_sync();
         if (any) {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
@@ -652,7 +660,7 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                     h2[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[j] + L.b2[col]);
             }
         }
-        __syncthreads();
+        wave_sync();
         if (any) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -663,7 +671,7 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                 for (int j = 0; j < 4; ++j) yl[(4 * (lane >> 4) + j) * 8 + fr] = acc[j] + L.b3[fr];
             }
         }
-        __syncthreads();
+        wave_sync();
         if (lane < 16 && row_in) {
             float o[kMlpOut];
             bool fb = !live;
@@ -684,9 +692,10 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
             prm[2 * ((long)b * n_vox + v)] = ul;
             prm[2 * ((long)b * n_vox + v) + 1] = wv;
         }
-        // the next group's layer-1 writes must not overtake this epilogue's
-        // reads of y (different buffer) or layer 3's reads of h2: the next
-        // barrier after layer 1 orders them
+        // each wave reads and writes only its own h1, h2 and y (the weights
+        // are read-only here), so waves need not wait for one another: a
+        // wave's LDS accesses complete in order, and wave_sync keeps the
+        // compiler from moving them across the layer boundaries
     }
 }
 
