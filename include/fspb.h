@@ -143,6 +143,12 @@ typedef struct {
     float sample_step;
     int dc_enabled;
     long long device_bytes;
+    /* weight-drift tables a density-corrected pair reads: 1 when the
+     * commissioned b2 equals drift_ratio * b1 at every sample of one density
+     * grid (Section 2.1's single b: drift_ratio = 1), so that the second
+     * drift is drift_ratio * W1; 2 otherwise (a table per component) */
+    int drift_tables;
+    float drift_ratio;
 } fspb_info;
 
 /* Per-beamlet geometry and tables, for inspection and tests. */

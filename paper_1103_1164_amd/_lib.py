@@ -59,7 +59,8 @@ class fspb_info(C.Structure):
                 ("k_stride", C.c_int), ("k_max", C.c_int), ("n_hit", C.c_int),
                 ("n_entry_ambiguous", C.c_int), ("smooth_radius", C.c_int * 3),
                 ("sample_step", C.c_float), ("dc_enabled", C.c_int),
-                ("device_bytes", C.c_longlong)]
+                ("device_bytes", C.c_longlong), ("drift_tables", C.c_int),
+                ("drift_ratio", C.c_float)]
 
 
 class fspb_beamlet_info(C.Structure):

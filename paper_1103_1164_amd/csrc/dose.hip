@@ -63,7 +63,7 @@ __device__ __forceinline__ int bricks_total(const PlanConst& P) {
     return bricks_x<BX, BY, BZ>(P) * bricks_y<BX, BY, BZ>(P) * ((P.nz + BZ - 1) / BZ);
 }
 
-template <bool DC, int MODE, int BX, int BY, int BZ, class WT>
+template <int DC, int MODE, int BX, int BY, int BZ, class WT>
 __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                            const float* fluence_, float* dose_, int* out_int_,
                                            const WT& water, const float4* prm_ = nullptr) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                 ib = first + (n_lo + c / nm) * nbl_x + (m_lo + c % nm);
                 if (MODE == kDose || fluence_) fi = fluence[ib];
                 if (fi != 0.0f) {
-                    const FSPB_GLOBAL float4* dp = bl4 + 6 * ib;   // 96-byte descriptor
+                    const FSPB_GLOBAL float4* dp = bl4 + (sizeof(BeamletDesc) / 16) * ib;
                     const float4 r0 = dp[0], r1 = dp[1], r2 = dp[2];
                     float tc = fmaf(cqx, r0.x, fmaf(cqy, r0.y, fmaf(cqz, r0.z, r0.w)));
                     float xc = fmaf(cqx, r1.x, fmaf(cqy, r1.y, fmaf(cqz, r1.z, r1.w)));
@@ -233,7 +233,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
 // (with 8 waves per workgroup four workgroups, a full CU, fit in LDS for
 // tables up to 853 samples).
 
-template <bool DC, int MODE, int BX, int BY, int BZ, bool LW>
+template <int DC, int MODE, int BX, int BY, int BZ, bool LW>
 __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward(
     DoseArgs a, const int* __restrict__ order, const float* __restrict__ fluence,
     float* __restrict__ dose, int* __restrict__ out_int, const float4* __restrict__ prm) {
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
 // wave's last item of that plan; ts_start[q] the wave's start.  No atomics.
 // With LW every plan uses the same water table (water, n samples), which
 // the workgroup stages in LDS as dose_forward does.
-template <bool DC, int BX, int BY, int BZ, bool LW>
+template <int DC, int BX, int BY, int BZ, bool LW>
 __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward_batch(
     const DoseArgs* __restrict__ plans, const int2* __restrict__ items,
     const int* __restrict__ wave_begin, int n_waves, BatchPtrs ptrs,
@@ -313,7 +313,7 @@ __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
 
 // NW waves per workgroup; with LW the water table is staged in LDS first,
 // as in dose_forward.
-template <bool DC, int NW, bool LW>
+template <int DC, int NW, bool LW>
 __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_beamlets,
                                                           const float* __restrict__ w,
                                                           float* __restrict__ grad) {
@@ -570,7 +570,7 @@ void shape_dims(int shape, int d[3]) {
     d[2] = kShapes[shape].z;
 }
 
-template <bool DC, int MODE>
+template <int DC, int MODE>
 static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                         float* dose, int* out_int, hipStream_t s, const float4* prm = nullptr) {
     const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
@@ -599,28 +599,34 @@ static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const 
 
 void launch_forward(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
                     const float* fluence, float* dose, hipStream_t s) {
-    if (dc)
-        launch_mode<true, kDose>(a, cfg, order, fluence, dose, nullptr, s);
+    if (dc && a.P.w2_one)
+        launch_mode<kDcOneDrift, kDose>(a, cfg, order, fluence, dose, nullptr, s);
+    else if (dc)
+        launch_mode<kDcTwoDrift, kDose>(a, cfg, order, fluence, dose, nullptr, s);
     else
-        launch_mode<false, kDose>(a, cfg, order, fluence, dose, nullptr, s);
+        launch_mode<kPlain, kDose>(a, cfg, order, fluence, dose, nullptr, s);
 }
 
 void launch_forward_siddon(const DoseArgs& a, bool dc, TileCfg cfg, const int* order,
                            const float* fluence, float* dose, hipStream_t s) {
+    // the exact-table records carry both drifts
     if (dc)
-        launch_mode<true, kSid>(a, cfg, order, fluence, dose, nullptr, s);
+        launch_mode<kDcTwoDrift, kSid>(a, cfg, order, fluence, dose, nullptr, s);
     else
-        launch_mode<false, kSid>(a, cfg, order, fluence, dose, nullptr, s);
+        launch_mode<kPlain, kSid>(a, cfg, order, fluence, dose, nullptr, s);
 }
 
 void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
                               const float* fluence, const float4* prm, float* dose, hipStream_t s) {
-    launch_mode<true, kSurr>(a, cfg, order, fluence, dose, nullptr, s, prm);
+    if (a.P.w2_one)
+        launch_mode<kDcOneDrift, kSurr>(a, cfg, order, fluence, dose, nullptr, s, prm);
+    else
+        launch_mode<kDcTwoDrift, kSurr>(a, cfg, order, fluence, dose, nullptr, s, prm);
 }
 
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                   int* counts, hipStream_t s) {
-    launch_mode<false, kCount>(a, cfg, order, fluence, nullptr, counts, s);
+    launch_mode<kPlain, kCount>(a, cfg, order, fluence, nullptr, counts, s);
 }
 
 // Scheduling estimate, one thread per brick: the brick's bounding sphere is
@@ -671,7 +677,7 @@ void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s)
     }
 }
 
-void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
+void launch_forward_batch(int dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
                           const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
                           unsigned long long* ts_done, unsigned long long* ts_start,
                           const float4* water, int water_n, hipStream_t s) {
@@ -686,14 +692,18 @@ void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int
                        items, wave_begin, n_waves, ptrs, ts_done, ts_start, water, water_n)
 #define FSPB_SHAPE(ID, X, Y, Z)                                                               \
     case ID:                                                                                  \
-        if (dc && lw)                                                                         \
-            FSPB_BATCH(true, true, X, Y, Z);                                                  \
+        if (dc == kDcOneDrift && lw)                                                          \
+            FSPB_BATCH(kDcOneDrift, true, X, Y, Z);                                           \
+        else if (dc == kDcOneDrift)                                                           \
+            FSPB_BATCH(kDcOneDrift, false, X, Y, Z);                                          \
+        else if (dc && lw)                                                                    \
+            FSPB_BATCH(kDcTwoDrift, true, X, Y, Z);                                           \
         else if (dc)                                                                          \
-            FSPB_BATCH(true, false, X, Y, Z);                                                 \
+            FSPB_BATCH(kDcTwoDrift, false, X, Y, Z);                                          \
         else if (lw)                                                                          \
-            FSPB_BATCH(false, true, X, Y, Z);                                                 \
+            FSPB_BATCH(kPlain, true, X, Y, Z);                                                \
         else                                                                                  \
-            FSPB_BATCH(false, false, X, Y, Z);                                                \
+            FSPB_BATCH(kPlain, false, X, Y, Z);                                               \
         break;
     switch (cfg.shape) {
         FSPB_SHAPE(0, 4, 4, 4)
@@ -718,18 +728,23 @@ void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, 
     const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
     const bool lw = water_bytes <= (size_t)kLdsWaterMax;
     dim3 grid(8 * ((n_beamlets + 7) / 8));
-    if (lw && dc)
-        hipLaunchKernelGGL((dose_adjoint<true, 8, true>), grid, dim3(8 * kWave), water_bytes, s, a,
-                           n_beamlets, w, grad);
+#define FSPB_ADJ(DCV, NWV, LWV)                                                               \
+    hipLaunchKernelGGL((dose_adjoint<DCV, NWV, LWV>), grid, dim3(NWV * kWave),                \
+                       LWV ? water_bytes : 0, s, a, n_beamlets, w, grad)
+    const int mode = !dc ? kPlain : a.P.w2_one ? kDcOneDrift : kDcTwoDrift;
+    if (lw && mode == kDcOneDrift)
+        FSPB_ADJ(kDcOneDrift, 8, true);
+    else if (lw && mode == kDcTwoDrift)
+        FSPB_ADJ(kDcTwoDrift, 8, true);
     else if (lw)
-        hipLaunchKernelGGL((dose_adjoint<false, 8, true>), grid, dim3(8 * kWave), water_bytes, s, a,
-                           n_beamlets, w, grad);
-    else if (dc)
-        hipLaunchKernelGGL((dose_adjoint<true, 4, false>), grid, dim3(4 * kWave), 0, s, a,
-                           n_beamlets, w, grad);
+        FSPB_ADJ(kPlain, 8, true);
+    else if (mode == kDcOneDrift)
+        FSPB_ADJ(kDcOneDrift, 4, false);
+    else if (mode == kDcTwoDrift)
+        FSPB_ADJ(kDcTwoDrift, 4, false);
     else
-        hipLaunchKernelGGL((dose_adjoint<false, 4, false>), grid, dim3(4 * kWave), 0, s, a,
-                           n_beamlets, w, grad);
+        FSPB_ADJ(kPlain, 4, false);
+#undef FSPB_ADJ
 }
 
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,

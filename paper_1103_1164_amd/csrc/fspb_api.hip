@@ -189,6 +189,8 @@ struct TableSet {
     float4* atab = nullptr;
     float* denstab = nullptr;
     DensTabs dens{};
+    float w2c = 1.0f;            // b2 = w2c b1 at every sample when w2_one
+    int w2_one = 0;
     int refs = 0;
     unsigned long long last_use = 0;
 };
@@ -557,6 +559,23 @@ static bool table_key_equals(const std::vector<uint32_t>& key, const fspb_tables
     return eq && pos == key.size();
 }
 
+// True when b2 = c b1 at every sample of one density grid (Section 2.1 uses
+// a single b for both weight components: c = 1).  c is the ratio at the
+// largest |b1|, and every sample must then satisfy c b1 == b2 exactly in
+// FP32; b1 = b2 = 0 gives c = 1.
+static bool drift_proportional(const fspb_table1d& b1, const fspb_table1d& b2, float* c) {
+    if (b1.n != b2.n || b1.start != b2.start || (b1.n > 1 && b1.step != b2.step)) return false;
+    int k0 = -1;
+    for (int k = 0; k < b1.n; ++k)
+        if (b1.v[k] != 0.0f && (k0 < 0 || std::fabs(b1.v[k]) > std::fabs(b1.v[k0]))) k0 = k;
+    const float cc = k0 >= 0 ? b2.v[k0] / b1.v[k0] : 1.0f;
+    if (!std::isfinite(cc)) return false;
+    for (int k = 0; k < b1.n; ++k)
+        if (!(cc * b1.v[k] == b2.v[k])) return false;
+    *c = cc;
+    return true;
+}
+
 static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** out) {
     std::lock_guard<std::mutex> lk(g_tables_mu);
     auto& sets = table_sets();
@@ -617,6 +636,7 @@ static int acquire_tables(int dev, const fspb_tables* t, int a_cols, TableSet** 
         DT[q]->off = (int)dens.size();
         dens.insert(dens.end(), D[q]->v, D[q]->v + D[q]->n);
     }
+    ts->w2_one = drift_proportional(t->b1, t->b2, &ts->w2c) ? 1 : 0;
     hipError_t e = hipMalloc((void**)&ts->dtab, sizeof(float4) * dtab.size());
     if (e == hipSuccess) e = hipMalloc((void**)&ts->atab, sizeof(float4) * atab.size());
     if (e == hipSuccess) e = hipMalloc((void**)&ts->denstab, sizeof(float) * dens.size());
@@ -720,6 +740,8 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     // ---- commissioned tables: packed and uploaded once per distinct set -------
     int rc;
     if ((rc = acquire_tables(G->device, t, P.a_cols, &G->tabs)) != FSPB_OK) return rc;
+    P.w2c = G->tabs->w2c;
+    P.w2_one = G->tabs->w2_one;
     G->dtab = G->tabs->dtab;
     G->atab = G->tabs->atab;
     G->denstab = G->tabs->denstab;
@@ -1007,6 +1029,8 @@ int fspb_geometry_info(const fspb_geometry* g, fspb_info* info) {
     info->sample_step = g->sample_step;
     info->dc_enabled = g->dc_enabled;
     info->device_bytes = (long long)g->device_bytes;
+    info->drift_tables = g->P.w2_one ? 1 : 2;
+    info->drift_ratio = g->P.w2_one ? g->P.w2c : 0.0f;
     return FSPB_OK;
 }
 
@@ -1265,7 +1289,8 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
 // Batches: many plans in one persistent launch.
 struct fspb_batch {
     int device = 0;
-    int n_plans = 0, n_waves = 0, dc = 0;
+    int n_plans = 0, n_waves = 0;
+    int dc = kPlain;                 // correction mode shared by every plan
     TileCfg tile;
     std::vector<fspb_geometry*> plans;
     std::vector<std::pair<void*, size_t>> blocks;
@@ -1313,7 +1338,7 @@ static int batch_enqueue(fspb_batch* b, const float* const* fluence, float* cons
     }
     launch_fill_u64(b->ts_done, (long)b->n_plans * b->n_waves, 0ULL, s);
     HIP_TRY(hipGetLastError());
-    launch_forward_batch(b->dc != 0, b->tile, b->d_args, b->d_items, b->d_begin, b->n_waves, ptrs,
+    launch_forward_batch(b->dc, b->tile, b->d_args, b->d_items, b->d_begin, b->n_waves, ptrs,
                          b->ts_done, b->ts_start, b->water, b->water_n, s);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
@@ -1348,7 +1373,12 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
     if (!B) return fail(FSPB_E_NOMEM, "host allocation failed");
     B->device = geoms[0]->device;
     B->n_plans = n;
-    B->dc = geoms[0]->dc_enabled;
+    B->dc = kPlain;
+    if (geoms[0]->dc_enabled) {
+        B->dc = kDcOneDrift;
+        for (int p = 0; p < n; ++p)
+            if (!geoms[p]->P.w2_one) B->dc = kDcTwoDrift;
+    }
     B->tile.shape = shape;
     B->tile.waves_per_block = waves_per_block;
     B->plans.assign(geoms, geoms + n);

@@ -32,7 +32,8 @@ struct Frame64 {
 //   yp = q.ey + c_y
 // with q = r - P0.  96 bytes, read with scalar loads (wave-uniform index);
 // everything the uniform-table pair arithmetic reads sits in the first 80
-// bytes (one 64-byte and one 16-byte scalar load).
+// bytes (one 64-byte and one 16-byte scalar load).  A larger descriptor
+// costs the forward more in scalar loads than the arithmetic it could save.
 struct alignas(16) BeamletDesc {
     float d[3];
     float c_t;
@@ -42,7 +43,8 @@ struct alignas(16) BeamletDesc {
     float c_y;
     float s_entry;     // |r_a| = t + s_entry
     float sad;
-    float x0, y0;      // beamlet half widths at the isocentre plane (Eq. 4)
+    float nx2, ny2;    // -2 x0, -2 y0: beamlet half widths at the isocentre
+                       // plane (Eq. 4), in the form the profile arithmetic uses
     float th_frac;     // A-table theta interpolation weight
     int a_off;         // first A-table record of the beamlet's theta rows (r, r+1): r n_A
     int tab_off;       // first sample of this beamlet's depth tables
@@ -53,6 +55,7 @@ struct alignas(16) BeamletDesc {
     int K;             // depth-table length (0 if the beamlet misses the body)
 };
 static_assert(sizeof(BeamletDesc) == 96, "BeamletDesc layout");
+static_assert(sizeof(BeamletDesc) % 16 == 0, "BeamletDesc is read as float4 records");
 
 // Per-beam data for candidate-beamlet culling.  A voxel at q (relative to
 // P0) projects onto the isocentre plane at (a, b) = (v.ex, v.ey) * sad/(v.cax)
@@ -73,6 +76,15 @@ struct alignas(16) BeamDesc {
 };
 static_assert(sizeof(BeamDesc) == 96, "BeamDesc layout");
 
+// Density-correction modes of the pair kernels (their template argument DC).
+// Section 2.1 gives both weight components one drift integral of a single
+// b(rho); the library accepts a separate b_i per component.  When the
+// commissioned b2 is c b1 at every table sample (c = 1: the single b of the
+// paper), the second drift is c W1 and a pair reads one depth record (tTW)
+// instead of two (tTW and tW2); that load is what limits the corrected
+// forward.  With c = +-1 both modes give bitwise the same dose.
+enum { kPlain = 0, kDcTwoDrift = 1, kDcOneDrift = 2 };
+
 // Plan-wide constants passed by value to the pair kernels.
 struct PlanConst {
     int nx, ny, nz, n_beams;
@@ -81,6 +93,8 @@ struct PlanConst {
     float inv_d;          // 1 / ray sample step
     float dt_inv, dt_off, at_inv, at_off;  // table coordinate = value * inv + off
     int dt_n, at_n, a_cols, dc;
+    float w2c;            // b2 = w2c b1 at every table sample when w2_one
+    int w2_one;           // (the second weight drift is then w2c W1)
 };
 
 // Density-table grid (host copy of start/step/n for the factor kernel and

@@ -272,8 +272,8 @@ __global__ __launch_bounds__(256) void ray_trace(const Frame64* __restrict__ fra
     o.theta = (float)f.theta;
     o.beam = f.beam;
     o.j_last = 0;
-    o.x0 = (float)f.x0;
-    o.y0 = (float)f.y0;
+    o.nx2 = (float)(-2.0 * f.x0);   // exactly -2 (float)x0
+    o.ny2 = (float)(-2.0 * f.y0);
     {
         double c = f.theta / tp.theta_step;
         c = fmin(fmax(c, 0.0), (double)(tp.n_theta - 1));

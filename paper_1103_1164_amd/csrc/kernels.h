@@ -101,8 +101,9 @@ struct BatchPtrs {
     float* dose[kMaxBatchPlans];
 };
 // water: the water table every plan of the batch uses (n samples per plane),
-// or null when the plans' tables differ (then no LDS staging)
-void launch_forward_batch(bool dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
+// or null when the plans' tables differ (then no LDS staging); dc: the
+// correction mode shared by every plan (kPlain, kDcTwoDrift, kDcOneDrift)
+void launch_forward_batch(int dc, TileCfg cfg, const DoseArgs* plans, const int2* items,
                           const int* wave_begin, int n_waves, const BatchPtrs& ptrs,
                           unsigned long long* ts_done, unsigned long long* ts_start,
                           const float4* water, int water_n, hipStream_t s);

@@ -77,7 +77,10 @@ struct WaterGlobal {
 struct WaterLds {
     const FSPB_LDS float4* p;
     __device__ __forceinline__ void get(unsigned j, float4& u0, float4& us, float4& wv) const {
-        const FSPB_LDS float4* r = p + 3 * j;
+        // 48 j in a 24-bit multiply (the table holds well under 2^24
+        // records); indexing the pointer directly makes a 64-bit multiply-add
+        const FSPB_LDS float4* r =
+            (const FSPB_LDS float4*)((const FSPB_LDS char*)p + __umul24(j, 48u));
         u0 = r[0];
         us = r[1];
         wv = r[2];
@@ -104,28 +107,32 @@ __device__ __forceinline__ float penumbra2(float ul, float dm, float dp, float s
 
 // The two Eq. 3 profile products, 2 p_x(u_ax) 2 p_y(u_ay) for the steepness
 // pairs (u1x, u1y) and (u2x, u2y) (times log2 e), at isocentre-plane offsets
-// (x, y) from the axis of a beamlet of half widths (x0, y0).  Outside the box
-// along both axes, 2 p_x = e^{-u_x(|x| - x0)} (1 - e^{-2 u_x x0}), so
+// (x, y) from the axis of a beamlet of half widths (x0, y0), given as
+// (nx2, ny2) = (-2 x0, -2 y0): |x| - x0 = fma(nx2, 1/2, |x|) exactly, and the
+// outer form below needs -2 u x0.  Outside the box along both axes,
+// 2 p_x = e^{-u_x(|x| - x0)} (1 - e^{-2 u_x x0}), so
 //   2 p_x 2 p_y = e^{-u_x(|x| - x0) - u_y(|y| - y0)} (1 - e^{-2 u_x x0}) (1 - e^{-2 u_y y0}):
 // three exponentials per product instead of four.  That form is taken when
 // every active lane of the wave lies outside the box along both axes (most
 // pairs: the box is a beamlet wide, the ROI ten times wider); otherwise the
 // general form of penumbra2.
-__device__ __forceinline__ void profile_products(float x, float y, float x0, float y0, float u1x,
-                                                 float u1y, float u2x, float u2y, float& p1,
-                                                 float& p2) {
+__device__ __forceinline__ void profile_products(float x, float y, float nx2, float ny2,
+                                                 float u1x, float u1y, float u2x, float u2y,
+                                                 float& p1, float& p2) {
     const float ax = fabsf(x), ay = fabsf(y);
-    const float ox = ax - x0, oy = ay - y0;   // signed distances past the box edge
+    const float ox = fmaf(nx2, 0.5f, ax), oy = fmaf(ny2, 0.5f, ay);   // |x| - x0, |y| - y0
     const bool outer = (ox > 0.0f) & (oy > 0.0f);
     if (__ballot(!outer) == 0) {              // wave-uniform branch
-        const float x2 = x0 + x0, y2 = y0 + y0;
-        p1 = fast_exp2(-fmaf(u1x, ox, u1y * oy)) * (1.0f - fast_exp2(-u1x * x2)) *
-             (1.0f - fast_exp2(-u1y * y2));
-        p2 = fast_exp2(-fmaf(u2x, ox, u2y * oy)) * (1.0f - fast_exp2(-u2x * x2)) *
-             (1.0f - fast_exp2(-u2y * y2));
+        // E (1 - a) (1 - b) as two fmas: t = E - a E, then t - b t
+        const float e1 = fast_exp2(-fmaf(u1x, ox, u1y * oy));
+        const float t1 = fmaf(-fast_exp2(u1x * nx2), e1, e1);
+        p1 = fmaf(-fast_exp2(u1y * ny2), t1, t1);
+        const float e2 = fast_exp2(-fmaf(u2x, ox, u2y * oy));
+        const float t2 = fmaf(-fast_exp2(u2x * nx2), e2, e2);
+        p2 = fmaf(-fast_exp2(u2y * ny2), t2, t2);
     } else {
-        const float dmx = fabsf(ox), dpx = ax + x0;
-        const float dmy = fabsf(oy), dpy = ay + y0;
+        const float dmx = fabsf(ox), dpx = fmaf(nx2, -0.5f, ax);   // |x| + x0
+        const float dmy = fabsf(oy), dpy = fmaf(ny2, -0.5f, ay);
         const float sgx = copysignf(1.0f, ox), o2x = 1.0f - sgx;
         const float sgy = copysignf(1.0f, oy), o2y = 1.0f - sgy;
         p1 = penumbra2(u1x, dmx, dpx, sgx, o2x) * penumbra2(u1y, dmy, dpy, sgy, o2y);
@@ -168,7 +175,7 @@ __device__ __forceinline__ float magnification(float t, const BD& b) {
 // below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
 // fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
 // k = SAD / |r_a| (see magnification()) is computed by the caller.
-template <bool DC, class BD, class WT>
+template <int DC, class BD, class WT>
 __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k, const BD& b,
                                            float4 fac, const PlanConst& P, const WT& water,
                                            const FSPB_GLOBAL float4* __restrict__ atab,
@@ -200,10 +207,12 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     if (DC) {
         const unsigned ot = (unsigned)(b.tab_off + j);
         const float4 r0 = load_at(tTW, 16u * ot);
-        const float2 r1 = load_at(tW2, 8u * ot);
         teq = fmaf(f, r0.y, r0.x);
         W1 = fmaf(f, r0.w, r0.z);
-        W2 = fmaf(f, r1.y, r1.x);
+        if (DC == kDcTwoDrift) {
+            const float2 r1 = load_at(tW2, 8u * ot);
+            W2 = fmaf(f, r1.y, r1.x);
+        }
     } else {
         const float2 te = load_at(tT, 8u * (unsigned)(b.tab_off + j));
         teq = fmaf(f, te.y, te.x);
@@ -226,14 +235,14 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
         u2x *= fac.y;
         u2y *= fac.y;
         w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
-        w2 = fmaxf(fac.w * (w2 + W2), 0.0f);
+        w2 = fmaxf(fac.w * (DC == kDcOneDrift ? fmaf(P.w2c, W1, w2) : w2 + W2), 0.0f);
     }
 
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
 
     // Eq. 3 with the Eq. 4 profiles
     float p1, p2;
-    profile_products(x, y, b.x0, b.y0, u1x, u1y, u2x, u2y, p1, p2);
+    profile_products(x, y, b.nx2, b.ny2, u1x, u1y, u2x, u2y, p1, p2);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
@@ -243,7 +252,7 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
 // kernels.h), found by a binary search on the segment start depths -- the
 // search the uniform samples of Section 2.2 avoid.  Everything else is
 // pair_dose's.
-template <bool DC, class BD, class WT>
+template <int DC, class BD, class WT>
 __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, float k, const BD& b,
                                                   float4 fac, const PlanConst& P, const WT& water,
                                                   const FSPB_GLOBAL float4* __restrict__ atab,
@@ -286,7 +295,7 @@ __device__ __forceinline__ float pair_dose_siddon(float t, float xp, float yp, f
     }
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
     float p1, p2;
-    profile_products(x, y, b.x0, b.y0, u1x, u1y, u2x, u2y, p1, p2);
+    profile_products(x, y, b.nx2, b.ny2, u1x, u1y, u2x, u2y, p1, p2);
     float F = fmaf(w1, p1, w2 * p2);
     return F * A * isq;
 }
@@ -341,7 +350,7 @@ __device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, fl
     const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
     const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
     float p1, p2;
-    profile_products(x, y, b.x0, b.y0, ul.x, ul.y, ul.z, ul.w, p1, p2);
+    profile_products(x, y, b.nx2, b.ny2, ul.x, ul.y, ul.z, ul.w, p1, p2);
     float F = fmaf(wv.x, p1, wv.y * p2);
     return F * A * isq;
 }

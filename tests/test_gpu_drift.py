@@ -1,0 +1,122 @@
+"""The two weight-drift modes of the density-corrected pair kernels.
+
+Section 2.1 integrates one b(rho) for both weight components; the library
+takes a b_i per component and, when the commissioned b2 is c * b1 at every
+sample of one density grid, reads a single drift table per pair (the second
+drift is then c * W1).  These tests check which mode a handle takes, each
+mode against the FP64 oracle (forward and adjoint), and that the two modes
+give bitwise the same dose and gradient where they must (c = -1 and c = 1,
+with the second table on a longer grid that forces the two-table mode while
+every lookup reads the same values).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import fspb_synth as S
+from fspb_synth.tables import Table1D
+from gpu_helpers import REL_TOL, assert_dose_parity, gpu_dose, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def _tables(kind):
+    t = S.make_tables(0)
+    b1 = t.b1
+    rho = b1.start + b1.step * np.arange(b1.n)
+    if kind == "neg":            # the nominal tables: b2 = -b1
+        b2 = t.b2
+    elif kind == "same":         # one b for both components, as in Section 2.1
+        b2 = Table1D(b1.start, b1.step, b1.values.copy())
+    elif kind == "half":         # b2 = b1 / 2 (exact in FP32)
+        b2 = Table1D(b1.start, b1.step, _f32(0.5 * b1.values))
+    elif kind == "indep":        # not proportional
+        b2 = Table1D(b1.start, b1.step, _f32(-0.6 * b1.values + 0.01 * (rho - 1.0) ** 2))
+    elif kind in ("neg_ext", "same_ext"):
+        # the same values on a grid one sample longer: the tables no longer
+        # share a grid (two-table mode), while every density inside the
+        # clamped range looks up the same samples
+        v = -b1.values if kind == "neg_ext" else b1.values
+        b2 = Table1D(b1.start, b1.step, _f32(np.concatenate([v, v[-1:]])))
+    else:
+        raise ValueError(kind)
+    return dataclasses.replace(t, b2=b2)
+
+
+def _plan(kind, seed=5):
+    rng = np.random.default_rng(seed)
+    n = (29, 23, 19)
+    rho = rng.uniform(0.05, 1.95, size=(n[2], n[1], n[0])).astype(np.float32)
+    rho[:, :, :6] = 0.001                 # air on one side: entrances inside the grid
+    beams = [S.Beam(gantry=0.3, nbx=5, nby=4, wx=0.5, wy=0.5),
+             S.Beam(gantry=2.2, nbx=3, nby=6, wx=0.5, wy=0.5, cx=0.2, cy=-0.1)]
+    return S.plan_small(n=n, density=rho, beams=beams, tables=_tables(kind), seed=seed,
+                        name=f"drift_{kind}")
+
+
+def _geo(plan):
+    from paper_1103_1164_amd import Geometry
+    return Geometry.from_plan(plan, device="cuda", dc_enabled=1)
+
+
+@pytest.mark.parametrize("kind,tables,ratio", [("neg", 1, -1.0), ("same", 1, 1.0),
+                                               ("half", 1, 0.5), ("indep", 2, 0.0),
+                                               ("neg_ext", 2, 0.0)])
+def test_mode_and_parity_with_oracle(oracle_mod, kind, tables, ratio):
+    plan = _plan(kind)
+    geo = _geo(plan)
+    info = geo.info()
+    assert info["drift_tables"] == tables and info["drift_ratio"] == ratio
+    say(f"drift {kind}: {tables} table(s), ratio {ratio}")
+    orc = oracle_mod.Oracle(plan, dc_enabled=1)
+    d_orc, amb, _ = orc.dose()
+    rel = assert_dose_parity(gpu_dose(geo, plan.fluence), d_orc, amb, what=f"drift {kind}")
+    w = np.random.default_rng(11).uniform(0, 1, plan.n_vox).astype(np.float32)
+    g_o, amb_g = orc.adjoint(w)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(g - g_o) <= REL_TOL * np.abs(g_o).max() + amb_g)
+    say(f"drift {kind}: forward max |err|/max D = {rel:.2e}")
+    geo.close()
+
+
+@pytest.mark.parametrize("one,two", [("neg", "neg_ext"), ("same", "same_ext")])
+def test_one_and_two_table_modes_agree_bitwise(one, two):
+    p1, p2 = _plan(one), _plan(two)
+    g1, g2 = _geo(p1), _geo(p2)
+    assert g1.info()["drift_tables"] == 1 and g2.info()["drift_tables"] == 2
+    d1, d2 = gpu_dose(g1, p1.fluence), gpu_dose(g2, p2.fluence)
+    assert np.array_equal(d1, d2)
+    w = torch.as_tensor(np.random.default_rng(4).uniform(0, 1, p1.n_vox).astype(np.float32),
+                        device="cuda")
+    assert torch.equal(g1.adjoint(w), g2.adjoint(w))
+    g1.close()
+    g2.close()
+
+
+def test_batch_takes_the_shared_mode_only_when_every_plan_has_it():
+    """A batch reads one drift table only if every plan qualifies; a mixed
+    batch falls back to two tables for all plans and still matches each
+    plan's own forward."""
+    from paper_1103_1164_amd import Batch
+    plans = [_plan("neg", 7), _plan("indep", 8)]
+    geos = [_geo(p) for p in plans]
+    refs = [gpu_dose(g, p.fluence) for g, p in zip(geos, plans)]
+    fl = [torch.as_tensor(p.fluence, device="cuda") for p in plans]
+    for sel in ([0], [0, 1]):
+        b = Batch([geos[i] for i in sel])
+        outs = [torch.empty(plans[i].shape, device="cuda") for i in sel]
+        b.forward([fl[i] for i in sel], outs)
+        torch.cuda.synchronize()
+        for i, o in zip(sel, outs):
+            got = o.cpu().numpy().astype(np.float64)
+            scale = np.abs(refs[i]).max()
+            assert np.max(np.abs(got - refs[i])) <= 2e-6 * scale, (sel, i)
+        b.close()
+    for g in geos:
+        g.close()
