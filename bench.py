@@ -32,8 +32,11 @@ METRIC = "voxel·beamlet evals/s + ms/plan, plain DC-FSPB vs surrogate at ≤1% 
 
 # Algorithmic FP32 operations per evaluated pair (each add, multiply, divide,
 # exponential and comparison counts 1, an FMA counts 2); the breakdown is in
-# the design notes.  Plain FSPB skips the 14 density-correction operations.
-FLOPS_PER_PAIR_DC = 109
+# the design notes.  The density correction is 14 of them with a weight-drift
+# table per component and 13 when the second drift is a multiple of the first
+# (one table: a multiply-add replaces the second lerp and its add); plain
+# FSPB skips it.  Keyed by the drift tables a pair reads.
+FLOPS_PER_PAIR_DC = {2: 109, 1: 108}
 FLOPS_PER_PAIR_PLAIN = 95
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published, packed FP32)
 # Forward tile of the config-2 workload: (brick shape index, waves per
@@ -241,7 +244,9 @@ def main():
     h2d_ms = time_loop(lambda: dens.copy_(h_ct, non_blocking=True), n_side)
     d2h_ms = time_loop(lambda: h_dose.copy_(dose, non_blocking=True), n_side)
 
-    achieved_tf = pairs_fwd * FLOPS_PER_PAIR_DC / (fwd_ms * 1e-3) / 1e12
+    drift_tables = geo.info()["drift_tables"]
+    fpp = FLOPS_PER_PAIR_DC[drift_tables]
+    achieved_tf = pairs_fwd * fpp / (fwd_ms * 1e-3) / 1e12
     pmc = pmc_record(geo_tile)
     roofline = {
         "bound": "alu", "kernel": "dose_forward<DC>",
@@ -253,7 +258,7 @@ def main():
         "valu_busy": float(pmc["valu_busy_at_2.4GHz"]) if "valu_busy_at_2.4GHz" in pmc else None,
         "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
         "frac_nonpacked": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
-        "flops_per_pair": FLOPS_PER_PAIR_DC, "pairs_per_launch": pairs_fwd,
+        "flops_per_pair": fpp, "drift_tables": drift_tables, "pairs_per_launch": pairs_fwd,
         "launch_ms": round(fwd_ms, 4),
     }
 
