@@ -15,9 +15,11 @@
 //
 // Adjoint: beamlet-major.  A workgroup owns one beamlet.  It walks the grid
 // row by row (rows along x); for each row it solves for the x-interval that
-// can lie inside the ROI past the entrance, compacts the intervals of a batch
-// of rows (one per thread) with a block scan, and spreads the voxels of those
-// intervals over its lanes.
+// can lie inside the ROI past the entrance, compacts the non-empty intervals
+// of a batch of rows (one per thread) with block scans, and spreads their
+// voxels over its lanes, 64 consecutive voxels per wave: a table gives the
+// row of each such block's first voxel, and lanes step over the few rows
+// their own voxel lies beyond.
 // Partial sums are reduced in a fixed order, so the gradient is deterministic.
 #include "kernels.h"
 #include "pair.h"
@@ -313,17 +315,26 @@ __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
 
 // NW waves per workgroup; with LW the water table is staged in LDS first,
 // as in dose_forward.
+// Items (voxels) of a chunk are dealt to the waves 64 at a time; the row of
+// each block's first item comes from a table built per window of
+// kAdjBlocks blocks.
+constexpr int kAdjBlocks = 1024;
+
 template <int DC, int NW, bool LW>
 __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_beamlets,
                                                           const float* __restrict__ w,
                                                           float* __restrict__ grad) {
     constexpr int NT = NW * kWave;
-    __shared__ int s_off[NT];
-    __shared__ int s_lo[NT];
+    constexpr int kWinItems = kAdjBlocks * kWave;
+    // the chunk's rows that meet the ROI, compacted in row order
+    __shared__ int s_off[NT];        // first item of the row
+    __shared__ int s_lo[NT];         // first voxel (i) of the row's interval
     __shared__ int s_vbase[NT];      // voxel index of the row's first voxel
     __shared__ float s_qy[NT];       // the row's voxel-centre y and z (relative to P0)
     __shared__ float s_qz[NT];
+    __shared__ int s_brow[kAdjBlocks + 1];   // compacted row of item w0 + 64 b
     __shared__ int s_wsum[NW];
+    __shared__ int s_wcnt[NW];
     __shared__ float s_red[NW];
     extern __shared__ float4 s_water[];
     if (LW) {
@@ -363,13 +374,11 @@ __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_bea
         for (int r0 = 0; r0 < n_rows; r0 += NT) {
             const int row = r0 + tid;
             int lo = 0, len = 0;
+            float qy = 0.0f, qz = 0.0f;
             if (row < n_rows) {
                 const int j = row % P.ny, k = row / P.ny;
-                float qx, qy, qz;
+                float qx;
                 voxel_q(P, 0, j, k, qx, qy, qz);
-                s_vbase[tid] = row * P.nx;
-                s_qy[tid] = qy;
-                s_qz[tid] = qz;
                 double xp0 = (double)qx * d.ex[0] + (double)qy * d.ex[1] + (double)qz * d.ex[2] + d.c_x;
                 double yp0 = (double)qx * d.ey[0] + (double)qy * d.ey[1] + (double)qz * d.ey[2] + d.c_y;
                 double t0 = (double)qx * d.d[0] + (double)qy * d.d[1] + (double)qz * d.d[2] + d.c_t;
@@ -401,50 +410,76 @@ __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_bea
                     }
                 }
             }
-            // block exclusive scan of the interval lengths
-            int incl = wave_incl_scan_int(len, lane);
+            // block scans: the rows' first items and their compacted slots
+            const int incl = wave_incl_scan_int(len, lane);
+            const unsigned long long ne = __ballot(len > 0);
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(ne >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)ne, 0));
             if (lane == kWave - 1) s_wsum[wid] = incl;
+            if (lane == 0) s_wcnt[wid] = __popcll(ne);
             __syncthreads();
-            int base = 0, total = 0;
+            int base = 0, total = 0, rbase = 0, nrows = 0;
             for (int q = 0; q < NW; ++q) {
-                if (q < wid) base += s_wsum[q];
-                total += s_wsum[q];
-            }
-            s_off[tid] = base + incl - len;
-            s_lo[tid] = lo;
-            __syncthreads();
-            for (int e0 = wid * kWave; e0 < total; e0 += NT) {
-                // a wave takes 64 consecutive items: the row of its first item
-                // is found once (same address on every lane), then each lane
-                // steps forward over the few rows its own item lies beyond
-                const int e = e0 + lane;
-                int rlo = 0, rhi = NT - 1;
-                while (rlo < rhi) {
-                    int mid = (rlo + rhi + 1) >> 1;
-                    if (s_off[mid] <= e0) rlo = mid;
-                    else rhi = mid - 1;
+                if (q < wid) {
+                    base += s_wsum[q];
+                    rbase += s_wcnt[q];
                 }
-                while (rlo < NT - 1 && s_off[rlo + 1] <= e) ++rlo;
-                if (e >= total) continue;
-                const int i = s_lo[rlo] + (e - s_off[rlo]);
-                // the voxel centre as voxel_q computes it (same pair decisions
-                // as the forward kernel)
-                const float qx = fmaf((float)i, P.dx, P.qx0), qy = s_qy[rlo], qz = s_qz[rlo];
-                float t, xp, yp;
-                if (pair_coords(d, P, qx, qy, qz, t, xp, yp)) {
-                    const unsigned v = (unsigned)(s_vbase[rlo] + i);
-                    float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-                    if (DC) fac = facs[v];
-                    const float pd =
-                        LW ? pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
-                                           WaterLds{(const FSPB_LDS float4*)s_water},
-                                           as_global(a.atab), as_global(a.tT), as_global(a.tTW),
-                                           as_global(a.tW2))
-                           : pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
-                                           WaterGlobal{as_global(a.dtab), P.dt_n},
-                                           as_global(a.atab), as_global(a.tT), as_global(a.tTW),
-                                           as_global(a.tW2));
-                    acc = fmaf(wv[v], pd, acc);
+                total += s_wsum[q];
+                nrows += s_wcnt[q];
+            }
+            if (len > 0) {
+                const int c = rbase + rank;
+                s_off[c] = base + incl - len;
+                s_lo[c] = lo;
+                s_vbase[c] = row * P.nx;
+                s_qy[c] = qy;
+                s_qz[c] = qz;
+            }
+            for (int w0 = 0; w0 < total; w0 += kWinItems) {
+                __syncthreads();   // the compacted rows are written; the last window is read
+                // s_brow[b] = the row holding item w0 + 64 b (the last row
+                // past the end): row c holds items [s_off[c], s_off[c+1])
+                for (int b = tid; b <= kAdjBlocks; b += NT)
+                    if (w0 + b * kWave >= total) s_brow[b] = nrows - 1;
+                for (int c = tid; c < nrows; c += NT) {
+                    const int x0 = s_off[c] - w0;
+                    const int x1 = (c + 1 < nrows ? s_off[c + 1] : total) - w0;   // exclusive
+                    int b = x0 > 0 ? (x0 + kWave - 1) / kWave : 0;
+                    for (; b <= kAdjBlocks && b * kWave < x1; ++b) s_brow[b] = c;
+                }
+                __syncthreads();
+                const int wend = min(total - w0, kWinItems);
+                for (int e0 = wid * kWave; e0 < wend; e0 += NT) {
+                    // the block's first row, then each lane steps over the
+                    // few rows its own item lies beyond (same trip count on
+                    // every lane: offsets increase strictly)
+                    const int blk = e0 / kWave;
+                    int c = s_brow[blk];
+                    const int c_hi = s_brow[blk + 1];
+                    const int e = w0 + e0 + lane;
+                    for (int cc = c + 1; cc <= c_hi; ++cc)
+                        if (s_off[cc] <= e) c = cc;
+                    if (e >= total) continue;
+                    const int i = s_lo[c] + (e - s_off[c]);
+                    // the voxel centre as voxel_q computes it (same pair
+                    // decisions as the forward kernel)
+                    const float qx = fmaf((float)i, P.dx, P.qx0), qy = s_qy[c], qz = s_qz[c];
+                    float t, xp, yp;
+                    if (pair_coords(d, P, qx, qy, qz, t, xp, yp)) {
+                        const unsigned v = (unsigned)(s_vbase[c] + i);
+                        float4 fac = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+                        if (DC) fac = facs[v];
+                        const float pd =
+                            LW ? pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                               WaterLds{(const FSPB_LDS float4*)s_water},
+                                               as_global(a.atab), as_global(a.tT), as_global(a.tTW),
+                                               as_global(a.tW2))
+                               : pair_dose<DC>(t, xp, yp, magnification(t, d), d, fac, P,
+                                               WaterGlobal{as_global(a.dtab), P.dt_n},
+                                               as_global(a.atab), as_global(a.tT), as_global(a.tTW),
+                                               as_global(a.tW2));
+                        acc = fmaf(wv[v], pd, acc);
+                    }
                 }
             }
             __syncthreads();
