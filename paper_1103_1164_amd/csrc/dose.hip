@@ -370,13 +370,38 @@ __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_bea
         const double inv_a3 = a3 != 0.0 ? 1.0 / a3 : 0.0;
         const FSPB_GLOBAL float4* __restrict__ facs = as_global(a.fac);
         const FSPB_GLOBAL float* __restrict__ wv = as_global(w);
-        const int n_rows = P.ny * P.nz;
+        // only rows (j, k) near the beamlet's cylinder: every pair lies
+        // within R of the axis segment from the entrance (t = 0) to t = the
+        // grid's diagonal, whose y and z extents (padded by R and a voxel)
+        // bound j and k; rows outside meet no pair
+        int j_lo = 0, j_hi = P.ny - 1, k_lo = 0, k_hi = P.nz - 1;
+        {
+            // entrance relative to P0: q.d = -c_t, q.ex = -c_x, q.ey = -c_y
+            double qe[3], dd[3];
+            for (int c = 0; c < 3; ++c) {
+                qe[c] = -((double)d.c_t * d.d[c] + (double)d.c_x * d.ex[c] + (double)d.c_y * d.ey[c]);
+                dd[c] = d.d[c];
+            }
+            const double ex_ = (double)P.nx * P.dx, ey_ = (double)P.ny * P.dy, ez_ = (double)P.nz * P.dz;
+            const double T = sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+            const double R = sqrt((double)P.R2);
+            const double y0 = fmin(qe[1], qe[1] + T * dd[1]) - R, y1 = fmax(qe[1], qe[1] + T * dd[1]) + R;
+            const double z0 = fmin(qe[2], qe[2] + T * dd[2]) - R, z1 = fmax(qe[2], qe[2] + T * dd[2]) + R;
+            // voxel index = (q - q0) / delta, one voxel of margin
+            j_lo = max(j_lo, (int)floor((y0 - P.qy0) / P.dy) - 1);
+            j_hi = min(j_hi, (int)ceil((y1 - P.qy0) / P.dy) + 1);
+            k_lo = max(k_lo, (int)floor((z0 - P.qz0) / P.dz) - 1);
+            k_hi = min(k_hi, (int)ceil((z1 - P.qz0) / P.dz) + 1);
+        }
+        const int nj = j_hi - j_lo + 1;
+        const int n_rows = (nj > 0 && k_hi >= k_lo) ? nj * (k_hi - k_lo + 1) : 0;
         for (int r0 = 0; r0 < n_rows; r0 += NT) {
-            const int row = r0 + tid;
-            int lo = 0, len = 0;
+            const int rr = r0 + tid;
+            int lo = 0, len = 0, row = 0;
             float qy = 0.0f, qz = 0.0f;
-            if (row < n_rows) {
-                const int j = row % P.ny, k = row / P.ny;
+            if (rr < n_rows) {
+                const int j = j_lo + rr % nj, k = k_lo + rr / nj;
+                row = k * P.ny + j;
                 float qx;
                 voxel_q(P, 0, j, k, qx, qy, qz);
                 double xp0 = (double)qx * d.ex[0] + (double)qy * d.ex[1] + (double)qz * d.ex[2] + d.c_x;
