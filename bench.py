@@ -142,10 +142,9 @@ def main():
     dose = torch.empty(plan.shape, device=dev)
 
     def make(dc=1, stream=None):
-        g = Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables,
-                     _opts(plan.options, dc), stream=stream)
-        g.set_tile(*C2_TILE, stream=stream)   # brick order rebuilt on the creation stream
-        return g
+        # the forward schedule is built for the benchmark's tile at creation
+        return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables,
+                        _opts(plan.options, dc), stream=stream, tile=C2_TILE)
 
     geo = make()
     geo_tile = geo.get_tile()

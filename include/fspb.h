@@ -118,6 +118,13 @@ typedef struct {
     float sample_step;   /* ray sampling step [min(dx,dy,dz)/2] (Section 2.2) */
     int dc_enabled;      /* 1: 3D density correction, 0: plain FSPB (A1 without step 11) */
     int flags;           /* 0, or FSPB_FLAG_SIDDON */
+    /* forward tile built at creation (see fspb_set_tile): tile_waves = 0
+     * takes the default (brick shape 0, 8 waves per workgroup); otherwise
+     * 1, 2, 4 or 8 waves per workgroup with brick shape tile_shape
+     * (0 .. fspb_tile_shapes() - 1).  Equivalent to fspb_set_tile right
+     * after creation, without building the default schedule first. */
+    int tile_shape;
+    int tile_waves;
 } fspb_options;
 
 /* fspb_options.flags: build exact radiological-depth tables (Siddon's

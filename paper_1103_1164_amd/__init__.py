@@ -70,7 +70,7 @@ class Geometry:
     """A plan's geometry on the GPU (owning handle of libfspb)."""
 
     def __init__(self, density: torch.Tensor, spacing, origin, beams, tables, options=None,
-                 stream=None):
+                 stream=None, tile=None):
         L = load()
         if not (isinstance(density, torch.Tensor) and density.is_cuda):
             raise TypeError("density must be a CUDA (HIP) tensor")
@@ -89,12 +89,20 @@ class Geometry:
                                    float(b.cx), float(b.cy))
         tabs = _marshal_tables(tables)
         opt_p = None
-        if options is not None:
-            o = options
-            opt = _lib.fspb_options(float(o.roi_radius), float(o.rho_surface),
-                                    float(o.smooth_sigma), float(o.rho_min), float(o.rho_max),
-                                    float(o.sample_step), int(o.dc_enabled),
-                                    _lib.FSPB_FLAG_SIDDON if getattr(o, "siddon", 0) else 0)
+        if options is not None or tile is not None:
+            # zero fields take the library's defaults; tile = (shape, waves
+            # per workgroup) builds that forward schedule at creation
+            opt = _lib.fspb_options()
+            opt.dc_enabled = 1
+            if options is not None:
+                o = options
+                opt.roi_radius, opt.rho_surface = float(o.roi_radius), float(o.rho_surface)
+                opt.smooth_sigma, opt.rho_min = float(o.smooth_sigma), float(o.rho_min)
+                opt.rho_max, opt.sample_step = float(o.rho_max), float(o.sample_step)
+                opt.dc_enabled = int(o.dc_enabled)
+                opt.flags = _lib.FSPB_FLAG_SIDDON if getattr(o, "siddon", 0) else 0
+            if tile is not None:
+                opt.tile_shape, opt.tile_waves = int(tile[0]), int(tile[1])
             opt_p = C.byref(opt)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -106,14 +114,15 @@ class Geometry:
         self.n_beams = len(beams)
 
     @classmethod
-    def from_plan(cls, plan, device="cuda", dc_enabled: Optional[int] = None, stream=None):
+    def from_plan(cls, plan, device="cuda", dc_enabled: Optional[int] = None, stream=None,
+                  tile=None):
         dens = torch.as_tensor(np.ascontiguousarray(plan.density, dtype=np.float32), device=device)
         opts = plan.options
         if dc_enabled is not None:
             import copy
             opts = copy.copy(opts)
             opts.dc_enabled = int(dc_enabled)
-        return cls(dens, plan.spacing, plan.origin, plan.beams, plan.tables, opts, stream)
+        return cls(dens, plan.spacing, plan.origin, plan.beams, plan.tables, opts, stream, tile)
 
     # -- lifetime -------------------------------------------------------------
     def close(self):

@@ -50,7 +50,8 @@ class fspb_tables(C.Structure):
 class fspb_options(C.Structure):
     _fields_ = [("roi_radius", C.c_float), ("rho_surface", C.c_float),
                 ("smooth_sigma", C.c_float), ("rho_min", C.c_float), ("rho_max", C.c_float),
-                ("sample_step", C.c_float), ("dc_enabled", C.c_int), ("flags", C.c_int)]
+                ("sample_step", C.c_float), ("dc_enabled", C.c_int), ("flags", C.c_int),
+                ("tile_shape", C.c_int), ("tile_waves", C.c_int)]
 
 
 class fspb_info(C.Structure):

@@ -364,6 +364,13 @@ int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_
             return fail(FSPB_E_ARG, "options must be finite and non-negative");
         if ((o->rho_min != 0 || o->rho_max != 0) && !(o->rho_min < o->rho_max))
             return fail(FSPB_E_ARG, "options: rho_min must be below rho_max");
+        if (o->tile_waves != 0) {
+            if (o->tile_shape < 0 || o->tile_shape >= kNumShapes)
+                return fail(FSPB_E_ARG, "options.tile_shape %d out of range", o->tile_shape);
+            if (o->tile_waves != 1 && o->tile_waves != 2 && o->tile_waves != 4 &&
+                o->tile_waves != kLdsWaves)
+                return fail(FSPB_E_ARG, "options.tile_waves must be 0, 1, 2, 4 or 8");
+        }
     }
     // every voxel must lie in front of every source (positive depth along the
     // central axis), so that the isocentre-plane projection is defined
@@ -698,6 +705,10 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     G->n_beams = n_beams;
     G->dc_created = G->dc_enabled = o.dc_enabled;
     G->siddon = (o.flags & FSPB_FLAG_SIDDON) ? 1 : 0;
+    if (o.tile_waves != 0) {
+        G->tile.shape = o.tile_shape;
+        G->tile.waves_per_block = o.tile_waves;
+    }
     int nbl = 0;
     for (int b = 0; b < n_beams; ++b) nbl += beams[b].nbx * beams[b].nby;
     G->n_beamlets = nbl;

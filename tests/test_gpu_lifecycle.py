@@ -96,3 +96,22 @@ def test_pipeline_of_plans_recycles_buffers_safely():
     torch.cuda.synchronize()
     for k, o in outs:
         assert np.array_equal(o.cpu().numpy().astype(np.float64), refs[k]), k
+
+
+@pytest.mark.parametrize("shape,waves", [(3, 8), (1, 4), (2, 1), (0, 8)])
+def test_tile_given_at_creation_matches_set_tile(shape, waves):
+    """options.tile_shape / tile_waves build the forward schedule at
+    creation: the same tile and bitwise the same dose as fspb_set_tile
+    after a default creation."""
+    from paper_1103_1164_amd import Geometry
+    plan = _plans()[1]
+    dens = torch.as_tensor(plan.density, device="cuda")
+    f = torch.as_tensor(plan.fluence, device="cuda")
+    o = S.Options(dc_enabled=1)
+    a = Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables, o, tile=(shape, waves))
+    b = Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables, o)
+    b.set_tile(shape, waves)
+    assert a.get_tile() == b.get_tile()
+    assert torch.equal(a.forward(f), b.forward(f))
+    a.close()
+    b.close()

@@ -99,6 +99,8 @@ def test_validation_rejects_bad_input(lib):
     o = lib.fspb_options(5, 0.5, 0.5, 0.1, 2.0, 0, 1, 7); bad.append((ct, bs, tabs, o, None))   # flags
     o = lib.fspb_options(5, 0.5, 0.5, 2.0, 0.1, 0, 1, 0); bad.append((ct, bs, tabs, o, None))   # rho range
     o = lib.fspb_options(5, 0.5, 0.5, 0.1, 2.0, 0, 3, 0); bad.append((ct, bs, tabs, o, None))   # dc flag
+    o = lib.fspb_options(5, 0.5, 0.5, 0.1, 2.0, 0, 1, 0, 4, 8); bad.append((ct, bs, tabs, o, None))  # tile shape
+    o = lib.fspb_options(5, 0.5, 0.5, 0.1, 2.0, 0, 1, 0, 0, 3); bad.append((ct, bs, tabs, o, None))  # tile waves
     for c, b, t, o, nb in bad:
         rc, h = _create(lib, c, b, t, o, nb)
         assert rc == lib.FSPB_E_ARG, lib.load().fspb_last_error()
