@@ -231,6 +231,28 @@ def test_adjoint_full_small(oracle_mod, dc):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+def test_adjoint_long_rows_span_several_windows(oracle_mod):
+    """A beam along the x rows of a long grid: the 512 rows of a chunk hold
+    about 150,000 voxels, more than one window of the adjoint's block table
+    (65,536), so several windows per chunk are walked."""
+    n = (300, 40, 13)
+    rng = np.random.default_rng(21)
+    rho = rng.uniform(0.6, 1.4, size=(n[2], n[1], n[0])).astype(np.float32)
+    rho[:, :, :4] = 0.001
+    rho[:, :, -4:] = 0.001
+    beams = [S.Beam(gantry=math.pi / 2, nbx=4, nby=3, wx=0.5, wy=0.5),
+             S.Beam(gantry=-math.pi / 2 + 0.05, nbx=3, nby=3, wx=0.5, wy=0.5)]
+    plan = S.plan_small(n=n, density=rho, beams=beams, seed=21, name="long_rows")
+    w = rng.uniform(0, 1, plan.n_vox).astype(np.float32)
+    orc = oracle_mod.Oracle(plan)
+    g_o, amb = orc.adjoint(w)
+    geo = geometry(plan, 1)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    say(f"long rows adjoint: max |err|/max g = {np.abs(g - g_o).max() / np.abs(g_o).max():.2e}")
+    assert np.all(np.abs(g - g_o) <= REL_TOL * np.abs(g_o).max() + amb)
+    geo.close()
+
+
 def test_autograd_function():
     from paper_1103_1164_amd import FspbDose
     plan = _ragged_plans()[0]

@@ -168,7 +168,7 @@ def test_loss_decreases_on_a_smooth_target():
 
 
 # ---------------------------------------------------------------------------
-def _hetero_plan(seed=0, n=(30, 26, 22)):
+def _hetero_plan(seed=0, n=(30, 26, 22), tables=None):
     rng = np.random.default_rng(seed)
     Z, Y, X = np.meshgrid(*[np.arange(k) for k in n[::-1]], indexing="ij")
     rho = rng.normal(1.03, 0.02, size=n[::-1])
@@ -178,7 +178,19 @@ def _hetero_plan(seed=0, n=(30, 26, 22)):
     beams = [S.Beam(gantry=0.2, nbx=6, nby=5, wx=0.5, wy=0.5),
              S.Beam(gantry=2.4, couch=0.3, nbx=5, nby=5, wx=0.6, wy=0.4, cx=0.2)]
     return S.plan_small(n=n, density=rho.astype(np.float32), beams=beams, seed=seed,
-                        name=f"hetero{seed}")
+                        tables=tables, name=f"hetero{seed}")
+
+
+def _indep_drift_tables():
+    """Tables whose second weight drift is not a multiple of the first, so
+    the corrected pairs read two drift tables."""
+    import dataclasses
+    from fspb_synth.tables import Table1D
+    t = S.make_tables(0)
+    b1 = t.b1
+    rho = b1.start + b1.step * np.arange(b1.n)
+    v = (-0.6 * b1.values + 0.01 * (rho - 1.0) ** 2).astype(np.float32)
+    return dataclasses.replace(t, b2=Table1D(b1.start, b1.step, v))
 
 
 def test_sample_rows_match_oracle(oracle_mod):
@@ -277,10 +289,11 @@ def test_infer_matches_oracle(oracle_mod):
     assert n_checked > 20 and n_fb > 20, (n_checked, n_fb)
 
 
-@pytest.mark.parametrize("het", [0.3, -1.0])
-def test_forward_surrogate_matches_oracle(oracle_mod, het):
-    plan = _hetero_plan(4)
+@pytest.mark.parametrize("het,indep", [(0.3, False), (-1.0, False), (0.3, True)])
+def test_forward_surrogate_matches_oracle(oracle_mod, het, indep):
+    plan = _hetero_plan(4, tables=_indep_drift_tables() if indep else None)
     geo = geometry(plan, 1)
+    assert geo.info()["drift_tables"] == (2 if indep else 1)
     o = oracle_mod.Oracle(plan)
     mean = np.array([np.log(2.0), np.log(2.0), np.log(0.7), np.log(0.7), 0.6, 0.3], np.float32)
     std = np.array([0.3, 0.3, 0.2, 0.2, 0.05, 0.05], np.float32)
