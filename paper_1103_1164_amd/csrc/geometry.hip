@@ -80,6 +80,89 @@ __global__ __launch_bounds__(256) void smooth_last_factors(
                          dens_lookup(tabs, dt.fw1, hc), dens_lookup(tabs, dt.fw2, hc));
 }
 
+// LDS-staged form of the three passes, for radii up to kSmMaxR voxels: a
+// workgroup stages a clamped (clamp-to-edge) neighbourhood of its tile in LDS
+// and sums the taps there, in the order smooth_taps uses, so the results are
+// bitwise those of the single-axis passes.
+constexpr int kSmTX = 64, kSmTY = 16, kSmTZ = 16, kSmMaxR = 24;
+
+// x and y passes of one 64 x 16 tile of a z-plane: the (64 + 2 rx) x
+// (16 + 2 ry) neighbourhood is staged, the x-pass runs on every staged row,
+// the y-pass on its results.  A wave takes whole rows, lane = x offset.  The
+// staged interior is the handle's copy of the input when `copy` is set.
+__global__ __launch_bounds__(256) void smooth_xy(const float* __restrict__ in,
+                                                 float* __restrict__ out, int nx, int ny,
+                                                 const float* __restrict__ wx, int rx,
+                                                 const float* __restrict__ wy, int ry,
+                                                 float* __restrict__ copy) {
+    extern __shared__ float sm[];
+    constexpr int kWaves = 256 / kWave;
+    const int W = kSmTX + 2 * rx, H = kSmTY + 2 * ry;
+    float* s_in = sm;           // [H][W]
+    float* s_x = sm + W * H;    // [H][kSmTX]
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int i0 = blockIdx.x * kSmTX, j0 = blockIdx.y * kSmTY;
+    const long plane = (long)blockIdx.z * nx * ny;
+    for (int jj = wid; jj < H; jj += kWaves) {
+        const float* src = in + plane + (long)min(max(j0 - ry + jj, 0), ny - 1) * nx;
+        for (int ii = lane; ii < W; ii += kWave) s_in[jj * W + ii] = src[min(max(i0 - rx + ii, 0), nx - 1)];
+    }
+    __syncthreads();
+    for (int jj = wid; jj < H; jj += kWaves) {
+        const float* row = s_in + jj * W + lane;   // tap d (-rx..rx) at row[d + rx]
+        float acc = 0.0f;
+        for (int d = 0; d <= 2 * rx; ++d) acc = fmaf(wx[d], row[d], acc);
+        s_x[jj * kSmTX + lane] = acc;
+    }
+    __syncthreads();
+    const int i = i0 + lane;
+    if (i >= nx) return;
+    for (int jj = wid; jj < kSmTY; jj += kWaves) {
+        const int j = j0 + jj;
+        if (j >= ny) break;
+        const float* col = s_x + jj * kSmTX + lane;   // tap d at col[(d + ry) kSmTX]
+        float acc = 0.0f;
+        for (int d = 0; d <= 2 * ry; ++d) acc = fmaf(wy[d], col[d * kSmTX], acc);
+        const long v = plane + (long)j * nx + i;
+        out[v] = acc;
+        if (copy) copy[v] = s_in[(jj + ry) * W + lane + rx];
+    }
+}
+
+// z pass of one 64 x 16 tile of an x-z plane (fixed j), fused with the
+// per-voxel factors as smooth_last_factors computes them.
+__global__ __launch_bounds__(256) void smooth_z_factors(
+    const float* __restrict__ in, const float* __restrict__ rho, float* __restrict__ rhohat,
+    float4* __restrict__ fac, int nx, int ny, int nz, const float* __restrict__ wz, int rz,
+    const float* __restrict__ tabs, DensTabs dt) {
+    extern __shared__ float sm[];   // [16 + 2 rz][kSmTX]
+    constexpr int kWaves = 256 / kWave;
+    const int H = kSmTZ + 2 * rz;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int i0 = blockIdx.x * kSmTX, k0 = blockIdx.y * kSmTZ, j = blockIdx.z;
+    const int gi = min(i0 + lane, nx - 1);
+    for (int kk = wid; kk < H; kk += kWaves) {
+        const int gk = min(max(k0 - rz + kk, 0), nz - 1);
+        sm[kk * kSmTX + lane] = in[((long)gk * ny + j) * nx + gi];
+    }
+    __syncthreads();
+    const int i = i0 + lane;
+    if (i >= nx) return;
+    for (int kk = wid; kk < kSmTZ; kk += kWaves) {
+        const int k = k0 + kk;
+        if (k >= nz) break;
+        const float* col = sm + kk * kSmTX + lane;   // tap d at col[(d + rz) kSmTX]
+        float acc = 0.0f;
+        for (int d = 0; d <= 2 * rz; ++d) acc = fmaf(wz[d], col[d * kSmTX], acc);
+        const long v = ((long)k * ny + j) * nx + i;
+        rhohat[v] = acc;
+        const float rc = fminf(fmaxf(rho[v], dt.rho_min), dt.rho_max);
+        const float hc = fminf(fmaxf(acc, dt.rho_min), dt.rho_max);
+        fac[v] = make_float4(dens_lookup(tabs, dt.fu1, rc), dens_lookup(tabs, dt.fu2, hc),
+                             dens_lookup(tabs, dt.fw1, hc), dens_lookup(tabs, dt.fw2, hc));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 2: beamlet frames in FP64, one thread per beamlet.
 // Beam (gantry phi, couch psi): central axis cax = Rc (-sin phi, cos phi, 0),
@@ -349,6 +432,20 @@ void launch_smooth(const float* rho, float* copy, hipEvent_t after_copy, float* 
     const float* wx = w3;
     const float* wy = w3 + (2 * r[0] + 1);
     const float* wz = wy + (2 * r[1] + 1);
+    // (grid dimension z of these launches is nz, then ny: at most 65535)
+    if (r[0] <= kSmMaxR && r[1] <= kSmMaxR && r[2] <= kSmMaxR && ny <= 65535 && nz <= 65535) {
+        const int bx = (nx + kSmTX - 1) / kSmTX;
+        const size_t sh_xy =
+            sizeof(float) * (size_t)(kSmTY + 2 * r[1]) * (kSmTX + 2 * r[0] + kSmTX);
+        hipLaunchKernelGGL(smooth_xy, dim3(bx, (ny + kSmTY - 1) / kSmTY, nz), dim3(256), sh_xy, s,
+                           rho, tmp0, nx, ny, wx, r[0], wy, r[1], copy);
+        if (after_copy) (void)hipEventRecord(after_copy, s);
+        const size_t sh_z = sizeof(float) * (size_t)(kSmTZ + 2 * r[2]) * kSmTX;
+        hipLaunchKernelGGL(smooth_z_factors, dim3(bx, (nz + kSmTZ - 1) / kSmTZ, ny), dim3(256), sh_z,
+                           s, (const float*)tmp0, copy ? (const float*)copy : rho, rhohat, fac, nx,
+                           ny, nz, wz, r[2], dtabs, dt);
+        return;
+    }
     hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, rho, tmp0, nx, ny, nz, 0, wx, r[0],
                        copy);
     if (after_copy) (void)hipEventRecord(after_copy, s);

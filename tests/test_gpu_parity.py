@@ -62,6 +62,25 @@ def test_c1_intermediates(oracle_mod):
         assert np.max(np.abs(g["W1"] - o["W1"])) < 1e-7 and np.max(np.abs(g["W2"] - o["W2"])) < 1e-7
 
 
+@pytest.mark.parametrize("sigma,spacing", [(0.5, (0.2, 0.25, 0.3)), (2.0, (0.2, 0.2, 0.2))])
+def test_smoothed_density_lds_and_wide_passes(oracle_mod, sigma, spacing):
+    """The smoothed density against the oracle's direct 3D sum: unequal
+    radii per axis (8, 6, 5 voxels: the LDS-staged passes) and a radius of
+    30 voxels (beyond the LDS tiles: the single-axis passes)."""
+    rng = np.random.default_rng(17)
+    n = (26, 21, 17)
+    rho = rng.uniform(0.05, 2.0, size=(n[2], n[1], n[0])).astype(np.float32)
+    plan = S.plan_small(n=n, spacing=spacing, density=rho, seed=17,
+                        options=S.Options(smooth_sigma=sigma), name="smooth")
+    geo = geometry(plan, 1)
+    orc = oracle_mod.Oracle(plan)
+    assert geo.info()["smooth_radius"] == orc.smooth_radius()
+    say(f"smoothing sigma={sigma}: radius {orc.smooth_radius()}")
+    rh = geo.smoothed_density().cpu().numpy()
+    assert np.max(np.abs(rh - orc.smoothed())) < 2e-6
+    geo.close()
+
+
 def test_c1_pair_counts_per_voxel(oracle_mod):
     plan = S.plan_c1()
     orc = oracle_mod.Oracle(plan)
