@@ -1,6 +1,8 @@
 // geometry.hip -- per-plan geometry kernels for gfx950 (Algorithm A2 kernels 1-4):
-//   smooth_pass / smooth_last_factors  smoothed density and per-voxel correction
-//                                      factors (Section 2.1, A1 step 1)
+//   smooth_xy / smooth_z_factors       smoothed density and per-voxel correction
+//                                      factors (Section 2.1, A1 step 1), with
+//                                      smooth_pass / smooth_last_factors for
+//                                      radii beyond the LDS tiles
 //   beamlet_setup                      beamlet frames and angles (A1 step 3)
 //   ray_trace                          entrance point and uniform-sampled
 //                                      radiological-depth / weight-drift tables
@@ -15,11 +17,12 @@ namespace fspb {
 // ---------------------------------------------------------------------------
 // Kernel 1: separable Gaussian smoothing with clamp-to-edge borders.  The
 // normalised 3D cube-truncated Gaussian is the product of three normalised
-// 1D kernels, so three 1D passes give the same sums.  Each thread produces
-// one voxel; the 64 lanes of a wave read consecutive x, so every tap load is
-// coalesced whatever the pass axis.  Grids hold fewer than 2^31 voxels
-// (checked at creation), so indices are 32-bit; taps are taken eight at a
-// time so that their loads are in flight together.
+// 1D kernels, so three 1D passes give the same sums.  The single-axis passes
+// below (one thread per voxel; the 64 lanes of a wave read consecutive x, so
+// every tap load is coalesced whatever the pass axis; taps taken eight at a
+// time so that their loads are in flight together; 32-bit indices, grids
+// hold fewer than 2^31 voxels) serve radii beyond the LDS-staged kernels
+// further down, which sum the same taps in the same order.
 __device__ __forceinline__ float smooth_taps(const float* __restrict__ base, int c, int n, int stride,
                                             const float* __restrict__ w, int r) {
     float acc = 0.0f;

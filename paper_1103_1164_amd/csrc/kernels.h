@@ -30,8 +30,9 @@ struct TraceInfo {
 };
 
 // Smoothed density and per-voxel factors from rho.  With copy non-null the
-// first pass also copies rho there (after_copy, if non-null, is recorded
-// once that pass is queued) and the factors read the copy.
+// first kernel also copies rho there (after_copy, if non-null, is recorded
+// once that kernel is queued) and the factors read the copy.  tmp1 is used
+// only by the single-axis passes (radii over 24 voxels).
 void launch_smooth(const float* rho, float* copy, hipEvent_t after_copy, float* tmp0, float* tmp1,
                    float* rhohat, float4* fac, int nx, int ny, int nz, const float* w3,
                    const int r[3], const float* dtabs, const DensTabs& dt, hipStream_t s);
