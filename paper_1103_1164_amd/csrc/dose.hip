@@ -321,7 +321,8 @@ __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
 constexpr int kAdjBlocks = 1024;
 
 template <int DC, int NW, bool LW>
-__global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_beamlets,
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6)))
+void dose_adjoint(DoseArgs a, int n_beamlets,
                                                           const float* __restrict__ w,
                                                           float* __restrict__ grad) {
     constexpr int NT = NW * kWave;
@@ -354,7 +355,10 @@ __global__ __launch_bounds__(NW * kWave) void dose_adjoint(DoseArgs a, int n_bea
     const int ib = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (ib >= n_beamlets) return;  // whole workgroup
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const BeamletDesc& d = a.bl[ib];
+    // the workgroup's descriptor, read once into scalar registers (through a
+    // plain reference the compiler reloads it with vector loads on every
+    // voxel block)
+    const BeamletDesc d = as_const(a.bl)[ib];
     float acc = 0.0f;
     if (d.hit) {
         // along a grid row (fixed j,k) the lateral offsets and the depth are
