@@ -398,7 +398,7 @@ int check_device(int* dev) {
     // the architecture of each device is looked up once (the property query
     // is slow compared with creating a plan)
     constexpr int kMaxDevices = 64;
-    static std::atomic<int> verdict[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
+    static std::atomic<int> arch_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || n < 1) {
@@ -406,12 +406,12 @@ int check_device(int* dev) {
         return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
     }
     HIP_TRY(hipGetDevice(dev));
-    const int v = (*dev >= 0 && *dev < kMaxDevices) ? verdict[*dev].load() : 0;
+    const int v = (*dev >= 0 && *dev < kMaxDevices) ? arch_ok[*dev].load() : 0;
     if (v == 1) return FSPB_OK;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, *dev));
     const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (*dev >= 0 && *dev < kMaxDevices) verdict[*dev].store(ok ? 1 : -1);
+    if (*dev >= 0 && *dev < kMaxDevices) arch_ok[*dev].store(ok ? 1 : -1);
     if (!ok)
         return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
                     prop.gcnArchName);
