@@ -226,6 +226,15 @@ int fspb_set_dc(fspb_geometry* g, int enabled);
 /* Plan summary (host struct). */
 int fspb_geometry_info(const fspb_geometry* g, fspb_info* info);
 
+/* Weight-drift tables a density-corrected pair reads with these commissioned
+ * tables (host call; needs no device).  Returns 1 when b2 equals
+ * ratio * b1 at every sample of one density grid (Section 2.1 integrates a
+ * single b: ratio 1), so that the second drift is ratio * W1; 2 otherwise
+ * (ratio 0).  ratio (host) may be NULL.  FSPB_E_ARG when t, or the b1 or b2
+ * values, are NULL or a table has no samples.  fspb_geometry_info reports
+ * the same for a handle (drift_tables, drift_ratio). */
+int fspb_drift_tables(const fspb_tables* t, float* ratio);
+
 /* Copies the smoothed density (device [n_vox]) of a DC handle. */
 int fspb_smoothed_density(const fspb_geometry* g, float* out, void* stream);
 

@@ -66,6 +66,16 @@ def _marshal_tables(tables):
     return tabs
 
 
+def drift_tables(tables):
+    """(1, ratio) when the commissioned b2 is ratio * b1 at every sample (the
+    corrected pairs then read one weight-drift table), else (2, 0.0).  A host
+    call of the library; no device needed."""
+    r = C.c_float()
+    n = load().fspb_drift_tables(C.byref(_marshal_tables(tables)), C.byref(r))
+    check(n if n < 0 else 0, "fspb_drift_tables")
+    return n, r.value
+
+
 class Geometry:
     """A plan's geometry on the GPU (owning handle of libfspb)."""
 

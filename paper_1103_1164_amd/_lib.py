@@ -111,6 +111,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_ulonglong), C.c_void_p]),
     "fspb_set_dc": (C.c_int, [C.c_void_p, C.c_int]),
     "fspb_geometry_info": (C.c_int, [C.c_void_p, C.POINTER(fspb_info)]),
+    "fspb_drift_tables": (C.c_int, [C.POINTER(fspb_tables), C.POINTER(C.c_float)]),
     "fspb_smoothed_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_beamlet": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(fspb_beamlet_info),
                                C.POINTER(C.c_float), C.POINTER(C.c_float),

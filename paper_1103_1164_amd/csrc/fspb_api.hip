@@ -1021,6 +1021,15 @@ int fspb_set_dc(fspb_geometry* g, int enabled) {
     return FSPB_OK;
 }
 
+int fspb_drift_tables(const fspb_tables* t, float* ratio) {
+    if (!t || !t->b1.v || !t->b2.v || t->b1.n < 1 || t->b2.n < 1)
+        return fail(FSPB_E_ARG, "drift_tables: NULL tables or empty b1 / b2");
+    float c = 0.0f;
+    const bool one = drift_proportional(t->b1, t->b2, &c);
+    if (ratio) *ratio = one ? c : 0.0f;
+    return one ? 1 : 2;
+}
+
 int fspb_geometry_info(const fspb_geometry* g, fspb_info* info) {
     if (!g || !info) return fail(FSPB_E_ARG, "geometry_info: NULL argument");
     int rc = g->fetch_host();

@@ -129,3 +129,32 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_drift_table_mode_on_the_host(lib):
+    """fspb_drift_tables: one weight-drift table when b2 is a multiple of b1
+    at every sample of one grid (Section 2.1's single b has ratio 1), two
+    otherwise; checked without a device on the table variants the GPU tests
+    run."""
+    import dataclasses
+    from fspb_synth.tables import Table1D
+    from paper_1103_1164_amd import drift_tables
+    t = S.make_tables(0)
+    b1 = t.b1
+    rho = b1.start + b1.step * np.arange(b1.n)
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a, np.float32))
+    cases = [
+        (t.b2, (1, -1.0)),                                                        # b2 = -b1
+        (Table1D(b1.start, b1.step, b1.values.copy()), (1, 1.0)),                 # one b
+        (Table1D(b1.start, b1.step, f32(0.5 * b1.values)), (1, 0.5)),
+        (Table1D(b1.start, b1.step, f32(-0.6 * b1.values + 0.01 * (rho - 1) ** 2)), (2, 0.0)),
+        (Table1D(b1.start, b1.step, f32(np.concatenate([-b1.values, -b1.values[-1:]]))), (2, 0.0)),
+        (Table1D(b1.start + b1.step, b1.step, f32(-b1.values)), (2, 0.0)),        # shifted grid
+    ]
+    for b2, want in cases:
+        assert drift_tables(dataclasses.replace(t, b2=b2)) == want
+    z = Table1D(b1.start, b1.step, f32(0.0 * b1.values))
+    assert drift_tables(dataclasses.replace(t, b1=z, b2=z)) == (1, 1.0)          # no drift at all
+    assert drift_tables(dataclasses.replace(t, b1=z)) == (2, 0.0)                 # b1 = 0, b2 != 0
+    L = lib.load()
+    assert L.fspb_drift_tables(None, None) == lib.FSPB_E_ARG
