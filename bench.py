@@ -114,6 +114,8 @@ def parse():
                     help="training heads for the surrogate (config 5 uses 200)")
     ap.add_argument("--forward-only", type=int, default=0,
                     help="profiling aid: only launch the forward kernel this many times")
+    ap.add_argument("--adjoint-only", type=int, default=0,
+                    help="profiling aid: only launch the adjoint kernel this many times")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling aid: also copy a buffer of this many MiB once (a kernel "
                          "of known traffic, to calibrate the HBM byte counters)")
@@ -162,6 +164,15 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"forward_launches": a.forward_only, "pairs": pairs_fwd}))
+        return
+    if a.adjoint_only:
+        w = torch.as_tensor(np.random.default_rng(5).uniform(0, 1, plan.n_vox).astype(np.float32),
+                            device=dev)
+        g = torch.empty(plan.n_beamlets, device=dev)
+        for _ in range(a.adjoint_only):
+            geo.adjoint(w, out=g)
+        torch.cuda.synchronize()
+        print(json.dumps({"adjoint_launches": a.adjoint_only, "pairs": pairs_all}))
         return
 
     # A stream of plans: each plan's geometry is created on its own stream and
