@@ -351,7 +351,17 @@ def test_edge_cases(oracle_mod):
     # 1x1x1 grid
     p3 = S.plan_small(n=(1, 1, 1), density=1.0, beams=[S.Beam(gantry=0.7, nbx=2, nby=2)], seed=0)
     d_o, amb, _ = oracle_mod.Oracle(p3).dose()
-    assert_dose_parity(gpu_dose(geometry(p3, 1), p3.fluence), d_o, amb, what="1x1x1")
+    g3 = geometry(p3, 1)
+    assert_dose_parity(gpu_dose(g3, p3.fluence), d_o, amb, what="1x1x1")
+    # the adjoint on the same cases: the missing beamlet gets zero, nothing
+    # entering gives a zero gradient, the single voxel matches the oracle
+    for plan_, geo_, what in ((p, g, "miss"), (p2, g2, "no entry"), (p3, g3, "1x1x1")):
+        w = np.random.default_rng(2).uniform(0.5, 1.0, plan_.n_vox).astype(np.float32)
+        grad = geo_.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+        g_o, amb_g = oracle_mod.Oracle(plan_).adjoint(w)
+        assert np.all(np.abs(grad - g_o) <= REL_TOL * max(np.abs(g_o).max(), 1e-30) + amb_g), what
+    assert geometry(p, 1).adjoint(torch.ones(p.n_vox, device="cuda"))[2].item() == 0.0
+    assert torch.count_nonzero(g2.adjoint(torch.ones(p2.n_vox, device="cuda"))) == 0
 
 
 def test_errors_on_gpu():
