@@ -496,3 +496,24 @@ def test_longitudinal_factor_uses_beamlet_angle(oracle_mod):
     m = d0 > 1e-3 * d0.max()
     ratio = d1[m] / d0[m]
     assert np.max(np.abs(ratio - (1.0 + theta))) < 1e-6
+
+
+def test_second_drift_integrates_its_own_b(oracle_mod):
+    """Section 2.1's drift is the integral of b(rho) along the beamlet from
+    the entrance; with a b per weight component (a reading of the paper's
+    single b) the second drift integrates b2, not b1: b2 = 0 gives W2 = 0
+    while W1 is not, b2 = 2 b1 gives W2 = 2 W1 and b2 = -b1 gives -W1
+    (exactly: the trapezoid sums scale), on the slab phantom's central
+    beamlet."""
+    import dataclasses
+    from fspb_synth.tables import Table1D
+    rho = S.slab_density()
+    base = S.make_tables(0)
+    b1 = base.b1
+    for scale in (0.0, 2.0, -1.0):
+        b2 = Table1D(b1.start, b1.step, np.ascontiguousarray(scale * b1.values, np.float32))
+        plan = _axis_plan(rho, dataclasses.replace(base, b2=b2), n=(64, 64, 64))
+        tr = oracle_mod.Oracle(plan).trace(0)
+        W1, W2 = np.asarray(tr["W1"]), np.asarray(tr["W2"])
+        assert np.max(np.abs(W1)) > 1e-3                 # the slabs give a real drift
+        assert np.array_equal(W2, scale * W1), scale
