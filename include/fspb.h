@@ -267,7 +267,8 @@ int fspb_wait_ready(fspb_geometry* g, void* stream);
  * 8, each workgroup stages the water (depth) table in LDS when it fits in
  * 64 KB, i.e. up to 1365 depth samples (else that launch uses 4 waves and
  * reads the table from global memory).  A new handle starts with shape 0,
- * 4 x 4 x 4 voxels, and 8 waves.  For a given brick shape results do not
+ * 4 x 4 x 4 voxels, and 8 waves, or with the tile given in
+ * fspb_options.tile_shape / tile_waves.  For a given brick shape results do not
  * depend on the configuration (each voxel sums its pairs in the same order,
  * from the same table values); another shape may change a pair's rounding,
  * as each wave picks one of two exact forms of the Eq. 4 profile product,
