@@ -89,23 +89,35 @@ __global__ __launch_bounds__(256) void smooth_last_factors(
 // bitwise those of the single-axis passes.
 constexpr int kSmTX = 64, kSmTY = 16, kSmTZ = 16, kSmMaxR = 24;
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// tiles of these kernels share their halos with their neighbours, so each
+// XCD takes a contiguous run of tiles (x fastest): workgroup q works on tile
+// (q mod 8) per + q / 8 of a grid of 8 per workgroups; tiles past n_tiles
+// return at once.
+__device__ __forceinline__ int xcd_tile(int per) {
+    return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
 // x and y passes of one 64 x 16 tile of a z-plane: the (64 + 2 rx) x
 // (16 + 2 ry) neighbourhood is staged, the x-pass runs on every staged row,
 // the y-pass on its results.  A wave takes whole rows, lane = x offset.  The
 // staged interior is the handle's copy of the input when `copy` is set.
 __global__ __launch_bounds__(256) void smooth_xy(const float* __restrict__ in,
-                                                 float* __restrict__ out, int nx, int ny,
+                                                 float* __restrict__ out, int nx, int ny, int nz,
                                                  const float* __restrict__ wx, int rx,
                                                  const float* __restrict__ wy, int ry,
-                                                 float* __restrict__ copy) {
+                                                 float* __restrict__ copy, int per) {
     extern __shared__ float sm[];
     constexpr int kWaves = 256 / kWave;
+    const int nbx = (nx + kSmTX - 1) / kSmTX, nby = (ny + kSmTY - 1) / kSmTY;
+    const int tile = xcd_tile(per);
+    if (tile >= nbx * nby * nz) return;   // the whole workgroup
     const int W = kSmTX + 2 * rx, H = kSmTY + 2 * ry;
     float* s_in = sm;           // [H][W]
     float* s_x = sm + W * H;    // [H][kSmTX]
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int i0 = blockIdx.x * kSmTX, j0 = blockIdx.y * kSmTY;
-    const long plane = (long)blockIdx.z * nx * ny;
+    const int i0 = (tile % nbx) * kSmTX, j0 = ((tile / nbx) % nby) * kSmTY;
+    const long plane = (long)(tile / (nbx * nby)) * nx * ny;
     for (int jj = wid; jj < H; jj += kWaves) {
         const float* src = in + plane + (long)min(max(j0 - ry + jj, 0), ny - 1) * nx;
         for (int ii = lane; ii < W; ii += kWave) s_in[jj * W + ii] = src[min(max(i0 - rx + ii, 0), nx - 1)];
@@ -137,12 +149,15 @@ __global__ __launch_bounds__(256) void smooth_xy(const float* __restrict__ in,
 __global__ __launch_bounds__(256) void smooth_z_factors(
     const float* __restrict__ in, const float* __restrict__ rho, float* __restrict__ rhohat,
     float4* __restrict__ fac, int nx, int ny, int nz, const float* __restrict__ wz, int rz,
-    const float* __restrict__ tabs, DensTabs dt) {
+    const float* __restrict__ tabs, DensTabs dt, int per) {
     extern __shared__ float sm[];   // [16 + 2 rz][kSmTX]
     constexpr int kWaves = 256 / kWave;
+    const int nbx = (nx + kSmTX - 1) / kSmTX, nbk = (nz + kSmTZ - 1) / kSmTZ;
+    const int tile = xcd_tile(per);
+    if (tile >= nbx * nbk * ny) return;   // the whole workgroup
     const int H = kSmTZ + 2 * rz;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int i0 = blockIdx.x * kSmTX, k0 = blockIdx.y * kSmTZ, j = blockIdx.z;
+    const int i0 = (tile % nbx) * kSmTX, k0 = ((tile / nbx) % nbk) * kSmTZ, j = tile / (nbx * nbk);
     const int gi = min(i0 + lane, nx - 1);
     for (int kk = wid; kk < H; kk += kWaves) {
         const int gk = min(max(k0 - rz + kk, 0), nz - 1);
@@ -435,18 +450,20 @@ void launch_smooth(const float* rho, float* copy, hipEvent_t after_copy, float* 
     const float* wx = w3;
     const float* wy = w3 + (2 * r[0] + 1);
     const float* wz = wy + (2 * r[1] + 1);
-    // (grid dimension z of these launches is nz, then ny: at most 65535)
-    if (r[0] <= kSmMaxR && r[1] <= kSmMaxR && r[2] <= kSmMaxR && ny <= 65535 && nz <= 65535) {
-        const int bx = (nx + kSmTX - 1) / kSmTX;
+    if (r[0] <= kSmMaxR && r[1] <= kSmMaxR && r[2] <= kSmMaxR) {
+        const long bx = (nx + kSmTX - 1) / kSmTX;
+        const long t_xy = bx * ((ny + kSmTY - 1) / kSmTY) * nz;   // tiles of each kernel
+        const long t_z = bx * ((nz + kSmTZ - 1) / kSmTZ) * ny;
+        const int per_xy = (int)((t_xy + 7) / 8), per_z = (int)((t_z + 7) / 8);
         const size_t sh_xy =
             sizeof(float) * (size_t)(kSmTY + 2 * r[1]) * (kSmTX + 2 * r[0] + kSmTX);
-        hipLaunchKernelGGL(smooth_xy, dim3(bx, (ny + kSmTY - 1) / kSmTY, nz), dim3(256), sh_xy, s,
-                           rho, tmp0, nx, ny, wx, r[0], wy, r[1], copy);
+        hipLaunchKernelGGL(smooth_xy, dim3(8 * per_xy), dim3(256), sh_xy, s, rho, tmp0, nx, ny,
+                           nz, wx, r[0], wy, r[1], copy, per_xy);
         if (after_copy) (void)hipEventRecord(after_copy, s);
         const size_t sh_z = sizeof(float) * (size_t)(kSmTZ + 2 * r[2]) * kSmTX;
-        hipLaunchKernelGGL(smooth_z_factors, dim3(bx, (nz + kSmTZ - 1) / kSmTZ, ny), dim3(256), sh_z,
-                           s, (const float*)tmp0, copy ? (const float*)copy : rho, rhohat, fac, nx,
-                           ny, nz, wz, r[2], dtabs, dt);
+        hipLaunchKernelGGL(smooth_z_factors, dim3(8 * per_z), dim3(256), sh_z, s,
+                           (const float*)tmp0, copy ? (const float*)copy : rho, rhohat, fac, nx,
+                           ny, nz, wz, r[2], dtabs, dt, per_z);
         return;
     }
     hipLaunchKernelGGL(smooth_pass, dim3(blocks), dim3(256), 0, s, rho, tmp0, nx, ny, nz, 0, wx, r[0],
