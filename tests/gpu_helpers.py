@@ -20,9 +20,9 @@ def say(msg):
     sys.stdout.flush()
 
 
-def geometry(plan, dc=None):
+def geometry(plan, dc=None, tile=None):
     from paper_1103_1164_amd import Geometry
-    return Geometry.from_plan(plan, device="cuda", dc_enabled=dc)
+    return Geometry.from_plan(plan, device="cuda", dc_enabled=dc, tile=tile)
 
 
 def gpu_dose(geo, fluence):

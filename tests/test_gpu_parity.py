@@ -154,10 +154,14 @@ _FULL = {"c2": S.plan_c2, "c3": S.plan_c3, "paper_h5": S.plan_paper_h5, "paper_l
 def test_full_size_forward_sampled(oracle_mod, cfg):
     """Configs 2 and 3, and the paper-shaped plans (Table 1 scales: 0.4 x 0.4
     x 0.25 cm voxels, 0.2 x 0.5 cm beamlets, non-coplanar beams for the
-    head-and-neck case)."""
+    head-and-neck case).  Config 2 runs with the tile bench.py times it with."""
+    from bench import C2_TILE
     plan = _FULL[cfg]()
-    say(f"{cfg}: geometry")
-    geo = geometry(plan, 1)
+    tile = C2_TILE if cfg == "c2" else None
+    say(f"{cfg}: geometry, tile {tile}")
+    geo = geometry(plan, 1, tile=tile)
+    if tile is not None:
+        assert geo.get_tile() == tuple(tile)
     d_gpu = gpu_dose(geo, plan.fluence)
     info = geo.info()
     assert info["n_entry_ambiguous"] == 0
@@ -227,6 +231,28 @@ def test_c3_adjoint_sampled_and_fd(oracle_mod):
         dL = torch.sum(wt.double() * (Dp - Dm) * (Dp + Dm - 2 * D0.double()))
         fd = float(dL / (2 * hh))
         assert abs(fd - float(gq[i])) <= 2e-3 * max(abs(float(gq[i])), 1e-3 * float(gq.abs().max()))
+
+
+def test_c2_adjoint_sampled(oracle_mod):
+    """The adjoint over every beamlet of config 2 (the launch bench.py
+    times), against the oracle at sampled beamlets: random ones and those
+    with the largest gradients."""
+    from bench import C2_TILE
+    plan = S.plan_c2()
+    geo = geometry(plan, 1, tile=C2_TILE)
+    w = np.random.default_rng(13).uniform(0, 1, plan.n_vox).astype(np.float32)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(g)) and g.min() >= 0.0
+    rng = np.random.default_rng(14)
+    pick = np.unique(np.concatenate([rng.choice(plan.n_beamlets, 16, replace=False),
+                                     np.argsort(g)[-4:]]))
+    say(f"c2 adjoint: oracle for {pick.size} beamlets")
+    g_o, amb = oracle_mod.Oracle(plan).adjoint(w, pick)
+    scale = np.max(np.abs(g_o))
+    err = np.abs(g[pick] - g_o)
+    assert np.all(err <= REL_TOL * scale + amb), (err / scale).max()
+    say(f"c2 adjoint: max |err|/max g = {(err / scale).max():.2e}")
+    geo.close()
 
 
 # ---------------------------------------------------------------------------
