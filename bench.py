@@ -612,9 +612,35 @@ def cpu_baseline(plan, n_sample):
     _, _, pc = orc.dose(vox=vox)
     dt = time.perf_counter() - t0
     pairs = int(pc.sum())
-    return {"value": pairs / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_sample} voxels of the same plan drawn at random with replacement "
-                      f"(all beamlets, DC), {pairs} evaluated pairs in {dt:.2f} s, FP64, OpenMP"}
+    res = {"value": pairs / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_sample} voxels of the same plan drawn at random with replacement "
+                     f"(all beamlets, DC), {pairs} evaluated pairs in {dt:.2f} s, FP64, OpenMP"}
+    res["single_core"] = _oracle_one_core(plan, vox[: max(1, n_sample // 64)])
+    return res
+
+
+def _oracle_one_core(plan, vox):
+    """The oracle on one host core: config 1 whole and a voxel sample of the
+    given plan, evaluated pairs per second each."""
+    import ctypes
+    import oracle
+    import fspb_synth as S
+    gomp = ctypes.CDLL("libgomp.so.1")        # the OpenMP runtime the oracle is built with
+    n_before = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(1)
+    out = {}
+    try:
+        for name, p, v in (("c1", S.plan_c1(), None), ("sample", plan, vox)):
+            t0 = time.perf_counter()
+            _, _, pc = oracle.Oracle(p).dose(vox=v)
+            dt = time.perf_counter() - t0
+            out[name] = {"evals_per_s": int(pc.sum()) / dt, "pairs": int(pc.sum()),
+                         "s": round(dt, 2)}
+    finally:
+        gomp.omp_set_num_threads(n_before)
+    out["note"] = (f"one thread; c1: the whole 64^3 grid; sample: the first {len(vox)} "
+                   "voxels of the sample above")
+    return out
 
 
 if __name__ == "__main__":
