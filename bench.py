@@ -311,6 +311,7 @@ def main():
                         "geometry + forward",
             "voxels": plan.n_vox, "beamlets": plan.n_beamlets,
             "pairs_forward": pairs_fwd, "pairs_all_beamlets": pairs_all,
+            "dense_pairs": plan.n_vox * plan.n_beamlets,
             "k_max": info["k_max"],
         },
         "ms_per_plan": round(ms_plan, 4),
