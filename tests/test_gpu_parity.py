@@ -222,7 +222,7 @@ def test_c3_adjoint_sampled_and_fd(oracle_mod):
     gq = geo.adjoint(wq).double()
     h = 0.05
     rng = np.random.default_rng(5)
-    for i in rng.choice(nb, size=8, replace=False):
+    for i in rng.choice(nb, size=16, replace=False):
         fp, fm = f.clone(), f.clone()
         fp[i] += h
         fm[i] -= h
