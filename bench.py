@@ -116,6 +116,9 @@ def parse():
                     help="profiling aid: only launch the forward kernel this many times")
     ap.add_argument("--adjoint-only", type=int, default=0,
                     help="profiling aid: only launch the adjoint kernel this many times")
+    ap.add_argument("--profile-plan", choices=("c2", "paper_h5"), default="c2",
+                    help="profiling aid: the plan --forward-only / --adjoint-only launch on "
+                         "(paper_h5: the paper-shaped head-and-neck plan, default tile)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling aid: also copy a buffer of this many MiB once (a kernel "
                          "of known traffic, to calibrate the HBM byte counters)")
@@ -138,7 +141,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    plan = S.plan_c2()
+    if a.profile_plan != "c2" and not (a.forward_only or a.adjoint_only):
+        print("--profile-plan is a profiling aid: give --forward-only or --adjoint-only",
+              file=sys.stderr)
+        sys.exit(2)
+    plan = S.plan_paper_h5() if a.profile_plan == "paper_h5" else S.plan_c2()
+    tile = C2_TILE if a.profile_plan == "c2" else None
     dens = torch.as_tensor(plan.density, device=dev)
     flu = torch.as_tensor(plan.fluence, device=dev)
     dose = torch.empty(plan.shape, device=dev)
@@ -146,7 +154,7 @@ def main():
     def make(dc=1, stream=None):
         # the forward schedule is built for the benchmark's tile at creation
         return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables,
-                        _opts(plan.options, dc), stream=stream, tile=C2_TILE)
+                        _opts(plan.options, dc), stream=stream, tile=tile)
 
     geo = make()
     geo_tile = geo.get_tile()
