@@ -17,7 +17,7 @@ beam counts and beamlet counts of the paper's head-and-neck and lung cases
 """
 from .tables import (Tables, Table1D, make_tables, make_tables_coeffs, table_coeffs, TABLE_COEFFS,
                      constant_tables)
-from .plan import Beam, Options, Plan, grid_origin_centered
+from .plan import Beam, Options, Plan, grid_origin_centered, abi_rounded
 from .phantoms import (
     plan_c1, plan_c2, plan_c3, plans_c4, plan_c4, c5_phantom, plan_c5, plan_small,
     c2_density, c3_density, slab_density, c3_objective, C3_ISO, C5_TRAIN_SEEDS, C5_HELDOUT_SEEDS,
@@ -27,7 +27,7 @@ from .phantoms import (
 __all__ = [
     "Tables", "Table1D", "make_tables", "make_tables_coeffs", "table_coeffs", "TABLE_COEFFS",
     "constant_tables",
-    "Beam", "Options", "Plan", "grid_origin_centered",
+    "Beam", "Options", "Plan", "grid_origin_centered", "abi_rounded",
     "plan_c1", "plan_c2", "plan_c3", "plans_c4", "plan_c4", "c5_phantom", "plan_c5",
     "C5_TRAIN_SEEDS", "C5_HELDOUT_SEEDS", "plan_paper_h5", "plan_paper_l2", "PAPER_SPACING",
     "commissioning_plans",

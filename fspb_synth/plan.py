@@ -76,3 +76,31 @@ def grid_origin_centered(n: Tuple[int, int, int], spacing: Tuple[float, float, f
                          center=(0.0, 0.0, 0.0)) -> Tuple[float, float, float]:
     """Origin (centre of voxel 0) of an (nx, ny, nz) grid centred on ``center``."""
     return tuple(float(c - (ni - 1) * d / 2.0) for ni, d, c in zip(n, spacing, center))
+
+
+def _f32(x) -> float:
+    return float(np.float32(x))
+
+
+def abi_rounded(plan: Plan) -> Plan:
+    """The plan as the library's C interface receives it: every geometric,
+    table-grid and option value that the interface passes as a 32-bit float
+    (spacing, origin, beam angles, isocentre, SAD, beamlet widths and offsets,
+    table starts and steps, the theta step, the option scalars) rounded to
+    float32.  Arrays (density, fluence, table values) are float32 already.
+    A reference that is given this plan computes on exactly the instance the
+    library computes on."""
+    import copy
+    beams = [Beam(gantry=_f32(b.gantry), couch=_f32(b.couch), iso=tuple(_f32(v) for v in b.iso),
+                  sad=_f32(b.sad), nbx=b.nbx, nby=b.nby, wx=_f32(b.wx), wy=_f32(b.wy),
+                  cx=_f32(b.cx), cy=_f32(b.cy)) for b in plan.beams]
+    tabs = copy.copy(plan.tables)
+    for name, val in vars(plan.tables).items():
+        if hasattr(val, "start") and hasattr(val, "step"):
+            setattr(tabs, name, type(val)(_f32(val.start), _f32(val.step), val.values))
+    tabs.theta_step = _f32(plan.tables.theta_step)
+    o = copy.copy(plan.options)
+    for name in ("roi_radius", "rho_surface", "smooth_sigma", "rho_min", "rho_max", "sample_step"):
+        setattr(o, name, _f32(getattr(o, name)))
+    return Plan(plan.name, plan.density, tuple(_f32(v) for v in plan.spacing),
+                tuple(_f32(v) for v in plan.origin), beams, plan.fluence, tabs, o)

@@ -169,6 +169,17 @@ typedef struct {
     double theta;          /* angle to the beam's central axis */
     double src[3], dir[3], ex[3], ey[3];
     double entry_margin;   /* min |rho_k - rho_surface| over samples up to the entrance */
+    /* The single-precision constants of the pair test (Algorithm A1 step 8)
+     * as the dose kernels read them: with q the voxel centre relative to the
+     * grid centre P0 = o + (n - 1) delta / 2, each q_a = fma(index_a,
+     * delta_a, o_a - P0_a) in single precision,
+     *   t  = fma(q_x, pair_t[0], fma(q_y, pair_t[1], fma(q_z, pair_t[2], pair_t[3])))
+     * is the depth below the entrance and xp, yp (pair_x, pair_y alike) the
+     * lateral offsets from the axis; the pair counts iff t >= 0 and
+     * fma(xp, xp, yp * yp) <= R * R, all in single precision.  pair_t[0..2]
+     * is dir rounded to single precision, pair_t[3] = (P0 - src).dir -
+     * s_entry rounded from double; pair_x, pair_y likewise with ex, ey. */
+    float pair_t[4], pair_x[4], pair_y[4];
 } fspb_beamlet_info;
 
 /* Builds the per-plan geometry on the device (Algorithm A2 steps 2-5):

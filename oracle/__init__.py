@@ -23,7 +23,9 @@ LIB_PATH = HERE / "liboracle.so"
 
 def build(verbose: bool = False) -> Path:
     """Compile liboracle.so with gcc (OpenMP, -O2)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
+    # -ffp-contract=off: a * b + c is never fused behind the source's back
+    # (the single-precision pair test fuses exactly where it calls fmaf)
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
            "-o", str(LIB_PATH), str(HERE / "fspb_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
@@ -87,6 +89,7 @@ def lib():
         L.orc_smoothed_at.argtypes = [C.c_void_p, C.c_long]
         L.orc_smooth_all.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.orc_smooth_radius.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+        L.orc_pair_consts.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float)]
         L.orc_pair.restype = C.c_double
         L.orc_pair.argtypes = [C.c_void_p, C.c_long, C.c_int, C.POINTER(C.c_int)]
         L.orc_dose.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_long, C.POINTER(C.c_long),
@@ -194,6 +197,13 @@ class Oracle:
         a = [np.zeros(max(K, 1)) for _ in range(5)]
         lib().orc_trace_siddon(self.ctx, int(i), *[_ptr(v, C.c_double) for v in a], K)
         return dict(K=K, t=a[0][:K], T=a[1][:K], W1=a[2][:K], W2=a[3][:K], rho=a[4][:K])
+
+    def pair_consts(self, i: int) -> np.ndarray:
+        """Single-precision constants of beamlet i's pair test, [3, 4]:
+        rows (d, c_t), (ex, c_x), (ey, c_y)."""
+        out = np.zeros(12, dtype=np.float32)
+        lib().orc_pair_consts(self.ctx, int(i), _ptr(out, C.c_float))
+        return out.reshape(3, 4)
 
     # -- smoothing --------------------------------------------------------
     def smoothed(self, vox=None) -> np.ndarray:

@@ -39,6 +39,13 @@ typedef struct {
     double *st, *sT, *sW1, *sW2, *srho, *sb1, *sb2;
 } trace_t;
 
+/* The pair test's single-precision constants of one beamlet (see
+ * pair_counted): t = q.a + c over the voxel centre q relative to the grid
+ * centre, for the depth (t), and the two lateral offsets (x, y). */
+typedef struct {
+    float t[4], x[4], y[4];
+} pair32_t;
+
 struct orc_ctx {
     orc_grid g;
     orc_tables tab;
@@ -47,9 +54,13 @@ struct orc_ctx {
     frame_t* fr;
     trace_t* tr;
     beam_t* bm;
+    pair32_t* p32;     /* per beamlet */
+    float q0[3], d32[3], R2f;   /* voxel (0,0,0) relative to the grid centre, spacing, R^2 */
     int rad[3];
     double* wts;      /* normalised 3D smoothing weights, [2rz+1][2ry+1][2rx+1] */
 };
+
+static void build_pair32(orc_ctx* c);
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                                 */
@@ -473,6 +484,7 @@ orc_ctx* orc_create(const orc_grid* g, int n_beams, const orc_beam* beams,
         if (c->opt.siddon) trace_siddon(c, i);
     }
     build_weights(c);
+    build_pair32(c);
     return c;
 }
 
@@ -493,6 +505,7 @@ void orc_destroy(orc_ctx* c) {
     free(c->tr);
     free(c->fr);
     free(c->bm);
+    free(c->p32);
     free(c->wts);
     free(c);
 }
@@ -534,34 +547,93 @@ int orc_trace(const orc_ctx* c, int i, double info[10], double* T, double* W1, d
     return t->K;
 }
 
+static void voxel_center(const orc_grid* g, long vox, double* r) {
+    int i = (int)(vox % g->nx), j = (int)((vox / g->nx) % g->ny), k = (int)(vox / ((long)g->nx * g->ny));
+    r[0] = g->ox + i * g->dx;
+    r[1] = g->oy + j * g->dy;
+    r[2] = g->oz + k * g->dz;
+}
+
 /* ------------------------------------------------------------------ */
+/* The pair test of Algorithm A1 step 8: the voxel lies inside the ROI
+ * cylinder (distance from the beamlet axis at most R, inclusive) and below
+ * the entrance (t >= 0).  Its outcome is discrete, so near the cylinder
+ * surface and the entrance plane the precision of the arithmetic decides it.
+ * reading: the test is taken in single precision, the precision of the
+ * method's GPU implementation, by this recipe.  With P0 the grid centre
+ * (o + (n - 1) delta / 2, in double), the voxel centre relative to P0 is
+ * q_a = fma(index_a, (float)delta_a, (float)(o_a - P0_a)); each beamlet
+ * holds, rounded to single precision from double, its direction d, lateral
+ * axes ex, ey and the offsets c_t = (P0 - r_s).d - s_entry,
+ * c_x = (P0 - r_s).ex, c_y = (P0 - r_s).ey; then
+ *   t  = fma(q_x, d_x, fma(q_y, d_y, fma(q_z, d_z, c_t)))   (xp, yp alike)
+ * and the pair counts iff t >= 0 and fma(xp, xp, yp * yp) <= R * R (all
+ * single precision, fma rounded once).  Everything else about the pair is
+ * computed in double. */
+static void build_pair32(orc_ctx* c) {
+    const orc_grid* g = &c->g;
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double o[3] = {g->ox, g->oy, g->oz}, del[3] = {g->dx, g->dy, g->dz};
+    double P0[3];
+    for (int a = 0; a < 3; ++a) {
+        P0[a] = o[a] + 0.5 * (n[a] - 1) * del[a];
+        c->q0[a] = (float)(o[a] - P0[a]);
+        c->d32[a] = (float)del[a];
+    }
+    const float Rf = (float)c->opt.roi_radius;
+    c->R2f = Rf * Rf;
+    c->p32 = (pair32_t*)calloc(c->n_beamlets, sizeof(pair32_t));
+    for (int i = 0; i < c->n_beamlets; ++i) {
+        const frame_t* f = &c->fr[i];
+        double v0[3] = {P0[0] - f->src[0], P0[1] - f->src[1], P0[2] - f->src[2]};
+        pair32_t* p = &c->p32[i];
+        for (int a = 0; a < 3; ++a) {
+            p->t[a] = (float)f->d[a];
+            p->x[a] = (float)f->ex[a];
+            p->y[a] = (float)f->ey[a];
+        }
+        p->t[3] = (float)(dot3(v0, f->d) - c->tr[i].s_entry);
+        p->x[3] = (float)dot3(v0, f->ex);
+        p->y[3] = (float)dot3(v0, f->ey);
+    }
+}
+
+static int pair_counted(const orc_ctx* c, long vox, int i) {
+    const orc_grid* g = &c->g;
+    const int idx[3] = {(int)(vox % g->nx), (int)((vox / g->nx) % g->ny),
+                        (int)(vox / ((long)g->nx * g->ny))};
+    float q[3];
+    for (int a = 0; a < 3; ++a) q[a] = fmaf((float)idx[a], c->d32[a], c->q0[a]);
+    const pair32_t* p = &c->p32[i];
+    const float t = fmaf(q[0], p->t[0], fmaf(q[1], p->t[1], fmaf(q[2], p->t[2], p->t[3])));
+    const float xp = fmaf(q[0], p->x[0], fmaf(q[1], p->x[1], fmaf(q[2], p->x[2], p->x[3])));
+    const float yp = fmaf(q[0], p->y[0], fmaf(q[1], p->y[1], fmaf(q[2], p->y[2], p->y[3])));
+    const float yy = yp * yp;
+    return t >= 0.0f && fmaf(xp, xp, yy) <= c->R2f;
+}
+
 /* Eqs. 2-4 for one (voxel, beamlet) pair, Algorithm A1 steps 8-12.
  * x and y are the lateral offsets of the voxel from the beamlet axis scaled
  * to the isocentre plane by SAD/|r_a| (reading), |r_a| is the distance along
  * the beamlet direction, t = |r_a| - s_entry is the depth below the surface.
  * rho_c and rhohat_c are the voxel's density and smoothed density clamped to
- * the commissioned range (reading). */
-static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c, double rhohat_c,
+ * the commissioned range (reading).  flags: bit 0 = the pair counts. */
+static double pair_value(const orc_ctx* c, long vox, int i, double rho_c, double rhohat_c,
                          int* flags, const double* given, double* params) {
     const frame_t* f = &c->fr[i];
     const trace_t* t = &c->tr[i];
     const orc_tables* tb = &c->tab;
     *flags = 0;
     if (!t->hit) return 0.0;
+    if (!pair_counted(c, vox, i)) return 0.0;
+    double r[3];
+    voxel_center(&c->g, vox, r);
     double v[3] = {r[0] - f->src[0], r[1] - f->src[1], r[2] - f->src[2]};
     double s = dot3(v, f->d);
     double xp = dot3(v, f->ex), yp = dot3(v, f->ey);
-    double R2 = c->opt.roi_radius * c->opt.roi_radius;
-    double rr = xp * xp + yp * yp;
     double depth = s - t->s_entry;
-    int in_roi = rr <= R2, in_depth = depth >= 0.0;
-    int near_roi = fabs(rr - R2) <= ORC_TOL_ROI_REL * R2, near_t = fabs(depth) <= ORC_TOL_T;
-    /* a pair is evaluated if it passes both tests or misses them only by the
-     * ambiguity tolerance (then it is flagged, not counted) */
-    if (!((in_roi || near_roi) && (in_depth || near_t))) return 0.0;
-    if (in_roi && in_depth) *flags |= 1;
-    if (near_roi || near_t) *flags |= 2;
-    if (s <= 0.0) { *flags = 0; return 0.0; }
+    if (s <= 0.0) return 0.0;
+    *flags = 1;
 
     double mag = f->sad / s;
     double x = xp * mag, y = yp * mag;
@@ -611,12 +683,6 @@ static double pair_value(const orc_ctx* c, const double* r, int i, double rho_c,
     return F * A * isq;
 }
 
-static void voxel_center(const orc_grid* g, long vox, double* r) {
-    int i = (int)(vox % g->nx), j = (int)((vox / g->nx) % g->ny), k = (int)(vox / ((long)g->nx * g->ny));
-    r[0] = g->ox + i * g->dx;
-    r[1] = g->oy + j * g->dy;
-    r[2] = g->oz + k * g->dz;
-}
 
 static void voxel_densities(const orc_ctx* c, long vox, const double* rhohat_all, double* rc, double* rhc) {
     double rho = c->g.rho[vox];
@@ -628,12 +694,21 @@ static void voxel_densities(const orc_ctx* c, long vox, const double* rhohat_all
     }
 }
 
+void orc_pair_consts(const orc_ctx* c, int i, float out[12]) {
+    const pair32_t* p = &c->p32[i];
+    for (int a = 0; a < 4; ++a) {
+        out[a] = p->t[a];
+        out[4 + a] = p->x[a];
+        out[8 + a] = p->y[a];
+    }
+}
+
 double orc_pair(const orc_ctx* c, long vox, int i, int* flags) {
     double r[3], rc, rhc;
     int fl;
     voxel_center(&c->g, vox, r);
     voxel_densities(c, vox, NULL, &rc, &rhc);
-    double v = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
+    double v = pair_value(c, vox, i, rc, rhc, &fl, NULL, NULL);
     if (flags) *flags = fl;
     return v;
 }
@@ -652,7 +727,7 @@ void orc_dose(const orc_ctx* c, const float* fluence, long n, const long* vox,
         for (int i = 0; i < c->n_beamlets; ++i) {
             if (fluence[i] == 0.0f) continue;
             int fl;
-            double d = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
+            double d = pair_value(c, v, i, rc, rhc, &fl, NULL, NULL);
             if (fl & 1) {
                 acc += fluence[i] * d;
                 ++np;
@@ -680,7 +755,7 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list, doubl
             for (int q = 0; q < n && !need; ++q) {
                 int fl;
                 int i = list ? list[q] : q;
-                pair_value(c, r, i, 1.0, 1.0, &fl, NULL, NULL);
+                pair_value(c, v, i, 1.0, 1.0, &fl, NULL, NULL);
                 need = fl != 0;
             }
             rh[v] = need ? orc_smoothed_at(c, v) : 1.0;
@@ -696,7 +771,7 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list, doubl
             int fl;
             voxel_center(&c->g, v, r);
             voxel_densities(c, v, rh, &rc, &rhc);
-            double d = pair_value(c, r, i, rc, rhc, &fl, NULL, NULL);
+            double d = pair_value(c, v, i, rc, rhc, &fl, NULL, NULL);
             if (fl & 1) acc += w[v] * d;
             if (fl & 2) a += fabs(w[v] * d);
         }
@@ -715,7 +790,7 @@ void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts) {
         int cnt = 0;
         for (int i = 0; i < c->n_beamlets; ++i) {
             int fl;
-            pair_value(c, r, i, 1.0, 1.0, &fl, NULL, NULL);
+            pair_value(c, v, i, 1.0, 1.0, &fl, NULL, NULL);
             if (fl & 1) ++cnt;
         }
         counts[q] = cnt;
@@ -737,7 +812,7 @@ int orc_params(const orc_ctx* c, long vox, int i, double out[6]) {
     voxel_center(&c->g, vox, r);
     voxel_densities(c, vox, NULL, &rc, &rhc);
     for (int k = 0; k < 6; ++k) out[k] = 0.0;
-    pair_value(c, r, i, rc, rhc, &fl, NULL, out);
+    pair_value(c, vox, i, rc, rhc, &fl, NULL, out);
     return fl;
 }
 
@@ -745,7 +820,7 @@ double orc_pair_given(const orc_ctx* c, long vox, int i, const double prm[6], in
     double r[3];
     int fl;
     voxel_center(&c->g, vox, r);
-    double v = pair_value(c, r, i, 1.0, 1.0, &fl, prm, NULL);
+    double v = pair_value(c, vox, i, 1.0, 1.0, &fl, prm, NULL);
     if (flags) *flags = fl;
     return v;
 }
@@ -841,8 +916,8 @@ void orc_dose_given(const orc_ctx* c, const float* fluence, long n, const long* 
             if (fluence[i] == 0.0f) continue;
             const double* row = prm + (q * c->n_beams + c->fr[i].beam) * 7;
             int fl;
-            double d = row[6] != 0.0 ? pair_value(c, r, i, rc, rhc, &fl, NULL, NULL)
-                                     : pair_value(c, r, i, rc, rhc, &fl, row, NULL);
+            double d = row[6] != 0.0 ? pair_value(c, v, i, rc, rhc, &fl, NULL, NULL)
+                                     : pair_value(c, v, i, rc, rhc, &fl, row, NULL);
             if (fl & 1) acc += fluence[i] * d;
             if (fl & 2) a += fabs(fluence[i] * d);
         }

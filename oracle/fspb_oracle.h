@@ -18,8 +18,11 @@
  *   adjoint g = D^T w     (transpose of Eq. 1; not in the paper)
  *
  * Every value is computed in double precision, brute force over every voxel
- * and every beamlet, in a fixed summation order.  Parity status of each
- * function is listed at its declaration.
+ * and every beamlet, in a fixed summation order -- except the pair test (is
+ * the voxel inside the beamlet's ROI cylinder and below its entrance?),
+ * whose discrete outcome is taken in single precision by a fixed recipe (see
+ * orc_pair_consts).  Parity status of each function is listed at its
+ * declaration.
  */
 #ifndef FSPB_ORACLE_H
 #define FSPB_ORACLE_H
@@ -65,10 +68,6 @@ typedef struct {
                              uniform samples of Section 2.2, see orc_trace_siddon */
 } orc_options;
 
-/* Ambiguity tolerances: a pair whose ROI or depth test lies this close to
- * its boundary may be decided either way by a lower-precision implementation. */
-#define ORC_TOL_ROI_REL 1e-4   /* |xp^2+yp^2 - R^2| <= tol * R^2 */
-#define ORC_TOL_T       1e-4   /* |t| <= tol (cm) */
 
 typedef struct orc_ctx orc_ctx;
 
@@ -114,23 +113,30 @@ void orc_smooth_all(const orc_ctx* c, double* out);
 /* Truncation radius (voxels) of the smoothing kernel along each axis. */
 void orc_smooth_radius(const orc_ctx* c, int r[3]);
 
+/* The pair test (Algorithm A1 step 8: inside the ROI cylinder, below the
+ * entrance) decides a discrete outcome, so it is taken in single precision,
+ * the precision of the method's GPU implementation, by a fixed recipe (see
+ * pair_counted in the source); the pair's dose is computed in double.  The
+ * recipe's per-beamlet constants: out[0..3] = (d, c_t), out[4..7] = (ex, c_x),
+ * out[8..11] = (ey, c_y), each rounded to single precision. */
+void orc_pair_consts(const orc_ctx* c, int i, float out[12]);
+
 /* Unit-fluence dose of beamlet i at voxel vox (Eq. 2).  flags (if non-NULL)
- * gets bit 0 = pair counted (in ROI and t >= 0 and beamlet hits),
- * bit 1 = ambiguous (close to the ROI or depth boundary).  The returned value
- * is the would-be contribution for an ambiguous pair even when it is not
- * counted. */
+ * gets bit 0 = pair counted (beamlet hits, in ROI and t >= 0).  Returns 0 for
+ * a pair that does not count. */
 double orc_pair(const orc_ctx* c, long vox, int i, int* flags);
 
 /* Dose (Eq. 1) at n voxels listed in vox (or every voxel when vox is NULL, in
- * which case n must equal the grid size).  amb[k] gets the ambiguity
- * allowance sum |f_i D_i(r)| over ambiguous pairs; pairs[k] the number of
- * counted pairs with f_i != 0.  amb and pairs may be NULL. */
+ * which case n must equal the grid size).  pairs[k] gets the number of
+ * counted pairs with f_i != 0.  amb[k] is an allowance for pairs that two
+ * implementations of the method may count differently: 0, since the pair test
+ * follows the single-precision recipe above.  amb and pairs may be NULL. */
 void orc_dose(const orc_ctx* c, const float* fluence, long n, const long* vox,
               double* dose, double* amb, long long* pairs);
 
 /* Adjoint g_i = sum_r w(r) D_i(r) for the n beamlets listed (all beamlets
- * when list is NULL and n equals the beamlet count), with allowance
- * amb_i = sum |w(r) D_i(r)| over ambiguous pairs.  amb may be NULL. */
+ * when list is NULL and n equals the beamlet count); amb as for orc_dose.
+ * amb may be NULL. */
 void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list,
                  double* g, double* amb);
 
@@ -162,8 +168,8 @@ double orc_pair_given(const orc_ctx* c, long vox, int i, const double prm[6], in
 int orc_nearest_beamlet(const orc_ctx* c, long vox, int beam, double* tie);
 /* Surrogate input row (200 patch densities, depth, theta) of (voxel, beam),
  * definition at the function.  Returns the nearest beamlet, or -1 when the
- * row is invalid.  *amb (may be NULL) flags a pair test within tolerance of
- * its boundary.  Pinned: linear density fields give the analytic patch. */
+ * row is invalid.  *amb (may be NULL) gets 0 (the pair test follows the
+ * single-precision recipe, so no row is ambiguous).  Pinned: linear density fields give the analytic patch. */
 int orc_surrogate_row(const orc_ctx* c, long vox, int beam, double feat[202], int* amb);
 /* Dose with per-(voxel, beam) parameters prm[n][n_beams][7] (six parameters
  * and a fallback flag: non-zero means the method's own parameters).

@@ -316,7 +316,9 @@ class Geometry:
         out = dict(hit=bool(inf.hit), k_entry=inf.k_entry, n_samples=inf.n_samples, K=inf.K,
                    s_in=inf.s_in, s_entry=inf.s_entry, theta=inf.theta,
                    src=np.array(inf.src), d=np.array(inf.dir), ex=np.array(inf.ex),
-                   ey=np.array(inf.ey), entry_margin=inf.entry_margin)
+                   ey=np.array(inf.ey), entry_margin=inf.entry_margin,
+                   pair_consts=np.array([list(inf.pair_t), list(inf.pair_x), list(inf.pair_y)],
+                                        dtype=np.float32))
         if tables and inf.K > 0:
             T, W1, W2 = (np.zeros(inf.K, np.float32) for _ in range(3))
             P = C.POINTER(C.c_float)

@@ -68,7 +68,8 @@ class fspb_beamlet_info(C.Structure):
     _fields_ = [("hit", C.c_int), ("k_entry", C.c_int), ("n_samples", C.c_int), ("K", C.c_int),
                 ("s_in", C.c_double), ("s_entry", C.c_double), ("theta", C.c_double),
                 ("src", C.c_double * 3), ("dir", C.c_double * 3), ("ex", C.c_double * 3),
-                ("ey", C.c_double * 3), ("entry_margin", C.c_double)]
+                ("ey", C.c_double * 3), ("entry_margin", C.c_double),
+                ("pair_t", C.c_float * 4), ("pair_x", C.c_float * 4), ("pair_y", C.c_float * 4)]
 
 
 class fspb_tune_result(C.Structure):

@@ -1090,6 +1090,14 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
             info->ey[q] = f.ey[q];
         }
         info->entry_margin = ti.margin;
+        for (int q = 0; q < 3; ++q) {
+            info->pair_t[q] = d.d[q];
+            info->pair_x[q] = d.ex[q];
+            info->pair_y[q] = d.ey[q];
+        }
+        info->pair_t[3] = d.c_t;
+        info->pair_x[3] = d.c_x;
+        info->pair_y[3] = d.c_y;
     }
     int n = std::min(max_k, d.K);
     if (n > 0 && (T || W1 || W2) && g->siddon)

@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import fspb_synth as S
-from gpu_helpers import assert_dose_parity, geometry, gpu_dose, say
+from gpu_helpers import abi_oracle, assert_dose_parity, geometry, gpu_dose, say
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +116,7 @@ def test_water_table_too_large_for_lds(oracle_mod, dc):
     d8 = gpu_dose(geo, plan.fluence)
     geo.set_tile(0, 4)
     assert np.array_equal(gpu_dose(geo, plan.fluence), d8)
-    orc = oracle_mod.Oracle(plan, dc_enabled=dc)
+    orc = abi_oracle(plan, dc_enabled=dc)
     d_o, amb, _ = orc.dose()
     assert_dose_parity(d8, d_o, amb, what="fine water tables")
     # the adjoint's global-memory path (4-wave workgroups) on the same tables
@@ -230,5 +230,5 @@ def test_c4_batch_full_size(oracle_mod):
             hot = np.argsort(got.reshape(-1))[-300:]
             vox = np.unique(np.concatenate([vox, hot]))
             say(f"c4: oracle {p.name} at {vox.size} voxels")
-            d_o, amb, _ = oracle_mod.Oracle(p).dose(vox=vox)
+            d_o, amb, _ = abi_oracle(p).dose(vox=vox)
             assert_dose_parity(got.reshape(-1)[vox], d_o, amb, what=p.name)

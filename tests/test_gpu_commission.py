@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import fspb_synth as S
-from gpu_helpers import say
+from gpu_helpers import abi_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ def test_fit_recovers_perturbed_machine(oracle_mod):
     for p in plans:
         q = S.Plan(p.name, p.density, p.spacing, p.origin, p.beams, p.fluence,
                    S.make_tables_coeffs(truth), p.options)
-        refs.append(oracle_mod.Oracle(q).dose()[0].astype(np.float32))
+        refs.append(abi_oracle(q).dose()[0].astype(np.float32))
     say("commission: fit")
     res = fit_tables(plans, refs, S.make_tables_coeffs, np.ones(8), iters=30, log=say)
     err = np.abs(res["c"] - truth) / truth

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import fspb_synth as S
-from gpu_helpers import say
+from gpu_helpers import abi_oracle, say
 from oracle import gamma as G
 
 pytestmark = pytest.mark.gpu
@@ -78,7 +78,7 @@ def test_gamma_of_the_method_on_config1(oracle_mod):
     config 1 (doses from the oracle): gamma grid and statistics agree."""
     plan = S.plan_c1()
     say("c1: oracle doses")
-    d_dc = oracle_mod.Oracle(plan, dc_enabled=1).dose()[0].astype(np.float32)
-    d_pl = oracle_mod.Oracle(plan, dc_enabled=0).dose()[0].astype(np.float32)
+    d_dc = abi_oracle(plan, dc_enabled=1).dose()[0].astype(np.float32)
+    d_pl = abi_oracle(plan, dc_enabled=0).dose()[0].astype(np.float32)
     _, st = _check(d_dc, d_pl, plan.spacing)
     assert st["gamma_max"] > 0.5

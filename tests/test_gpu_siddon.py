@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import fspb_synth as S
-from gpu_helpers import assert_dose_parity, gpu_dose, say
+from gpu_helpers import abi_oracle, assert_dose_parity, gpu_dose, say
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,7 @@ def _plans():
 def test_siddon_full_grid(oracle_mod, k, dc):
     plan = _siddon(_plans()[k], dc)
     say(f"siddon {plan.name} dc={dc}")
-    d_o, amb, _ = oracle_mod.Oracle(plan).dose()
+    d_o, amb, _ = abi_oracle(plan).dose()
     geo = _geometry(plan)
     d = gpu_dose(geo, plan.fluence)
     assert d_o.max() > 0
@@ -65,7 +65,7 @@ def test_siddon_c2_sampled(oracle_mod):
     vox = np.unique(np.concatenate([rng.choice(plan.n_vox, 2000, replace=False),
                                     np.argsort(d.reshape(-1))[-500:]]))
     say(f"siddon c2: oracle at {vox.size} voxels")
-    o = oracle_mod.Oracle(plan)
+    o = abi_oracle(plan)
     d_o, amb, _ = o.dose(vox=vox)
     assert_dose_parity(d.reshape(-1)[vox], d_o, amb, what="siddon c2")
     hits = sum(o.trace(i)["hit"] for i in range(plan.n_beamlets))

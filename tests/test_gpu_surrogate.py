@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import fspb_synth as S
-from gpu_helpers import assert_dose_parity, geometry, say
+from gpu_helpers import abi_oracle, assert_dose_parity, geometry, say
 from oracle import mlp as M
 
 pytestmark = pytest.mark.gpu
@@ -196,7 +196,7 @@ def _indep_drift_tables():
 def test_sample_rows_match_oracle(oracle_mod):
     plan = _hetero_plan(1)
     geo = geometry(plan, 1)
-    o = oracle_mod.Oracle(plan)
+    o = abi_oracle(plan)
     rng = np.random.default_rng(2)
     n = 700
     vox = rng.integers(0, o.n_vox, size=n)
@@ -239,7 +239,7 @@ def _trained_like(seed, mean, std):
 def test_infer_matches_oracle(oracle_mod):
     plan = _hetero_plan(2)
     geo = geometry(plan, 1)
-    o = oracle_mod.Oracle(plan)
+    o = abi_oracle(plan)
     # outputs z = (log u1x, log u1y, log u2x, log u2y, w1, w2), standardised
     mean = np.array([np.log(2.0), np.log(2.1), np.log(0.7), np.log(0.65), 0.6, 0.3], np.float32)
     std = np.array([0.3, 0.3, 0.2, 0.2, 0.05, 0.05], np.float32)
@@ -294,7 +294,7 @@ def test_forward_surrogate_matches_oracle(oracle_mod, het, indep):
     plan = _hetero_plan(4, tables=_indep_drift_tables() if indep else None)
     geo = geometry(plan, 1)
     assert geo.info()["drift_tables"] == (2 if indep else 1)
-    o = oracle_mod.Oracle(plan)
+    o = abi_oracle(plan)
     mean = np.array([np.log(2.0), np.log(2.0), np.log(0.7), np.log(0.7), 0.6, 0.3], np.float32)
     std = np.array([0.3, 0.3, 0.2, 0.2, 0.05, 0.05], np.float32)
     mlp = _trained_like(31, mean, std)
