@@ -229,6 +229,24 @@ int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void*
 int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
                      unsigned long long* total, void* stream);
 
+/* fspb_count_pairs for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same count of the pairs fspb_forward evaluates (or of all pairs with
+ * fluence NULL), written to a device word, with no allocation, no host
+ * synchronisation and no memset, so the call can be captured in a graph.
+ *   fluence  device [n_beamlets] or NULL.
+ *   total    device unsigned long long; receives the sum (asynchronously).
+ * Its scratch is a static array of 4 MiB + 2 KiB on each device the library
+ * runs on (held until the process ends): per-brick counts for at most
+ * 1,048,576 bricks of the handle's tile shape (about 64 million voxels), then
+ * the partial sums.  A larger plan returns FSPB_E_ARG.  Every call on one
+ * device shares that device's array, so calls whose work overlaps on the
+ * device (on different streams without ordering between them) race; calls
+ * ordered on one stream do not.  The handle's device must be the current
+ * device (else FSPB_E_ARG).  Asynchronous on stream. */
+int fspb_count_pairs_noalloc(fspb_geometry* g, const float* fluence, unsigned long long* total,
+                             void* stream);
+
 /* Switches the forward/adjoint between the density-corrected model (1) and
  * plain FSPB (0).  Enabling DC on a handle created with dc_enabled = 0
  * returns FSPB_E_STATE. */

@@ -191,6 +191,22 @@ class Geometry:
               "fspb_count_pairs")
         return (int(tot.value), counts) if per_voxel else int(tot.value)
 
+    def count_pairs_noalloc(self, fluence: Optional[torch.Tensor] = None,
+                            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """The pair count of count_pairs into a device int64 word, with no
+        allocation in the library and no host synchronisation."""
+        fp = C.c_void_p(0)
+        if fluence is not None:
+            f = _dev_f32(fluence, self.device)
+            fp = C.c_void_p(f.data_ptr())
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=self.device)
+        if out.dtype != torch.int64 or out.numel() < 1 or not out.is_cuda:
+            raise ValueError("out must be a device int64 tensor")
+        check(load().fspb_count_pairs_noalloc(self._handle(), fp, C.c_void_p(out.data_ptr()),
+                                              _stream(stream)), "fspb_count_pairs_noalloc")
+        return out
+
     def wait_ready(self, stream=None) -> None:
         """Makes stream (default: the current one) wait on the device for this
         plan's creation work, e.g. before recording a timing event there."""

@@ -110,6 +110,7 @@ SIGNATURES = {
     "fspb_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_count_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_ulonglong), C.c_void_p]),
+    "fspb_count_pairs_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_set_dc": (C.c_int, [C.c_void_p, C.c_int]),
     "fspb_geometry_info": (C.c_int, [C.c_void_p, C.POINTER(fspb_info)]),
     "fspb_drift_tables": (C.c_int, [C.POINTER(fspb_tables), C.POINTER(C.c_float)]),

@@ -48,13 +48,14 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // Forward pass over one brick, three modes sharing the candidate search:
 //   kDose   D(r) = sum_i f_i D_i(r) over beamlets with f_i != 0
 //   kCount  number of evaluated pairs per voxel
+//   kCountBrick  the same summed over the brick's voxels: one value per brick
 //   kSurr   the dose with the learned surrogate's parameters: per (voxel,
 //           beam) row prm[2 (b n_vox + v) + 0..1] = ((u1x, u1y, u2x, u2y)
 //           log2 e, (w1, w2, fallback, 0)); a row whose fallback flag is set
 //           takes the density-corrected pair instead
 // A brick is BX x BY x BZ = 64 voxels, one per lane.
 //   kSid    the dose with the exact (Siddon) depth tables
-enum { kDose = 0, kCount = 1, kSurr = 3, kSid = 4 };
+enum { kDose = 0, kCount = 1, kCountBrick = 2, kSurr = 3, kSid = 4 };
 
 template <int BX, int BY, int BZ>
 __device__ __forceinline__ int bricks_x(const PlanConst& P) { return (P.nx + BX - 1) / BX; }
@@ -193,7 +194,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                 // evaluated on every lane (no short circuit) so that the whole
                 // descriptor is fetched in one scalar batch before the branch
                 const bool act = pair_coords(d, P, qx, qy, qz, t, xp, yp) & valid;
-                if (MODE == kCount) {
+                if (MODE == kCount || MODE == kCountBrick) {
                     cnt += act ? 1 : 0;
                     continue;
                 }
@@ -218,7 +219,12 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
         }
         acc += accb;
     }
-    if (valid) {
+    if (MODE == kCountBrick) {
+        // lanes outside the grid counted nothing; lane 0 (the brick's corner
+        // voxel) is always inside it
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+        if (lane == 0) out_int[brick] = cnt;
+    } else if (valid) {
         if (MODE == kCount)
             out_int[v] = cnt;
         else
@@ -639,7 +645,7 @@ static void launch_mode(const DoseArgs& a, TileCfg cfg, const int* order, const 
                         float* dose, int* out_int, hipStream_t s, const float4* prm = nullptr) {
     const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
     const bool lds = cfg.waves_per_block == kLdsWaves;
-    const bool lw = lds && MODE != kCount && water_bytes <= (size_t)kLdsWaterMax;
+    const bool lw = lds && MODE != kCount && MODE != kCountBrick && water_bytes <= (size_t)kLdsWaterMax;
     const int wpb = lds && !lw ? 4 : cfg.waves_per_block;
     const long nb = brick_count(a.P, cfg.shape);
     dim3 grid((unsigned)((nb + wpb - 1) / wpb)), block(kWave * wpb);
@@ -691,6 +697,11 @@ void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                   int* counts, hipStream_t s) {
     launch_mode<kPlain, kCount>(a, cfg, order, fluence, nullptr, counts, s);
+}
+
+void launch_count_bricks(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
+                         int* brick_counts, hipStream_t s) {
+    launch_mode<kPlain, kCountBrick>(a, cfg, order, fluence, nullptr, brick_counts, s);
 }
 
 // Scheduling estimate, one thread per brick: the brick's bounding sphere is

@@ -985,30 +985,97 @@ int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void*
     return FSPB_OK;
 }
 
+constexpr int kCountParts = 256;   // first-stage partial sums of a pair count
+
 int fspb_count_pairs(fspb_geometry* g, const float* fluence, int* counts,
                      unsigned long long* total, void* stream) {
     if (!g || !total) return fail(FSPB_E_ARG, "count_pairs: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     const long nv = (long)g->P.nx * g->P.ny * g->P.nz;
-    const int n_part = 256;
     int rc = settle(g, s);
     if (rc) return rc;
+    // without per-voxel counts, one count per brick of the tile's shape
+    long max_bricks = 0;
+    for (int sh = 0; sh < kNumShapes; ++sh) max_bricks = std::max(max_bricks, brick_count(g->P, sh));
     if (!counts && !g->counts)
-        if ((rc = g->alloc((void**)&g->counts, sizeof(int) * nv)) != FSPB_OK) return rc;
+        if ((rc = g->alloc((void**)&g->counts, sizeof(int) * max_bricks)) != FSPB_OK) return rc;
     if (!g->partial) {
-        if ((rc = g->alloc((void**)&g->partial, sizeof(unsigned long long) * n_part)) != FSPB_OK)
+        if ((rc = g->alloc((void**)&g->partial, sizeof(unsigned long long) * kCountParts)) != FSPB_OK)
             return rc;
         if ((rc = g->alloc((void**)&g->total, sizeof(unsigned long long))) != FSPB_OK) return rc;
     }
-    int* c = counts ? counts : g->counts;
-    launch_count(g->args(), g->tile, g->order, fluence, c, s);
-    HIP_TRY(hipGetLastError());
-    launch_sum_counts(c, nv, g->partial, n_part, g->total, s);
+    const DoseArgs a = g->args();
+    if (counts) {
+        launch_count(a, g->tile, g->order, fluence, counts, s);
+        HIP_TRY(hipGetLastError());
+        launch_sum_counts(counts, nv, g->partial, kCountParts, g->total, s);
+    } else {
+        launch_count_bricks(a, g->tile, g->order, fluence, g->counts, s);
+        HIP_TRY(hipGetLastError());
+        launch_sum_counts(g->counts, brick_count(g->P, g->tile.shape), g->partial, kCountParts,
+                          g->total, s);
+    }
     HIP_TRY(hipGetLastError());
     unsigned long long h = 0;
     HIP_TRY(hipMemcpyAsync(&h, g->total, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *total = h;
+    return FSPB_OK;
+}
+
+// ---- the pair count without allocation ------------------------------------
+// Scratch of fspb_count_pairs_noalloc: per-brick counts, then the partial
+// sums.  One copy per device, held until the process ends; kernels take its
+// device address (scratch_ptr), never the host-side name.
+constexpr long kNoAllocMaxBricks = 1L << 20;
+constexpr size_t kNoAllocPartOff = sizeof(int) * kNoAllocMaxBricks;
+constexpr size_t kNoAllocScratchBytes = kNoAllocPartOff + sizeof(unsigned long long) * kCountParts;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device), looked up
+// once per device.
+static int scratch_ptr(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(FSPB_E_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FSPB_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FSPB_OK;
+}
+
+int fspb_count_pairs_noalloc(fspb_geometry* g, const float* fluence, unsigned long long* total,
+                             void* stream) {
+    if (!g || !total) return fail(FSPB_E_ARG, "count_pairs_noalloc: NULL argument");
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != g->device)
+        return fail(FSPB_E_ARG, "count_pairs_noalloc: the handle belongs to device %d, the current "
+                                "device is %d", g->device, cur);
+    const long nb = brick_count(g->P, g->tile.shape);
+    if (nb > kNoAllocMaxBricks)
+        return fail(FSPB_E_ARG, "count_pairs_noalloc: %ld bricks exceed the static scratch of %ld",
+                    nb, kNoAllocMaxBricks);
+    void* base = nullptr;
+    int rc = scratch_ptr(cur, &base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = settle(g, s)) != FSPB_OK) return rc;
+    // every brick and every partial is written: nothing needs clearing
+    int* bc = reinterpret_cast<int*>(base);
+    auto* part = reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(base) + kNoAllocPartOff);
+    launch_count_bricks(g->args(), g->tile, g->order, fluence, bc, s);
+    HIP_TRY(hipGetLastError());
+    launch_sum_counts(bc, nb, part, kCountParts, total, s);
+    HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
 

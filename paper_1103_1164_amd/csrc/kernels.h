@@ -91,6 +91,10 @@ void launch_forward_surrogate(const DoseArgs& a, TileCfg cfg, const int* order,
                               const float* fluence, const float4* prm, float* dose, hipStream_t s);
 void launch_count(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
                   int* counts, hipStream_t s);
+// Evaluated pairs summed per brick of the tile's shape: brick_counts[b] for
+// every brick b (brick_count(P, cfg.shape) values, each written once).
+void launch_count_bricks(const DoseArgs& a, TileCfg cfg, const int* order, const float* fluence,
+                         int* brick_counts, hipStream_t s);
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s);
 // order[0..n) = bricks by decreasing cost[brick] (one workgroup, no host round trip)
 void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s);
