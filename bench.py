@@ -116,9 +116,15 @@ def parse():
                     help="profiling aid: only launch the forward kernel this many times")
     ap.add_argument("--adjoint-only", type=int, default=0,
                     help="profiling aid: only launch the adjoint kernel this many times")
-    ap.add_argument("--profile-plan", choices=("c2", "paper_h5"), default="c2",
+    ap.add_argument("--profile-plan", choices=("c2", "c3", "paper_h5", "paper_l2"), default="c2",
                     help="profiling aid: the plan --forward-only / --adjoint-only launch on "
-                         "(paper_h5: the paper-shaped head-and-neck plan, default tile)")
+                         "(c2 with the benchmark's tile, the others with the library's default "
+                         "tile unless --profile-tile is given)")
+    ap.add_argument("--profile-tile", default=None,
+                    help="profiling aid: 'shape,waves' tile of the profiled forward")
+    ap.add_argument("--profile-schedule", type=int, choices=(0, 1), default=None,
+                    help="profiling aid: forward schedule of the profiled plan (0 bricks, "
+                         "1 per-beam items)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling aid: also copy a buffer of this many MiB once (a kernel "
                          "of known traffic, to calibrate the HBM byte counters)")
@@ -145,8 +151,11 @@ def main():
         print("--profile-plan is a profiling aid: give --forward-only or --adjoint-only",
               file=sys.stderr)
         sys.exit(2)
-    plan = S.plan_paper_h5() if a.profile_plan == "paper_h5" else S.plan_c2()
+    plan = {"c2": S.plan_c2, "c3": S.plan_c3, "paper_h5": S.plan_paper_h5,
+            "paper_l2": S.plan_paper_l2}[a.profile_plan]()
     tile = C2_TILE if a.profile_plan == "c2" else None
+    if a.profile_tile:
+        tile = tuple(int(v) for v in a.profile_tile.split(","))
     dens = torch.as_tensor(plan.density, device=dev)
     flu = torch.as_tensor(plan.fluence, device=dev)
     dose = torch.empty(plan.shape, device=dev)
@@ -157,6 +166,8 @@ def main():
                         _opts(plan.options, dc), stream=stream, tile=tile)
 
     geo = make()
+    if a.profile_schedule is not None:
+        geo.set_schedule(a.profile_schedule)
     geo_tile = geo.get_tile()
     pairs_fwd = geo.count_pairs(flu)
     pairs_all = geo.count_pairs(None)

@@ -125,6 +125,9 @@ typedef struct {
      * after creation, without building the default schedule first. */
     int tile_shape;
     int tile_waves;
+    /* forward work schedule built at creation (see fspb_set_schedule):
+     * 0 = bricks longest-first, 1 = per-beam items */
+    int schedule;
 } fspb_options;
 
 /* fspb_options.flags: build exact radiological-depth tables (Siddon's
@@ -307,6 +310,7 @@ typedef struct {
     int dims[3];          /* brick voxels along x, y, z */
     int waves_per_block;
     float ms;             /* median forward time */
+    int per_beam;         /* forward schedule (fspb_set_schedule) */
 } fspb_tune_result;
 
 /* Number of brick shapes; writes dims[3*q .. 3*q+2] for q < max_shapes when
@@ -318,6 +322,25 @@ int fspb_tile_shapes(int* dims, int max_shapes);
  * that work on the device, as after fspb_create_geometry). */
 int fspb_set_tile(fspb_geometry* g, int shape, int waves_per_block, void* stream);
 int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block);
+
+/* Selects the forward's work schedule (Algorithm A2 kernel 5).
+ *   per_beam = 0  (default) a wavefront takes a whole brick and sums every
+ *                 beam's pairs; bricks run longest-first.
+ *   per_beam = 1  a wavefront takes a (brick, beam) item and writes that
+ *                 beam's partial dose to a plane [n_beams][n_vox] the handle
+ *                 owns (allocated on first use: 4 n_beams n_vox bytes); a
+ *                 second pass adds the planes in beam order.  The items are
+ *                 sorted by beam and by depth along the beam's central axis,
+ *                 and the sorted list is cut into 8 runs of about equal
+ *                 estimated work, one per XCD, so each XCD sweeps one beam's
+ *                 slabs and the depth-table lines its bricks share stay in
+ *                 its L2.  For a given brick shape the dose is bitwise that
+ *                 of per_beam = 0.
+ * Builds the schedule on the stream (calls on other streams then wait for it
+ * on the device).  FSPB_E_STATE with exact depth tables (FSPB_FLAG_SIDDON).
+ * fspb_autotune covers both schedules. */
+int fspb_set_schedule(fspb_geometry* g, int per_beam, void* stream);
+int fspb_get_schedule(const fspb_geometry* g, int* per_beam);
 
 /* Times every tile configuration on this plan (reps timed forwards each,
  * median) and keeps the fastest.  fluence: device [n_beamlets];

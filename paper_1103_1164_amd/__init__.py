@@ -80,7 +80,7 @@ class Geometry:
     """A plan's geometry on the GPU (owning handle of libfspb)."""
 
     def __init__(self, density: torch.Tensor, spacing, origin, beams, tables, options=None,
-                 stream=None, tile=None):
+                 stream=None, tile=None, schedule=None):
         L = load()
         if not (isinstance(density, torch.Tensor) and density.is_cuda):
             raise TypeError("density must be a CUDA (HIP) tensor")
@@ -99,9 +99,10 @@ class Geometry:
                                    float(b.cx), float(b.cy))
         tabs = _marshal_tables(tables)
         opt_p = None
-        if options is not None or tile is not None:
+        if options is not None or tile is not None or schedule is not None:
             # zero fields take the library's defaults; tile = (shape, waves
-            # per workgroup) builds that forward schedule at creation
+            # per workgroup) and schedule (0 bricks, 1 per-beam items) build
+            # that forward schedule at creation
             opt = _lib.fspb_options()
             opt.dc_enabled = 1
             if options is not None:
@@ -113,6 +114,8 @@ class Geometry:
                 opt.flags = _lib.FSPB_FLAG_SIDDON if getattr(o, "siddon", 0) else 0
             if tile is not None:
                 opt.tile_shape, opt.tile_waves = int(tile[0]), int(tile[1])
+            if schedule is not None:
+                opt.schedule = int(schedule)
             opt_p = C.byref(opt)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -125,14 +128,15 @@ class Geometry:
 
     @classmethod
     def from_plan(cls, plan, device="cuda", dc_enabled: Optional[int] = None, stream=None,
-                  tile=None):
+                  tile=None, schedule=None):
         dens = torch.as_tensor(np.ascontiguousarray(plan.density, dtype=np.float32), device=device)
         opts = plan.options
         if dc_enabled is not None:
             import copy
             opts = copy.copy(opts)
             opts.dc_enabled = int(dc_enabled)
-        return cls(dens, plan.spacing, plan.origin, plan.beams, plan.tables, opts, stream, tile)
+        return cls(dens, plan.spacing, plan.origin, plan.beams, plan.tables, opts, stream, tile,
+                   schedule)
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -296,6 +300,17 @@ class Geometry:
         check(load().fspb_get_tile(self._handle(), C.byref(s), C.byref(w)), "fspb_get_tile")
         return s.value, w.value
 
+    def set_schedule(self, per_beam: int, stream=None) -> None:
+        """Forward work schedule: 0 = bricks longest-first, 1 = per-beam items
+        (see fspb_set_schedule)."""
+        check(load().fspb_set_schedule(self._handle(), int(per_beam), _stream(stream)),
+              "fspb_set_schedule")
+
+    def get_schedule(self) -> int:
+        v = C.c_int()
+        check(load().fspb_get_schedule(self._handle(), C.byref(v)), "fspb_get_schedule")
+        return v.value
+
     def autotune(self, fluence: torch.Tensor, reps: int = 3, stream=None):
         """Times every tile configuration and keeps the fastest; returns the
         timings as a list of dicts."""
@@ -307,7 +322,7 @@ class Geometry:
                                    C.c_void_p(scratch.data_ptr()), int(reps), _stream(stream),
                                    res, 64, C.byref(n)), "fspb_autotune")
         return [dict(shape=r.shape, dims=tuple(r.dims), waves_per_block=r.waves_per_block,
-                     ms=r.ms) for r in res[:n.value]]
+                     per_beam=r.per_beam, ms=r.ms) for r in res[:n.value]]
 
     def set_dc(self, enabled: bool) -> None:
         check(load().fspb_set_dc(self._handle(), int(bool(enabled))), "fspb_set_dc")

@@ -51,7 +51,7 @@ class fspb_options(C.Structure):
     _fields_ = [("roi_radius", C.c_float), ("rho_surface", C.c_float),
                 ("smooth_sigma", C.c_float), ("rho_min", C.c_float), ("rho_max", C.c_float),
                 ("sample_step", C.c_float), ("dc_enabled", C.c_int), ("flags", C.c_int),
-                ("tile_shape", C.c_int), ("tile_waves", C.c_int)]
+                ("tile_shape", C.c_int), ("tile_waves", C.c_int), ("schedule", C.c_int)]
 
 
 class fspb_info(C.Structure):
@@ -74,7 +74,7 @@ class fspb_beamlet_info(C.Structure):
 
 class fspb_tune_result(C.Structure):
     _fields_ = [("shape", C.c_int), ("dims", C.c_int * 3), ("waves_per_block", C.c_int),
-                ("ms", C.c_float)]
+                ("ms", C.c_float), ("per_beam", C.c_int)]
 
 
 class fspb_adam(C.Structure):
@@ -121,6 +121,8 @@ SIGNATURES = {
     "fspb_update_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_wait_ready": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fspb_tile_shapes": (C.c_int, [C.POINTER(C.c_int), C.c_int]),
+    "fspb_set_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "fspb_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "fspb_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "fspb_get_tile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "fspb_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,

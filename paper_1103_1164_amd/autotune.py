@@ -1,8 +1,8 @@
 """Tile-configuration cache for the forward kernel.
 
 The measurement itself is ``fspb_autotune`` in the library (it times every
-brick shape x waves-per-workgroup configuration on the plan and keeps the
-fastest).  This driver stores the winner in a JSON file keyed by the GPU
+schedule x brick shape x waves-per-workgroup configuration on the plan and
+keeps the fastest).  This driver stores the winner in a JSON file keyed by the GPU
 architecture and a shape bucket of the plan (grid size, beam count, beamlet
 count, density-correction mode), so later plans of similar size reuse it
 without timing.
@@ -50,13 +50,16 @@ def tune(geo, fluence, cache: Path | str | None = DEFAULT_CACHE, reps: int = 3,
             table = {}
     if not force and key in table:
         e = table[key]
+        geo.set_schedule(e.get("per_beam", 0))
         geo.set_tile(e["shape"], e["waves_per_block"])
         return dict(e, cached=True, key=key)
     results = geo.autotune(fluence, reps=reps)
     shape, wpb = geo.get_tile()
-    best = next(r for r in results if r["shape"] == shape and r["waves_per_block"] == wpb)
-    entry = dict(shape=shape, waves_per_block=wpb, dims=list(best["dims"]), ms=best["ms"],
-                 all=[dict(r, dims=list(r["dims"])) for r in results])
+    pb = geo.get_schedule()
+    best = next(r for r in results if r["shape"] == shape and r["waves_per_block"] == wpb
+                and r["per_beam"] == pb)
+    entry = dict(shape=shape, waves_per_block=wpb, per_beam=pb, dims=list(best["dims"]),
+                 ms=best["ms"], all=[dict(r, dims=list(r["dims"])) for r in results])
     if path:
         table[key] = entry
         path.parent.mkdir(parents=True, exist_ok=True)

@@ -25,6 +25,7 @@
 #include "pair.h"
 
 #include <float.h>
+#include <stdint.h>
 
 #include <algorithm>
 
@@ -69,7 +70,8 @@ __device__ __forceinline__ int bricks_total(const PlanConst& P) {
 template <int DC, int MODE, int BX, int BY, int BZ, class WT>
 __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                            const float* fluence_, float* dose_, int* out_int_,
-                                           const WT& water, const float4* prm_ = nullptr) {
+                                           const WT& water, const float4* prm_ = nullptr,
+                                           int b_lo = 0, int b_hi = -1) {
     static_assert(MODE != kSurr || DC, "the surrogate replaces the density-corrected parameters");
     static_assert(BX * BY * BZ == kWave, "a brick holds one voxel per lane");
     // The table offsets are held in vector registers: an FMA may read only one
@@ -117,7 +119,8 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     int cnt = 0;
     const FSPB_GLOBAL float4* __restrict__ prm = as_global(prm_);
     const long n_vox = (long)P.nx * P.ny * P.nz;
-    for (int b = 0; b < P.n_beams; ++b) {
+    if (b_hi < 0) b_hi = P.n_beams;
+    for (int b = b_lo; b < b_hi; ++b) {
         const FSPB_CONST BeamDesc& B = beams[b];
         // surrogate row of this voxel and beam
         float4 s_ul = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s_w = s_ul;
@@ -264,6 +267,87 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
     else
         brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int,
                                          WaterGlobal{as_global(a.dtab), a.P.dt_n}, prm);
+}
+
+// The per-beam schedule (see kernels.h).  XCD x (workgroups q with
+// q mod 8 = x) runs the concatenation of its segments x, x + 8, x + 16, ...
+// of the sorted items; wave w of its m-th workgroup takes positions
+// (m wpb + w) ipw .. + ipw - 1 of that concatenation (consecutive items: the
+// same beam, neighbouring slabs).  For each, the item's beam alone is
+// evaluated for its brick and written to that beam's plane.
+template <int DC, int BX, int BY, int BZ, bool LW>
+__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward_split(
+    DoseArgs a, const int* __restrict__ order, const int* __restrict__ chunk, int ipw,
+    const float* __restrict__ fluence, float* __restrict__ planes, long stride) {
+    extern __shared__ float4 s_water[];
+    const int wpb = blockDim.x / kWave;
+    const int x = blockIdx.x & 7, m = blockIdx.x >> 3;
+    int total = 0;
+    for (int k = 0; k < kSplitSegments; ++k) total += chunk[x + 8 * k + 1] - chunk[x + 8 * k];
+    if (m * wpb * ipw >= total) return;   // the whole workgroup: nothing to stage
+    if (LW) {
+        const int n = a.P.dt_n;
+        const FSPB_GLOBAL float4* __restrict__ g = as_global(a.dtab);
+        for (int q = threadIdx.x; q < 3 * n; q += blockDim.x) {
+            const int plane = q / n, j = q - plane * n;
+            s_water[3 * j + plane] = g[q];
+        }
+        __syncthreads();
+    }
+    const int nb = bricks_total<BX, BY, BZ>(a.P);
+    const int v0 = (m * wpb + (int)(threadIdx.x / kWave)) * ipw;
+    const int v1 = min(v0 + ipw, total);
+    for (int v = v0; v < v1; ++v) {
+        // position v of the concatenation -> position in order[]
+        int j = v, pos = 0;
+        for (int k = 0; k < kSplitSegments; ++k) {
+            const int s0 = chunk[x + 8 * k], len = chunk[x + 8 * k + 1] - s0;
+            if (j < len) {
+                pos = s0 + j;
+                break;
+            }
+            j -= len;
+        }
+        const int item = uniform(order[pos]);
+        const int b = item / nb, brick = item - b * nb;
+        float* plane = planes + (long)b * stride;
+        if (LW)
+            brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, plane, nullptr,
+                                              WaterLds{(const FSPB_LDS float4*)s_water}, nullptr, b,
+                                              b + 1);
+        else
+            brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, plane, nullptr,
+                                              WaterGlobal{as_global(a.dtab), a.P.dt_n}, nullptr, b,
+                                              b + 1);
+    }
+}
+
+// dose[v] = sum over beams of planes[b][v] (plane b at planes + b stride,
+// stride a multiple of 4), added in beam order from 0.  Four voxels a thread
+// when dose is 16-byte aligned (the caller's buffer need not be).
+__global__ __launch_bounds__(256) void sum_planes(const float* __restrict__ planes, int n_beams,
+                                                  long n_vox, long stride, float* __restrict__ dose) {
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, step = (long)gridDim.x * blockDim.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(dose) & 15) == 0;
+    const long n4 = vec ? n_vox / 4 : 0;
+    const float4* __restrict__ p4 = reinterpret_cast<const float4*>(planes);
+    float4* __restrict__ d4 = reinterpret_cast<float4*>(dose);
+    for (long q = t0; q < n4; q += step) {
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int b = 0; b < n_beams; ++b) {
+            const float4 v = p4[(long)b * (stride / 4) + q];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+        d4[q] = acc;
+    }
+    for (long q = 4 * n4 + t0; q < n_vox; q += step) {
+        float acc = 0.0f;
+        for (int b = 0; b < n_beams; ++b) acc += planes[(long)b * stride + q];
+        dose[q] = acc;
+    }
 }
 
 // Many plans in one persistent launch: wave q walks its own static list of
@@ -739,6 +823,318 @@ __global__ __launch_bounds__(256) void brick_cost_kernel(DoseArgs a, int* __rest
         if (m_hi >= m_lo && n_hi >= n_lo) c += (m_hi - m_lo + 1) * (n_hi - n_lo + 1);
     }
     cost[brick] = c;
+}
+
+// ---------------------------------------------------------------------------
+// The per-beam schedule (kernels.h).  item_cost: one thread per (brick, beam)
+// item: the estimate of brick_cost_kernel for that beam alone, and the sort
+// key beam * nbins + depth bin of the brick centre along the beam's axis.
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void item_cost_kernel(DoseArgs a, int* __restrict__ cost,
+                                                        int* __restrict__ key) {
+    const PlanConst& P = a.P;
+    const int nb = bricks_total<BX, BY, BZ>(P);
+    const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= (long)nb * P.n_beams) return;
+    const int b = (int)(item / nb), brick = (int)(item - (long)b * nb);
+    const int nbx = bricks_x<BX, BY, BZ>(P), nby = bricks_y<BX, BY, BZ>(P);
+    const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
+    float cqx, cqy, cqz;
+    voxel_q(P, bx * BX, by * BY, bz * BZ, cqx, cqy, cqz);
+    const float hx = 0.5f * (BX - 1) * P.dx, hy = 0.5f * (BY - 1) * P.dy, hz = 0.5f * (BZ - 1) * P.dz;
+    cqx += hx;
+    cqy += hy;
+    cqz += hz;
+    const float rb = sqrtf(hx * hx + hy * hy + hz * hz);
+    const BeamDesc& B = a.beams[b];
+    const float vx = cqx - B.src[0], vy = cqy - B.src[1], vz = cqz - B.src[2];
+    const float z = vx * B.cax[0] + vy * B.cax[1] + vz * B.cax[2];
+    const float zn = fmaxf(z - rb, 1e-3f);
+    const float pa = (vx * B.ex[0] + vy * B.ex[1] + vz * B.ex[2]) * B.sad / z;
+    const float pb = (vx * B.ey[0] + vy * B.ey[1] + vz * B.ey[2]) * B.sad / z;
+    const float half = (rb * B.sad + B.pad_scale) / zn;
+    const int m_lo = max((int)ceilf((pa - half - B.a0) / B.wx), 0);
+    const int m_hi = min((int)floorf((pa + half - B.a0) / B.wx), B.nbx - 1);
+    const int n_lo = max((int)ceilf((pb - half - B.b0) / B.wy), 0);
+    const int n_hi = min((int)floorf((pb + half - B.b0) / B.wy), B.nby - 1);
+    int c = (m_hi >= m_lo && n_hi >= n_lo) ? (m_hi - m_lo + 1) * (n_hi - n_lo + 1) : 0;
+    // a brick in front of the entrance of the beamlet whose axis passes
+    // nearest to it (in the air before the body) evaluates next to no pairs
+    if (c > 0) {
+        const int m = min(max((int)floorf((pa - B.a0) / B.wx + 0.5f), 0), B.nbx - 1);
+        const int n = min(max((int)floorf((pb - B.b0) / B.wy + 0.5f), 0), B.nby - 1);
+        const BeamletDesc& d = a.bl[B.first + n * B.nbx + m];
+        const float tc = cqx * d.d[0] + cqy * d.d[1] + cqz * d.d[2] + d.c_t;
+        if (!d.hit || tc + rb < 0.0f) c = 0;
+    }
+    // an item with no candidate still writes its plane: one unit of work
+    cost[item] = 1 + c;
+    const int bin = min(max((int)((z - B.zlo) * B.zinv), 0), B.nbins - 1);
+    key[item] = b * B.nbins + bin;
+}
+
+// Counting sort of the items by key (ties in any order; the dose does not
+// depend on it) in three passes, then the cut of the sorted list into
+// segments of about equal work at key boundaries.  Pass 1: workgroup g counts
+// the keys (and sums the work) of its slice of items into hist[g][key];
+// pass 2 (one workgroup): per key, each slice's first slot in the sorted list
+// and the cuts; pass 3: workgroup g writes its slice's items to their slots.
+// Inside a slice, lane l of every wave walks block l of 64 contiguous blocks,
+// the waves interleaved within it, so that the lanes of one wave hold items
+// far apart (neighbouring items mostly share a key, and same-address LDS
+// atomics serialise).
+constexpr int kSortThreads = 512;
+
+__device__ __forceinline__ void slice_range(int n, int n_slices, int g, int& lo, int& hi) {
+    const int per = (n + n_slices - 1) / n_slices;
+    lo = min(g * per, n);
+    hi = min(lo + per, n);
+}
+
+template <class F>
+__device__ __forceinline__ void for_slice_items(int lo, int hi, F f) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    const int blk = (hi - lo + kWave - 1) / kWave;
+    for (int j = wid; j < blk; j += nw) {
+        const int q = lo + lane * blk + j;
+        if (q < hi) f(q);
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void items_hist(const int* __restrict__ cost,
+                                                          const int* __restrict__ key, int n,
+                                                          int* __restrict__ hist_n,
+                                                          unsigned int* __restrict__ hist_w) {
+    __shared__ int cnt[kSplitKeys];
+    __shared__ unsigned int csum[kSplitKeys];
+    for (int k = threadIdx.x; k < kSplitKeys; k += blockDim.x) {
+        cnt[k] = 0;
+        csum[k] = 0u;
+    }
+    __syncthreads();
+    int lo, hi;
+    slice_range(n, gridDim.x, blockIdx.x, lo, hi);
+    for_slice_items(lo, hi, [&](int q) {
+        const int k = key[q];
+        atomicAdd(&cnt[k], 1);
+        atomicAdd(&csum[k], (unsigned int)cost[q]);
+    });
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSplitKeys; k += blockDim.x) {
+        hist_n[(long)blockIdx.x * kSplitKeys + k] = cnt[k];
+        hist_w[(long)blockIdx.x * kSplitKeys + k] = csum[k];
+    }
+}
+
+// One workgroup of 1024 threads, four keys a thread.  hist_n[g][k] becomes
+// the first slot of slice g's items of key k.
+__global__ __launch_bounds__(1024) void items_scan(int* __restrict__ hist_n,
+                                                   const unsigned int* __restrict__ hist_w,
+                                                   int n_slices, int n, int cap,
+                                                   int* __restrict__ chunk) {
+    __shared__ int kstart[kSplitKeys];
+    __shared__ unsigned long long wpre[kSplitKeys];   // inclusive prefix of the work
+    __shared__ int s_wsum[16];
+    __shared__ unsigned long long s_wcost[16];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    // the thread's four keys of every slice, 16 slices of 16-byte loads at a
+    // time (issued together: the loads, not the adds, take the time)
+    const int k0 = 4 * tid;
+    const int4* __restrict__ hn4 = reinterpret_cast<const int4*>(hist_n);
+    const uint4* __restrict__ hw4 = reinterpret_cast<const uint4*>(hist_w);
+    constexpr int kB = 16;
+    int c[4] = {0, 0, 0, 0};
+    unsigned long long w[4] = {0, 0, 0, 0};
+    for (int g0 = 0; g0 < n_slices; g0 += kB) {
+        int4 vn[kB];
+        uint4 vw[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const long at = (long)min(g0 + q, n_slices - 1) * (kSplitKeys / 4) + tid;
+            vn[q] = hn4[at];
+            vw[q] = hw4[at];
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            if (g0 + q < n_slices) {
+                c[0] += vn[q].x;
+                c[1] += vn[q].y;
+                c[2] += vn[q].z;
+                c[3] += vn[q].w;
+                w[0] += vw[q].x;
+                w[1] += vw[q].y;
+                w[2] += vw[q].z;
+                w[3] += vw[q].w;
+            }
+        }
+    }
+    int local = 0;
+    unsigned long long lw = 0;
+    for (int u = 0; u < 4; ++u) {
+        local += c[u];
+        lw += w[u];
+    }
+    int incl = local;
+    unsigned long long wincl = lw;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        const unsigned long long wy = __shfl_up(wincl, o, kWave);
+        if (lane >= o) {
+            incl += y;
+            wincl += wy;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_wsum[wid] = incl;
+        s_wcost[wid] = wincl;
+    }
+    __syncthreads();
+    int off = 0;
+    unsigned long long woff = 0;
+    for (int q = 0; q < wid; ++q) {
+        off += s_wsum[q];
+        woff += s_wcost[q];
+    }
+    int ex = off + incl - local;
+    unsigned long long wex = woff + wincl - lw;
+    int run[4];
+    for (int u = 0; u < 4; ++u) {
+        kstart[k0 + u] = ex;
+        run[u] = ex;
+        ex += c[u];
+        wex += w[u];
+        wpre[k0 + u] = wex;
+    }
+    // each slice's first slot of these keys (the counts are read again)
+    int4* __restrict__ hn4w = reinterpret_cast<int4*>(hist_n);
+    for (int g0 = 0; g0 < n_slices; g0 += kB) {
+        int4 vn[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            vn[q] = hn4[(long)min(g0 + q, n_slices - 1) * (kSplitKeys / 4) + tid];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            if (g0 + q < n_slices) {
+                hn4w[(long)(g0 + q) * (kSplitKeys / 4) + tid] =
+                    make_int4(run[0], run[1], run[2], run[3]);
+                run[0] += vn[q].x;
+                run[1] += vn[q].y;
+                run[2] += vn[q].z;
+                run[3] += vn[q].w;
+            }
+        }
+    }
+    __syncthreads();
+    // cuts: segment g (of 8 kSplitSegments, run by XCD g mod 8) ends at the
+    // first key whose inclusive work reaches (g + 1) / (8 kSplitSegments) of
+    // the total, each segment at most `cap` items
+    constexpr int kSeg = 8 * kSplitSegments;
+    if (tid == 0) {
+        const unsigned long long total = wpre[kSplitKeys - 1];
+        chunk[0] = 0;
+        int prev = 0;
+        for (int g = 1; g < kSeg; ++g) {
+            const unsigned long long target = total * (unsigned long long)g / (unsigned long long)kSeg;
+            int lo = 0, hi = kSplitKeys - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (wpre[mid] >= target) hi = mid;
+                else lo = mid + 1;
+            }
+            int pos = lo + 1 < kSplitKeys ? kstart[lo + 1] : n;   // items of keys 0..lo
+            pos = min(pos, prev + cap);
+            pos = max(pos, n - (kSeg - g) * cap);
+            pos = max(pos, prev);
+            chunk[g] = pos;
+            prev = pos;
+        }
+        chunk[kSeg] = n;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void items_scatter(const int* __restrict__ key, int n,
+                                                             const int* __restrict__ hist_n,
+                                                             int* __restrict__ order) {
+    __shared__ int slot[kSplitKeys];
+    for (int k = threadIdx.x; k < kSplitKeys; k += blockDim.x)
+        slot[k] = hist_n[(long)blockIdx.x * kSplitKeys + k];
+    __syncthreads();
+    int lo, hi;
+    slice_range(n, gridDim.x, blockIdx.x, lo, hi);
+    for_slice_items(lo, hi, [&](int q) { order[atomicAdd(&slot[key[q]], 1)] = q; });
+}
+
+// Longest segment: 1.5 times an even share of the items.
+long split_seg_cap(long n_items) {
+    return (3 * n_items + 16 * kSplitSegments - 1) / (16 * kSplitSegments);
+}
+long split_run_cap(long n_items) { return kSplitSegments * split_seg_cap(n_items); }
+int split_sort_slices(long n_items) { return (int)std::min<long>(64, (n_items + 2047) / 2048); }
+
+void launch_split_schedule(const DoseArgs& a, TileCfg cfg, const SplitSched& sc, hipStream_t s) {
+    const long n = brick_count(a.P, cfg.shape) * a.P.n_beams;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (cfg.shape) {
+        case 0: hipLaunchKernelGGL((item_cost_kernel<4, 4, 4>), grid, block, 0, s, a, sc.cost, sc.key); break;
+        case 1: hipLaunchKernelGGL((item_cost_kernel<8, 4, 2>), grid, block, 0, s, a, sc.cost, sc.key); break;
+        case 2: hipLaunchKernelGGL((item_cost_kernel<4, 8, 2>), grid, block, 0, s, a, sc.cost, sc.key); break;
+        case 3: hipLaunchKernelGGL((item_cost_kernel<8, 2, 4>), grid, block, 0, s, a, sc.cost, sc.key); break;
+    }
+    const int slices = split_sort_slices(n);
+    hipLaunchKernelGGL(items_hist, dim3(slices), dim3(kSortThreads), 0, s, (const int*)sc.cost,
+                       (const int*)sc.key, (int)n, sc.hist_n, sc.hist_w);
+    hipLaunchKernelGGL(items_scan, dim3(1), dim3(1024), 0, s, sc.hist_n,
+                       (const unsigned int*)sc.hist_w, slices, (int)n, (int)split_seg_cap(n),
+                       sc.chunk);
+    hipLaunchKernelGGL(items_scatter, dim3(slices), dim3(kSortThreads), 0, s, (const int*)sc.key,
+                       (int)n, (const int*)sc.hist_n, sc.order);
+}
+
+template <int DC>
+static void launch_split_dc(const DoseArgs& a, TileCfg cfg, const SplitSched& sc,
+                            const float* fluence, float* planes, long stride, hipStream_t s) {
+    const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
+    const bool lds = cfg.waves_per_block == kLdsWaves;
+    const bool lw = lds && water_bytes <= (size_t)kLdsWaterMax;
+    const int wpb = lds && !lw ? 4 : cfg.waves_per_block;
+    const long n = brick_count(a.P, cfg.shape) * a.P.n_beams;
+    const int ipw = kSplitItemsPerWave;
+    const long per_xcd = (split_run_cap(n) + (long)wpb * ipw - 1) / ((long)wpb * ipw);
+    dim3 grid((unsigned)(8 * per_xcd)), block(kWave * wpb);
+#define FSPB_SHAPE(ID, X, Y, Z)                                                                   \
+    case ID:                                                                                      \
+        if (lw)                                                                                   \
+            hipLaunchKernelGGL((dose_forward_split<DC, X, Y, Z, true>), grid, block, water_bytes, \
+                               s, a, (const int*)sc.order, (const int*)sc.chunk, ipw, fluence,    \
+                               planes, stride);                                                   \
+        else                                                                                      \
+            hipLaunchKernelGGL((dose_forward_split<DC, X, Y, Z, false>), grid, block, 0, s, a,    \
+                               (const int*)sc.order, (const int*)sc.chunk, ipw, fluence, planes,  \
+                               stride);                                                           \
+        break;
+    switch (cfg.shape) {
+        FSPB_SHAPE(0, 4, 4, 4)
+        FSPB_SHAPE(1, 8, 4, 2)
+        FSPB_SHAPE(2, 4, 8, 2)
+        FSPB_SHAPE(3, 8, 2, 4)
+    }
+#undef FSPB_SHAPE
+}
+
+void launch_forward_split(const DoseArgs& a, bool dc, TileCfg cfg, const SplitSched& sc,
+                          const float* fluence, float* planes, float* dose, hipStream_t s) {
+    const long nv = (long)a.P.nx * a.P.ny * a.P.nz;
+    const long stride = (nv + 63) / 64 * 64;
+    if (dc && a.P.w2_one)
+        launch_split_dc<kDcOneDrift>(a, cfg, sc, fluence, planes, stride, s);
+    else if (dc)
+        launch_split_dc<kDcTwoDrift>(a, cfg, sc, fluence, planes, stride, s);
+    else
+        launch_split_dc<kPlain>(a, cfg, sc, fluence, planes, stride, s);
+    const int blocks = (int)std::min<long>((nv / 4 + 255) / 256 + 1, 8192);
+    hipLaunchKernelGGL(sum_planes, dim3(blocks), dim3(256), 0, s, (const float*)planes,
+                       a.P.n_beams, nv, stride, dose);
 }
 
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s) {

@@ -240,6 +240,10 @@ struct fspb_geometry {
     int* counts = nullptr;
     int* order = nullptr;      // bricks in decreasing order of estimated work
     int* cost = nullptr;       // estimated work per brick (candidate beamlets)
+    // per-beam schedule (allocated on first use): sorted items, XCD runs,
+    // their scratch, and the per-beam partial doses [n_beams][stride]
+    SplitSched split{};
+    float* planes = nullptr;
     float* tmp0 = nullptr;     // smoothing intermediates (alias the depth tables when they fit)
     float* tmp1 = nullptr;
     float* rho = nullptr;      // the handle's copy of the CT it was created from
@@ -364,6 +368,10 @@ int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_
             return fail(FSPB_E_ARG, "options must be finite and non-negative");
         if ((o->rho_min != 0 || o->rho_max != 0) && !(o->rho_min < o->rho_max))
             return fail(FSPB_E_ARG, "options: rho_min must be below rho_max");
+        if (o->schedule != 0 && o->schedule != 1)
+            return fail(FSPB_E_ARG, "options.schedule must be 0 or 1");
+        if (o->schedule == 1 && (o->flags & FSPB_FLAG_SIDDON))
+            return fail(FSPB_E_ARG, "options.schedule 1 is not available with exact depth tables");
         if (o->tile_waves != 0) {
             if (o->tile_shape < 0 || o->tile_shape >= kNumShapes)
                 return fail(FSPB_E_ARG, "options.tile_shape %d out of range", o->tile_shape);
@@ -511,6 +519,27 @@ static int build_order(fspb_geometry* G, hipStream_t s) {
     launch_order_bricks(G->cost, nb, G->order, s);
     HIP_TRY(hipGetLastError());
     G->h_cost_valid = false;
+    if (G->tile.per_beam) {
+        // buffers for the largest item count of any shape, allocated once
+        if (!G->planes) {
+            long max_items = 0;
+            for (int sh = 0; sh < kNumShapes; ++sh)
+                max_items = std::max(max_items, brick_count(G->P, sh) * G->P.n_beams);
+            const long nv = (long)G->P.nx * G->P.ny * G->P.nz;
+            const long stride = (nv + 63) / 64 * 64;
+            int rc;
+            if ((rc = G->alloc((void**)&G->split.order, sizeof(int) * max_items)) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.cost, sizeof(int) * max_items)) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.key, sizeof(int) * max_items)) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.chunk, sizeof(int) * (8 * kSplitSegments + 1))) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.hist_n, sizeof(int) * 64 * kSplitKeys)) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.hist_w, sizeof(unsigned int) * 64 * kSplitKeys)) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->planes, sizeof(float) * stride * G->P.n_beams)) != FSPB_OK)
+                return rc;
+        }
+        launch_split_schedule(G->args(), G->tile, G->split, s);
+        HIP_TRY(hipGetLastError());
+    }
     return FSPB_OK;
 }
 
@@ -705,6 +734,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     G->n_beams = n_beams;
     G->dc_created = G->dc_enabled = o.dc_enabled;
     G->siddon = (o.flags & FSPB_FLAG_SIDDON) ? 1 : 0;
+    G->tile.per_beam = o.schedule;
     if (o.tile_waves != 0) {
         G->tile.shape = o.tile_shape;
         G->tile.waves_per_block = o.tile_waves;
@@ -801,6 +831,21 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         double am = 0.5 * (B.nbx - 1) * B.wx + fabs((double)B.cx);
         double bm = 0.5 * (B.nby - 1) * B.wy + fabs((double)B.cy);
         Q.pad_scale = (float)(o.roi_radius * sqrt((double)B.sad * B.sad + am * am + bm * bm));
+        // depth range of the grid box along the central axis (per-beam schedule)
+        {
+            const double h[3] = {0.5 * nx * ct->dx, 0.5 * ny * ct->dy, 0.5 * nz * ct->dz};
+            double zlo = 1e300, zhi = -1e300;
+            for (int c = 0; c < 8; ++c) {
+                double z = 0.0;
+                for (int q = 0; q < 3; ++q)
+                    z += (((c >> q) & 1) ? h[q] : -h[q]) * cax[q] - (double)Q.src[q] * cax[q];
+                zlo = std::min(zlo, z);
+                zhi = std::max(zhi, z);
+            }
+            Q.nbins = std::max(1, kSplitKeys / n_beams);
+            Q.zlo = (float)zlo;
+            Q.zinv = (float)(Q.nbins / std::max(zhi - zlo, 1e-3));
+        }
         first += B.nbx * B.nby;
     }
 
@@ -961,6 +1006,9 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
 static void enqueue_forward(fspb_geometry* g, const float* fluence, float* dose, hipStream_t s) {
     if (g->siddon)
         launch_forward_siddon(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
+    else if (g->tile.per_beam)
+        launch_forward_split(g->args(), g->dc_enabled != 0, g->tile, g->split, fluence, g->planes,
+                             dose, s);
     else
         launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
 }
@@ -1297,6 +1345,32 @@ int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block) {
     return FSPB_OK;
 }
 
+int fspb_set_schedule(fspb_geometry* g, int per_beam, void* stream) {
+    if (!g) return fail(FSPB_E_ARG, "set_schedule: NULL handle");
+    if (per_beam != 0 && per_beam != 1) return fail(FSPB_E_ARG, "set_schedule: per_beam must be 0 or 1");
+    if (per_beam && g->siddon)
+        return fail(FSPB_E_STATE, "set_schedule: not available with exact depth tables");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = settle(g, s);
+    if (rc) return rc;
+    if (per_beam == g->tile.per_beam) return FSPB_OK;
+    g->tile.per_beam = per_beam;
+    if (!per_beam) return FSPB_OK;
+    if ((rc = build_order(g, s)) != FSPB_OK) return rc;
+    if (g->ready && !capturing(s)) {
+        HIP_TRY(hipEventRecord(g->ready, s));
+        g->ready_stream = s;
+        g->pending = true;
+    }
+    return FSPB_OK;
+}
+
+int fspb_get_schedule(const fspb_geometry* g, int* per_beam) {
+    if (!g || !per_beam) return fail(FSPB_E_ARG, "get_schedule: NULL argument");
+    *per_beam = g->tile.per_beam;
+    return FSPB_OK;
+}
+
 int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, int reps,
                   void* stream, fspb_tune_result* results, int max_results, int* n_results) {
     if (!g || !fluence || !dose_scratch || reps < 1)
@@ -1310,9 +1384,12 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     TileCfg best = g->tile;
     float best_ms = 1e30f;
     int n = 0, rc = FSPB_OK;
+    const int n_sched = g->siddon ? 1 : 2;
+    for (int pb = 0; pb < n_sched && rc == FSPB_OK; ++pb)
     for (int sh = 0; sh < kNumShapes && rc == FSPB_OK; ++sh) {
         for (int w = 0; w < 4 && rc == FSPB_OK; ++w) {
-            rc = fspb_set_tile(g, sh, wpbs[w], stream);
+            rc = fspb_set_schedule(g, pb, stream);
+            if (rc == FSPB_OK) rc = fspb_set_tile(g, sh, wpbs[w], stream);
             if (rc) break;
             std::vector<float> ms;
             enqueue_forward(g, fluence, dose_scratch, s);
@@ -1336,6 +1413,7 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
                 shape_dims(sh, results[n].dims);
                 results[n].waves_per_block = wpbs[w];
                 results[n].ms = med;
+                results[n].per_beam = pb;
             }
             ++n;
             if (med < best_ms) {
@@ -1348,6 +1426,7 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (n_results) *n_results = n;
+    if ((rc = fspb_set_schedule(g, best.per_beam, stream)) != FSPB_OK) return rc;
     return fspb_set_tile(g, best.shape, best.waves_per_block, stream);
 }
 

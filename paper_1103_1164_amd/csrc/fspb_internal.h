@@ -72,7 +72,10 @@ struct alignas(16) BeamDesc {
     float wx, wy;
     int nbx, nby;
     int first;         // index of the beam's first beamlet
-    int pad[3];
+    // depth bins of the per-beam schedule: a point at depth z = (q - src).cax
+    // along the central axis falls in bin (z - zlo) zinv, of nbins
+    float zlo, zinv;
+    int nbins;
 };
 static_assert(sizeof(BeamDesc) == 96, "BeamDesc layout");
 

@@ -76,6 +76,7 @@ constexpr int kLdsWaterMax = 65536;
 struct TileCfg {
     int shape = 0;            // 4 x 4 x 4 bricks
     int waves_per_block = kLdsWaves;
+    int per_beam = 0;         // 1: the per-beam schedule (below)
 };
 long brick_count(const PlanConst& P, int shape);
 void shape_dims(int shape, int d[3]);
@@ -98,6 +99,38 @@ void launch_count_bricks(const DoseArgs& a, TileCfg cfg, const int* order, const
 void launch_brick_cost(const DoseArgs& a, TileCfg cfg, int* cost, hipStream_t s);
 // order[0..n) = bricks by decreasing cost[brick] (one workgroup, no host round trip)
 void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s);
+
+// The per-beam schedule of the forward.  Work items are (brick, beam) pairs,
+// item = beam * n_bricks + brick.  They are sorted by beam, then by the
+// depth of the brick along the beam's central axis (BeamDesc.nbins bins, at
+// most kSplitKeys keys in all), and the sorted list is cut into
+// 8 kSplitSegments segments of about equal estimated work; XCD x (workgroup
+// q runs on XCD q mod 8) runs segments x, x + 8, ...: within a segment it
+// sweeps one beam's slabs front to back, so the depth-table lines of its
+// concurrent bricks stay in its L2, and its segments spread over the beams
+// and depths so that the XCDs' shares of work match.  Each item writes its
+// beam's partial dose to planes[beam][voxel]; sum_planes adds the planes in
+// beam order, which is the order the brick-major forward adds its beams in,
+// so both give bitwise the same dose for one brick shape.
+constexpr int kSplitKeys = 4096;
+constexpr int kSplitItemsPerWave = 1;   // consecutive items a wavefront takes
+constexpr int kSplitSegments = 2;       // segments per XCD
+struct SplitSched {
+    int* order;     // [n_items] sorted items
+    int* chunk;     // [8 kSplitSegments + 1] segment boundaries in order[]
+    int* cost;      // [n_items] scratch: estimated work per item
+    int* key;       // [n_items] scratch: sort key per item
+    int* hist_n;    // [slices][kSplitKeys] scratch: items per key and slice
+    unsigned int* hist_w;   // [slices][kSplitKeys] scratch: work per key and slice
+};
+// Longest segment, and the most items an XCD runs (the launch covers it).
+long split_seg_cap(long n_items);
+long split_run_cap(long n_items);
+// Slices of the item list the sort's histograms are taken over (at most 64).
+int split_sort_slices(long n_items);
+void launch_split_schedule(const DoseArgs& a, TileCfg cfg, const SplitSched& sc, hipStream_t s);
+void launch_forward_split(const DoseArgs& a, bool dc, TileCfg cfg, const SplitSched& sc,
+                          const float* fluence, float* planes, float* dose, hipStream_t s);
 // Per-plan fluence and dose pointers of a batch, passed by value as a kernel
 // argument (so a captured graph keeps them).
 constexpr int kMaxBatchPlans = 64;

@@ -32,9 +32,9 @@ def abi_oracle(plan, **kw):
     return oracle.Oracle(S.abi_rounded(plan), **kw)
 
 
-def geometry(plan, dc=None, tile=None):
+def geometry(plan, dc=None, tile=None, schedule=None):
     from paper_1103_1164_amd import Geometry
-    return Geometry.from_plan(plan, device="cuda", dc_enabled=dc, tile=tile)
+    return Geometry.from_plan(plan, device="cuda", dc_enabled=dc, tile=tile, schedule=schedule)
 
 
 def gpu_dose(geo, fluence):

@@ -196,13 +196,17 @@ def test_autotune_and_cache(tmp_path):
     f = torch.as_tensor(plan.fluence, device="cuda")
     cache = tmp_path / "tune.json"
     r1 = tune(geo, f, cache=cache, reps=2)
-    assert not r1["cached"] and len(r1["all"]) == 4 * len(geo.tile_shapes())
+    # two schedules x shapes x four workgroup sizes
+    assert not r1["cached"] and len(r1["all"]) == 2 * 4 * len(geo.tile_shapes())
+    assert {r["per_beam"] for r in r1["all"]} == {0, 1}
     assert geo.get_tile() == (r1["shape"], r1["waves_per_block"])
+    assert geo.get_schedule() == r1["per_beam"]
     got = gpu_dose(geo, plan.fluence)
     assert np.max(np.abs(got - ref)) <= SHAPE_TOL * float(np.max(np.abs(ref)))
     geo2 = geometry(plan, 1)
     r2 = tune(geo2, f, cache=cache)
     assert r2["cached"] and geo2.get_tile() == geo.get_tile()
+    assert geo2.get_schedule() == geo.get_schedule()
     assert r1["key"] in json.loads(cache.read_text())
 
 
