@@ -12,7 +12,10 @@ per second of step time.  The JSON line also carries the forward-only, plain
 (no density correction) and adjoint rates, the host<->device transfer times,
 the roofline of the dominant kernel (the forward dose kernel, measured with
 HIP events on the stream it runs on) and the FP64 CPU oracle timed on a
-sample of the same workload.
+sample of the same workload (with the host's CPU model and core count).
+Beside it: config 3 at full size (forward and adjoint, exact pair counts,
+rooflines), the paper-shaped plans with the per-beam schedule, the 32-plan
+batch, the surrogate, the exact-path comparison and the commissioning fit.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -45,12 +48,21 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published, packed F
 # default 4x4x4 in its timing); fixed here, and given at creation, so that
 # the counter runs and the timed steps use the same kernel.
 C2_TILE = (3, 8)
+# Forward tile of the config-3 workload: 4x4x4 bricks, one wave per workgroup,
+# bricks longest-first (the fastest configuration of both schedules measured
+# on this plan: 8.4 ms against 9.5 ms for the per-beam schedule's best).
+C3_TILE = (0, 1)
+C3_SCHEDULE = 0
+# Forward tile of the paper-shaped plans' per-beam schedule: 4x4x4 bricks, one
+# wave per workgroup (the per-beam schedule's best or within 2% of it on both).
+PAPER_TILE = (0, 1)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
 FORWARD_SOURCES = ("dose.hip", "pair.h", "kernels.h", "fspb_internal.h")
 PMC_SUMMARY = ROOT / "profiles" / "dose_forward_c2_pmc.md"
+PMC_SUMMARY_C3 = ROOT / "profiles" / "dose_forward_c3_pmc.md"
 
 
 def _code_only(text: str) -> str:
@@ -74,13 +86,14 @@ def forward_source_hash() -> str:
     return h.hexdigest()
 
 
-def pmc_record(tile) -> dict:
+def pmc_record(tile, summary=None) -> dict:
     """The committed PMC summary's record, if it was taken on these sources
     with this tile configuration; else an empty dict."""
-    if not PMC_SUMMARY.exists():
+    summary = PMC_SUMMARY if summary is None else summary
+    if not summary.exists():
         return {}
     rec = {}
-    for line in PMC_SUMMARY.read_text().splitlines():
+    for line in summary.read_text().splitlines():
         if line.startswith("    ") and ":" in line:
             k, v = line.strip().split(":", 1)
             rec[k.strip()] = v.strip()
@@ -110,6 +123,8 @@ def parse():
                     help="skip the exact (Siddon) depth-table comparison")
     ap.add_argument("--no-paper-cases", action="store_true",
                     help="skip the paper-shaped head-and-neck and lung plans")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the config-3 plan (forward and adjoint at full size)")
     ap.add_argument("--surrogate-plans", type=int, default=200,
                     help="training heads for the surrogate (config 5 uses 200)")
     ap.add_argument("--forward-only", type=int, default=0,
@@ -303,6 +318,9 @@ def main():
     paper = None
     if not a.no_paper_cases:
         paper = paper_cases(time_loop)
+    c3 = None
+    if not a.no_c3:
+        c3 = c3_case(time_loop)
     surr = None
     if not a.no_surrogate:
         surr = surrogate_c5(plan, geo, flu, pairs_fwd, a.surrogate_plans, time_loop)
@@ -358,6 +376,7 @@ def main():
         "siddon_c2": sid,
         "commissioning": comm,
         "paper_cases": paper,
+        "c3": c3,
         "paper_context": "Tesla C1060, real H&N/lung IMRT plans (Table 4): median T_gpu "
                          "0.37 s DC (0.33 s plain), T_tr 0.20 s; different hardware and workload",
     }
@@ -373,8 +392,15 @@ def _opts(o, dc):
 
 def commission_fit():
     """The commissioning fitter on the water-tank and slab measurement set:
-    recover a perturbed machine's 8 table parameters from its doses (made by
-    the library with that machine's tables), starting from the nominal one."""
+    recover a perturbed machine's 8 table parameters from "measurements"
+    made by another engine -- the library with exact (Siddon) radiological
+    paths through voxel-constant density and that machine's tables -- while
+    the fit models them with the uniform samples of Section 2.2, starting
+    from the nominal machine.  The parameter error is the model mismatch
+    (the fit to FP64 oracle measurements of the fitted model itself is a GPU
+    test)."""
+    import copy
+
     import numpy as np
     import torch
 
@@ -386,17 +412,22 @@ def commission_fit():
     plans = S.commissioning_plans()
     refs = []
     for p in plans:
+        o = copy.copy(p.options)
+        o.siddon = 1
         g = Geometry(torch.as_tensor(p.density, device="cuda"), p.spacing, p.origin, p.beams,
-                     S.make_tables_coeffs(truth), p.options)
+                     S.make_tables_coeffs(truth), o)
         refs.append(g.forward(torch.as_tensor(p.fluence, device="cuda")).clone())
         g.close()
     res = fit_tables(plans, refs, S.make_tables_coeffs, np.ones(8))
     err = np.abs(res["c"] - truth) / truth
     return {"parameters": 8, "measurement_voxels": int(sum(p.n_vox for p in plans)),
+            "measurements": "library with exact (Siddon) paths and the perturbed tables",
+            "model": "uniform samples (Section 2.2)",
             "iterations": len(res["cost"]) - 1, "plan_evaluations": res["evaluations"],
             "seconds": round(res["seconds"], 3),
             "ms_per_evaluation": round(1e3 * res["seconds"] / res["evaluations"], 3),
             "max_rel_param_error": float(err.max()),
+            "rel_param_error": [float(e) for e in err],
             "cost_first": res["cost"][0], "cost_last": res["cost"][-1]}
 
 
@@ -449,8 +480,9 @@ def siddon_c2(plan, dens, flu, time_loop, n=10):
 def paper_cases(time_loop, n=10):
     """Plans shaped like the paper's largest head-and-neck (H5) and a lung
     case (L2), Table 1 scales: per-plan time (geometry + DC forward, the
-    paper's T_gpu) and forward rates, with the paper's own times (Tesla
-    C1060, real plans) beside them as context."""
+    paper's T_gpu) and forward rates with the per-beam schedule (the faster
+    one on these plans), the brick-major forward beside it, and the paper's
+    own times (Tesla C1060, real plans) as context."""
     import numpy as np
     import torch
 
@@ -465,9 +497,9 @@ def paper_cases(time_loop, n=10):
         flu = torch.as_tensor(plan.fluence, device="cuda")
         dose = torch.empty(plan.shape, device="cuda")
 
-        def make(dc=1):
+        def make(dc=1, schedule=1, tile=PAPER_TILE):
             return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables,
-                            _opts(plan.options, dc))
+                            _opts(plan.options, dc), tile=tile, schedule=schedule)
 
         for _ in range(2):
             g = make()
@@ -482,26 +514,100 @@ def paper_cases(time_loop, n=10):
             g.close()
             torch.cuda.synchronize()     # the plan's latency: geometry + forward done
             per.append((time.perf_counter() - t0) * 1e3)
-        step_ms = float(np.mean(per))
         geo = make()
         pairs = geo.count_pairs(flu)
         fwd_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
         geo.set_dc(False)
         plain_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
         geo.close()
+        # the brick-major schedule with the library's default tile
+        geo = make(schedule=0, tile=None)
+        brick_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
+        geo.close()
         dc_s, plain_s = paper_tgpu[plan.name]
         out[plan.name] = {
             "voxels": plan.n_vox, "beamlets": plan.n_beamlets, "beams": len(plan.beams),
             "spacing_cm": list(plan.spacing), "beamlet_cm": [plan.beams[0].wx, plan.beams[0].wy],
-            "pairs_forward": int(pairs), "ms_per_plan": round(step_ms, 4),
+            "pairs_forward": int(pairs), "schedule": "per-beam", "tile": list(PAPER_TILE),
+            "ms_per_plan": round(float(np.mean(per)), 4),
             "ms_per_plan_median": round(float(np.median(per)), 4),
             "ms_per_plan_max": round(float(np.max(per)), 4),
             "forward_ms": round(fwd_ms, 4), "plain_forward_ms": round(plain_ms, 4),
             "forward_evals_per_s": pairs / (fwd_ms * 1e-3),
+            "brick_major_forward_ms": round(brick_ms, 4),
             "paper_tgpu_s_dc": dc_s, "paper_tgpu_s_plain": plain_s,
             "note": "paper times: Tesla C1060 on the real plan of that name (Table 4); "
                     "this plan only matches its shape (Table 1)",
         }
+    return out
+
+
+def c3_case(time_loop, n=5):
+    """Config 3 at full size: the lung-like 256x256x128 phantom at 2 mm with
+    nine beams of 30x30 beamlets.  DC forward and adjoint (every beamlet)
+    with exact pair counts, one plan's latency, and the roofline of both
+    kernels (HIP events on the stream they run on)."""
+    import numpy as np
+    import torch
+
+    import fspb_synth as S
+    from paper_1103_1164_amd import Geometry
+
+    plan = S.plan_c3()
+    dens = torch.as_tensor(plan.density, device="cuda")
+    flu = torch.as_tensor(plan.fluence, device="cuda")
+    dose = torch.empty(plan.shape, device="cuda")
+
+    def make():
+        return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables, plan.options,
+                        tile=C3_TILE, schedule=C3_SCHEDULE)
+
+    g = make()
+    g.forward(flu, out=dose)
+    g.close()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        g = make()
+        g.forward(flu, out=dose)
+        g.close()
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) * 1e3)
+    geo = make()
+    pairs_fwd = geo.count_pairs(flu)
+    pairs_all = geo.count_pairs(None)
+    fwd_ms = time_loop(lambda: geo.forward(flu, out=dose), n)
+    w, _ = S.c3_objective(3, plan.n_vox)
+    wt = torch.as_tensor(w, device="cuda")
+    grad = torch.empty(plan.n_beamlets, device="cuda")
+    adj_ms = time_loop(lambda: geo.adjoint(wt, out=grad), n)
+    fpp = FLOPS_PER_PAIR_DC[geo.info()["drift_tables"]]
+    pmc = pmc_record(geo.get_tile(), PMC_SUMMARY_C3)
+
+    def roof(pairs, ms, kernel, traffic=None):
+        tf = pairs * fpp / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": kernel, "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                "frac_nonpacked": round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                "flops_per_pair": fpp, "pairs_per_launch": int(pairs), "launch_ms": round(ms, 4),
+                "traffic": traffic}
+
+    out = {
+        "workload": "c3 lung-like phantom 256x256x128 at 2 mm, 9 beams x 30x30 beamlets of 5 mm, "
+                    "lognormal fluence; DC-FSPB",
+        "voxels": plan.n_vox, "beamlets": plan.n_beamlets,
+        "pairs_forward": int(pairs_fwd), "pairs_all_beamlets": int(pairs_all),
+        "dense_pairs": plan.n_vox * plan.n_beamlets,
+        "tile": list(C3_TILE), "schedule": "brick-major" if C3_SCHEDULE == 0 else "per-beam",
+        "ms_per_plan_median": round(float(np.median(per)), 4),
+        "forward_ms": round(fwd_ms, 4), "forward_evals_per_s": pairs_fwd / (fwd_ms * 1e-3),
+        "adjoint_ms": round(adj_ms, 4), "adjoint_evals_per_s": pairs_all / (adj_ms * 1e-3),
+        "roofline_forward": roof(pairs_fwd, fwd_ms, "dose_forward<DC>",
+                                 int(pmc["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in pmc else None),
+        "roofline_adjoint": roof(pairs_all, adj_ms, "dose_adjoint<DC>"),
+    }
+    geo.close()
     return out
 
 
@@ -633,10 +739,30 @@ def cpu_baseline(plan, n_sample):
     dt = time.perf_counter() - t0
     pairs = int(pc.sum())
     res = {"value": pairs / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "host": _host_cpu(),
            "sample": f"{n_sample} voxels of the same plan drawn at random with replacement "
                      f"(all beamlets, DC), {pairs} evaluated pairs in {dt:.2f} s, FP64, OpenMP"}
     res["single_core"] = _oracle_one_core(plan, vox[: max(1, n_sample // 64)])
     return res
+
+
+def _host_cpu() -> dict:
+    """The host's CPU: model name, logical CPUs, and those this process may
+    run on (a job's share of the host)."""
+    model = None
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"model": model, "nproc": os.cpu_count(), "usable": allowed,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def _oracle_one_core(plan, vox):
