@@ -214,14 +214,25 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
  * the handle (see fspb_set_dc). */
 int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stream);
 
-/* Adjoint of fspb_forward: grad_i = sum_r voxel_weight(r) D_i(r) for every
- * beamlet, including those with zero fluence.  For L = sum w (D - D0)^2 pass
- * voxel_weight = 2 w (D - D0) to get dL/df.  Deterministic (fixed reduction
- * order, no atomics).
+/* Adjoint of fspb_forward (Eq. 1 transposed): grad_i = sum_r voxel_weight(r)
+ * D_i(r) for every beamlet, including those with zero fluence.  For
+ * L = sum w (D - D0)^2 pass voxel_weight = 2 w (D - D0) to get dL/df.
+ * Deterministic: each beamlet's sum is taken over fixed parts of the grid and
+ * the parts are added in a fixed order, whatever the scheduling.
  *   voxel_weight  device [n_vox].
  *   grad          device [n_beamlets], overwritten.
- * Asynchronous on stream. */
+ * Asynchronous on stream.  Uses per-handle scratch memory: adjoint and
+ * beamlet_pair_counts calls on one handle that overlap in time (on different
+ * streams without ordering) race.  FSPB_E_STATE with exact depth tables. */
 int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream);
+
+/* Number of voxels paired with each beamlet (the pairs of Algorithm A1 step
+ * 8: inside the ROI cylinder, depth t >= 0, beamlets that enter the body),
+ * found by the beamlet-major traversal fspb_adjoint uses.  Their sum equals
+ * fspb_count_pairs' total with fluence NULL.
+ *   counts  device int [n_beamlets], overwritten.
+ * Asynchronous on stream; the same per-handle scratch as fspb_adjoint. */
+int fspb_beamlet_pair_counts(fspb_geometry* g, int* counts, void* stream);
 
 /* Number of evaluated pairs: voxel-beamlet pairs inside the ROI with t >= 0
  * for beamlets that enter the body; with fluence non-NULL, only beamlets with

@@ -99,6 +99,8 @@ def lib():
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_pair_counts.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long),
                                       C.POINTER(C.c_int)]
+        L.orc_beamlet_pair_counts.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int),
+                                              C.POINTER(C.c_longlong)]
         L.orc_trace_siddon.restype = C.c_int
         L.orc_trace_siddon.argtypes = [C.c_void_p, C.c_int] + [C.POINTER(C.c_double)] * 5 + [C.c_int]
         L.orc_density_at.restype = C.c_double
@@ -256,6 +258,17 @@ class Oracle:
         lib().orc_adjoint(self.ctx, _ptr(w, C.c_float), n, lp, _ptr(g, C.c_double),
                           _ptr(a, C.c_double))
         return g, a
+
+    def beamlet_pair_counts(self, beamlets=None) -> np.ndarray:
+        """Voxels paired with each listed beamlet (all when None)."""
+        if beamlets is None:
+            n, lp = self.n_beamlets, None
+        else:
+            beamlets = np.ascontiguousarray(np.atleast_1d(beamlets), dtype=np.int32)
+            n, lp = beamlets.size, _ptr(beamlets, C.c_int)
+        out = np.zeros(n, dtype=np.int64)
+        lib().orc_beamlet_pair_counts(self.ctx, n, lp, _ptr(out, C.c_longlong))
+        return out
 
     def pair_counts(self, vox=None) -> np.ndarray:
         if vox is None:

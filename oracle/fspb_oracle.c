@@ -797,6 +797,23 @@ void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts) {
     }
 }
 
+/* Per beamlet: the number of voxels it is paired with (Algorithm A1 step 8,
+ * the same pair test as orc_pair_counts, summed over voxels instead). */
+void orc_beamlet_pair_counts(const orc_ctx* c, int n, const int* beamlets, long long* counts) {
+    const long nv = (long)c->g.nx * c->g.ny * c->g.nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < n; ++q) {
+        const int i = beamlets ? beamlets[q] : q;
+        long long cnt = 0;
+        for (long v = 0; v < nv; ++v) {
+            int fl;
+            pair_value(c, v, i, 1.0, 1.0, &fl, NULL, NULL);
+            if (fl & 1) ++cnt;
+        }
+        counts[q] = cnt;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Learned-surrogate support.  The surrogate is an extension beside the
  * method (not in the paper): for a (voxel, beam) row it predicts the six

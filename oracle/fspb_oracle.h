@@ -143,6 +143,8 @@ void orc_adjoint(const orc_ctx* c, const float* w, int n, const int* list,
 /* Number of counted pairs (all beamlets, regardless of fluence) per listed
  * voxel; vox may be NULL for the whole grid. */
 void orc_pair_counts(const orc_ctx* c, long n, const long* vox, int* counts);
+/* Voxels paired with each listed beamlet (all when beamlets is NULL). */
+void orc_beamlet_pair_counts(const orc_ctx* c, int n, const int* beamlets, long long* counts);
 
 
 /* ---- Learned-surrogate support (an extension beside the method, not in

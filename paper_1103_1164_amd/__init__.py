@@ -178,6 +178,17 @@ class Geometry:
                                   C.c_void_p(out.data_ptr()), _stream(stream)), "fspb_adjoint")
         return out
 
+    def beamlet_pair_counts(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Voxels paired with each beamlet (in ROI, t >= 0), device int32
+        [n_beamlets], from the adjoint's beamlet-major traversal."""
+        if out is None:
+            out = torch.empty(self.n_beamlets, dtype=torch.int32, device=self.device)
+        if out.dtype != torch.int32 or out.numel() != self.n_beamlets or not out.is_cuda:
+            raise ValueError("out must be a device int32 tensor of n_beamlets values")
+        check(load().fspb_beamlet_pair_counts(self._handle(), C.c_void_p(out.data_ptr()),
+                                              _stream(stream)), "fspb_beamlet_pair_counts")
+        return out
+
     def count_pairs(self, fluence: Optional[torch.Tensor] = None, per_voxel: bool = False,
                     stream=None):
         """Evaluated pairs (in ROI, t >= 0); with fluence, only f_i != 0."""

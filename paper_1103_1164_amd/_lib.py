@@ -108,6 +108,7 @@ SIGNATURES = {
                                        C.c_void_p, C.POINTER(C.c_void_p)]),
     "fspb_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_beamlet_pair_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_count_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_ulonglong), C.c_void_p]),
     "fspb_count_pairs_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

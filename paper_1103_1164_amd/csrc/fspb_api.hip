@@ -240,6 +240,8 @@ struct fspb_geometry {
     int* counts = nullptr;
     int* order = nullptr;      // bricks in decreasing order of estimated work
     int* cost = nullptr;       // estimated work per brick (candidate beamlets)
+    float* adj_part = nullptr; // the adjoint's per-(slab, beamlet) partial sums
+    int* adj_queue = nullptr;  // the adjoint's per-XCD unit counters
     // per-beam schedule (allocated on first use): sorted items, XCD runs,
     // their scratch, and the per-beam partial doses [n_beams][stride]
     SplitSched split{};
@@ -262,7 +264,7 @@ struct fspb_geometry {
     bool h_cost_valid = false;
     TraceGrid tg{};
     TraceParams tp{};
-    hipDeviceProp_t prop{};
+    int n_cu = 0;              // the device's compute units
     unsigned long long* partial = nullptr;
     unsigned long long* total = nullptr;
     // host copies
@@ -891,6 +893,8 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
     ALLOC(G->order, sizeof(int) * max_bricks);
     ALLOC(G->cost, sizeof(int) * max_bricks);
+    ALLOC(G->adj_part, sizeof(float) * (size_t)adjoint_slabs(G->P) * nbl);
+    ALLOC(G->adj_queue, sizeof(int) * 8 * kAdjQueueInts);
     if (o.dc_enabled) {
         // one block: the 16-byte plane, then the 8-byte plane
         ALLOC(G->tTW, (sizeof(float4) + sizeof(float2)) * (size_t)nbl * G->k_stride);
@@ -990,6 +994,10 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     fspb_geometry* G = new (std::nothrow) fspb_geometry();
     if (!G) return fail(FSPB_E_NOMEM, "host allocation failed");
     G->device = dev;
+    if (hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete G;
+        return fail(FSPB_E_HIP, "hipDeviceGetAttribute failed");
+    }
     rc = create_impl(ct, n_beams, beams, tables, opts, (hipStream_t)stream, G);
     if (rc) {
         (void)hipStreamSynchronize((hipStream_t)stream);
@@ -1027,8 +1035,18 @@ int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void*
     if (g->siddon) return fail(FSPB_E_STATE, "adjoint: not available with exact depth tables");
     int rc = settle(g, (hipStream_t)stream);
     if (rc) return rc;
-    launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad,
-                   (hipStream_t)stream);
+    launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad, g->adj_part,
+                   g->adj_queue, g->n_cu, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FSPB_OK;
+}
+
+int fspb_beamlet_pair_counts(fspb_geometry* g, int* counts, void* stream) {
+    if (!g || !counts) return fail(FSPB_E_ARG, "beamlet_pair_counts: NULL argument");
+    int rc = settle(g, (hipStream_t)stream);
+    if (rc) return rc;
+    launch_adjoint_count(g->args(), g->n_beamlets, counts, g->adj_part, g->adj_queue,
+                         g->n_cu, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }

@@ -92,6 +92,48 @@ def test_c1_pair_counts_per_voxel(oracle_mod):
     counts_g = counts_g.cpu().numpy()
     assert np.array_equal(counts_g, counts_o)
     assert tot == int(counts_o.sum())
+    # per beamlet, from the adjoint's traversal: every beamlet exactly
+    bpc = geo.beamlet_pair_counts().cpu().numpy().astype(np.int64)
+    assert np.array_equal(bpc, orc.beamlet_pair_counts())
+
+
+def _tight_plans():
+    """Small ROI radii (0.3 to 1.2 cm) on grids with unequal voxel sizes,
+    couch rotations and beams along grid axes: the row intervals the
+    adjoint scans are then short and their ends decide many pairs."""
+    rng = np.random.default_rng(31)
+    out = []
+    for k in range(6):
+        n = tuple(int(v) for v in rng.integers(10, 40, 3))
+        sp = tuple(float(v) for v in rng.uniform(0.1, 0.5, 3))
+        rho = rng.uniform(0.05, 2.2, size=(n[2], n[1], n[0])).astype(np.float32)
+        beams = [S.Beam(gantry=float(rng.uniform(0, 6.3)),
+                        couch=float(rng.uniform(-1.5, 1.5)) if k % 2 else 0.0,
+                        nbx=int(rng.integers(2, 7)), nby=int(rng.integers(2, 7)),
+                        wx=float(rng.uniform(0.1, 0.6)), wy=float(rng.uniform(0.1, 0.6)))
+                 for _ in range(2)]
+        beams.append(S.Beam(gantry=(math.pi / 2) * (k % 4), nbx=3, nby=2))
+        opts = S.Options(roi_radius=float(rng.uniform(0.3, 1.2)))
+        out.append(S.plan_small(n=n, spacing=sp, density=rho, beams=beams, options=opts,
+                                seed=k, name=f"tight{k}"))
+    return out
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_beamlet_pair_counts_tight_roi(oracle_mod, k):
+    plan = _tight_plans()[k]
+    orc = abi_oracle(plan)
+    geo = geometry(plan, 1)
+    bpc = geo.beamlet_pair_counts().cpu().numpy().astype(np.int64)
+    assert np.array_equal(bpc, orc.beamlet_pair_counts())
+    assert int(bpc.sum()) == geo.count_pairs(None)
+    # and the adjoint on the same plan, every beamlet
+    w = np.random.default_rng(k).uniform(0, 1, plan.n_vox).astype(np.float32)
+    g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
+    g_o, amb = orc.adjoint(w)
+    amb_stats(amb, np.abs(g_o).max(), f"tight{k} adjoint")
+    assert np.all(np.abs(g - g_o) <= REL_TOL * np.abs(g_o).max())
+    geo.close()
 
 
 # ---------------------------------------------------------------------------
@@ -189,6 +231,14 @@ def test_full_size_forward_sampled(oracle_mod, cfg):
     tot, cnt = geo.count_pairs(torch.as_tensor(plan.fluence, device="cuda"), per_voxel=True)
     cnt = cnt.cpu().numpy().reshape(-1)[vox]
     assert np.array_equal(cnt, pc)
+    # the adjoint's beamlet-major traversal visits the same pairs: its
+    # per-beamlet counts add up to the forward's total, and sampled beamlets
+    # match the oracle's count exactly
+    bpc = geo.beamlet_pair_counts().cpu().numpy().astype(np.int64)
+    assert int(bpc.sum()) == geo.count_pairs(None)
+    pick = np.random.default_rng(8).choice(plan.n_beamlets, 6, replace=False)
+    say(f"{cfg}: oracle pair counts of beamlets {pick.tolist()}")
+    assert np.array_equal(bpc[pick], orc.beamlet_pair_counts(pick))
 
 
 def test_c3_adjoint_sampled_and_fd(oracle_mod):
@@ -286,7 +336,7 @@ def test_adjoint_full_small(oracle_mod, dc):
 def test_adjoint_long_rows_span_several_windows(oracle_mod):
     """A beam along the x rows of a long grid: the 512 rows of a chunk hold
     about 150,000 voxels, more than one window of the adjoint's block table
-    (65,536), so several windows per chunk are walked."""
+    (16,384), so several windows per chunk are walked."""
     n = (300, 40, 13)
     rng = np.random.default_rng(21)
     rho = rng.uniform(0.6, 1.4, size=(n[2], n[1], n[0])).astype(np.float32)
@@ -301,6 +351,8 @@ def test_adjoint_long_rows_span_several_windows(oracle_mod):
     geo = geometry(plan, 1)
     g = geo.adjoint(torch.as_tensor(w, device="cuda")).cpu().numpy().astype(np.float64)
     say(f"long rows adjoint: max |err|/max g = {np.abs(g - g_o).max() / np.abs(g_o).max():.2e}")
+    bpc = geo.beamlet_pair_counts().cpu().numpy().astype(np.int64)
+    assert np.array_equal(bpc, orc.beamlet_pair_counts())
     amb_stats(amb, np.abs(g_o).max(), "long rows adjoint")
     assert np.all(np.abs(g - g_o) <= REL_TOL * np.abs(g_o).max())
     geo.close()

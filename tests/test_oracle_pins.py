@@ -552,3 +552,20 @@ def test_second_drift_integrates_its_own_b(oracle_mod):
         W1, W2 = np.asarray(tr["W1"]), np.asarray(tr["W2"])
         assert np.max(np.abs(W1)) > 1e-3                 # the slabs give a real drift
         assert np.array_equal(W2, scale * W1), scale
+
+
+def test_beamlet_pair_counts_transpose_voxel_counts(oracle_mod):
+    """The pair set of Algorithm A1 step 8 counted per beamlet and per voxel:
+    both totals are its size, and a beamlet whose ROI cylinder lies outside
+    the grid has no pairs."""
+    rng = np.random.default_rng(4)
+    n = (17, 13, 11)
+    rho = rng.uniform(0.05, 2.0, size=(n[2], n[1], n[0])).astype(np.float32)
+    plan = S.plan_small(n=n, density=rho, seed=4, options=S.Options(roi_radius=0.6), beams=[
+        S.Beam(gantry=0.7, nbx=3, nby=3, wx=0.4, wy=0.4),
+        S.Beam(gantry=2.1, couch=0.4, nbx=2, nby=3, wx=0.5, wy=0.3)])
+    orc = oracle_mod.Oracle(S.abi_rounded(plan))
+    per_b = orc.beamlet_pair_counts()
+    assert per_b.shape == (plan.n_beamlets,)
+    assert int(per_b.sum()) == int(orc.pair_counts().sum()) > 0
+    assert np.array_equal(orc.beamlet_pair_counts([2, 0]), per_b[[2, 0]])
