@@ -360,6 +360,28 @@ int fspb_get_schedule(const fspb_geometry* g, int* per_beam);
 int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, int reps,
                   void* stream, fspb_tune_result* results, int max_results, int* n_results);
 
+/* The adjoint's work unit is (beamlet, slab of `planes` grid planes k); each
+ * XCD takes its beamlets' units slab by slab, so thinner slabs keep more of
+ * the voxel data the units share in the XCDs' L2, thicker ones pay the
+ * per-unit set-up fewer times.  planes = 0 restores the default (the planes
+ * holding about 5 MiB of voxel weights and factors); otherwise
+ * ceil(nz / 64) <= planes <= nz, else FSPB_E_ARG.  The adjoint's per-slab
+ * partial sums are added in slab order, so its result depends on the
+ * thickness in the last bits only (and is deterministic for each).  Host
+ * state only: affects calls enqueued afterwards. */
+int fspb_set_adjoint_slab(fspb_geometry* g, int planes);
+int fspb_get_adjoint_slab(const fspb_geometry* g, int* planes);
+
+/* Times fspb_adjoint (reps timed calls each, median) with the default slab
+ * thickness, half and two and four times it, and the whole grid, and keeps
+ * the fastest.  voxel_weight: device [n_vox]; grad_scratch: device
+ * [n_beamlets], overwritten.  planes / ms (host, up to max_results entries)
+ * and n_results may be NULL.  Synchronous.  FSPB_E_STATE with exact depth
+ * tables (no adjoint). */
+int fspb_autotune_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad_scratch,
+                          int reps, void* stream, int* planes, float* ms, int max_results,
+                          int* n_results);
+
 /* ---- batches: many plans in one persistent launch -----------------------
  * A batch schedules every brick of up to 64 plans (sharing the
  * density-correction mode) over waves_per_cu x (number of CUs) persistent

@@ -335,6 +335,30 @@ class Geometry:
         return [dict(shape=r.shape, dims=tuple(r.dims), waves_per_block=r.waves_per_block,
                      per_beam=r.per_beam, ms=r.ms) for r in res[:n.value]]
 
+    def set_adjoint_slab(self, planes: int) -> None:
+        """Grid planes per adjoint work unit (0: the default; see
+        fspb_set_adjoint_slab)."""
+        check(load().fspb_set_adjoint_slab(self._handle(), int(planes)), "fspb_set_adjoint_slab")
+
+    def get_adjoint_slab(self) -> int:
+        v = C.c_int()
+        check(load().fspb_get_adjoint_slab(self._handle(), C.byref(v)), "fspb_get_adjoint_slab")
+        return v.value
+
+    def autotune_adjoint(self, voxel_weight: torch.Tensor, reps: int = 3, stream=None):
+        """Times the adjoint at a few slab thicknesses and keeps the fastest;
+        returns [dict(planes, ms)]."""
+        w = _dev_f32(voxel_weight, self.device)
+        if w.numel() != self.n_vox:
+            raise ValueError(f"voxel weight has {w.numel()} values, grid has {self.n_vox}")
+        scratch = torch.empty(self.n_beamlets, dtype=torch.float32, device=self.device)
+        planes, ms, n = (C.c_int * 16)(), (C.c_float * 16)(), C.c_int(0)
+        check(load().fspb_autotune_adjoint(self._handle(), C.c_void_p(w.data_ptr()),
+                                           C.c_void_p(scratch.data_ptr()), int(reps),
+                                           _stream(stream), planes, ms, 16, C.byref(n)),
+              "fspb_autotune_adjoint")
+        return [dict(planes=planes[i], ms=ms[i]) for i in range(n.value)]
+
     def set_dc(self, enabled: bool) -> None:
         check(load().fspb_set_dc(self._handle(), int(bool(enabled))), "fspb_set_dc")
 

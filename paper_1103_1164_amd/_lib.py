@@ -109,6 +109,11 @@ SIGNATURES = {
     "fspb_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_beamlet_pair_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_set_adjoint_slab": (C.c_int, [C.c_void_p, C.c_int]),
+    "fspb_get_adjoint_slab": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "fspb_autotune_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_float), C.c_int,
+                                        C.POINTER(C.c_int)]),
     "fspb_count_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_ulonglong), C.c_void_p]),
     "fspb_count_pairs_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

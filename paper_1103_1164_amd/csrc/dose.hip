@@ -441,16 +441,14 @@ constexpr int kAdjBlocks = 256;          // 64-item blocks per window of items
 constexpr float kAdjPad = 0.05f;         // voxels added to each interval end
 constexpr float kAdjTSlack = 1e-3f;      // depth below the entrance still scanned
 
+int adjoint_min_slab(const PlanConst& P) { return (P.nz + kAdjMaxSlabs - 1) / kAdjMaxSlabs; }
 int adjoint_slab(const PlanConst& P) {
-    // about 3 MiB of voxel data (16-byte factors, 4-byte weight) per slab
+    // about 5 MiB of voxel data (16-byte factors, 4-byte weight) per slab
     const long plane = (long)P.nx * P.ny * 20;
-    const long k = (3L << 20) / std::max(plane, 1L);
-    return (int)std::min(16L, std::max(2L, k));
+    const long k = ((5L << 20) + plane / 2) / std::max(plane, 1L);
+    return (int)std::min<long>(P.nz, std::max<long>({2L, k, (long)adjoint_min_slab(P)}));
 }
-int adjoint_slabs(const PlanConst& P) {
-    const int t = adjoint_slab(P);
-    return (P.nz + t - 1) / t;
-}
+int adjoint_slabs(const PlanConst& P, int slab) { return (P.nz + slab - 1) / slab; }
 
 // Per-beamlet constants of the row intervals (single precision).  Along a
 // grid row, voxel i = 0..nx-1, the pair coordinates are affine in i:
@@ -1316,12 +1314,12 @@ int persistent_grid(K kernel, int threads, size_t lds, int n_cu) {
 }  // namespace
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
-                    float* part, int* queue, int n_cu, hipStream_t s) {
+                    float* part, int* queue, int slab, int n_cu, hipStream_t s) {
     // with the water table in LDS, 8-wave workgroups; else 4-wave workgroups
     // reading it from global memory
     const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
     const bool lw = water_bytes <= (size_t)kLdsWaterMax;
-    const int slab = adjoint_slab(a.P), n_slabs = adjoint_slabs(a.P);
+    const int n_slabs = adjoint_slabs(a.P, slab);
     const int per = (n_beamlets + 7) / 8;
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(128), 0, s, queue, 8 * kAdjQueueInts, 0);
 #define FSPB_ADJ(DCV, NWV, LWV)                                                               \
@@ -1351,8 +1349,8 @@ void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, 
 }
 
 void launch_adjoint_count(const DoseArgs& a, int n_beamlets, int* counts, float* part,
-                          int* queue, int n_cu, hipStream_t s) {
-    const int slab = adjoint_slab(a.P), n_slabs = adjoint_slabs(a.P);
+                          int* queue, int slab, int n_cu, hipStream_t s) {
+    const int n_slabs = adjoint_slabs(a.P, slab);
     const int per = (n_beamlets + 7) / 8;
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(128), 0, s, queue, 8 * kAdjQueueInts, 0);
     auto k = dose_adjoint<kPlain, 8, false, kCount>;

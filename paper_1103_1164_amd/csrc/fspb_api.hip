@@ -241,6 +241,7 @@ struct fspb_geometry {
     int* order = nullptr;      // bricks in decreasing order of estimated work
     int* cost = nullptr;       // estimated work per brick (candidate beamlets)
     float* adj_part = nullptr; // the adjoint's per-(slab, beamlet) partial sums
+    int adj_slab = 0;          // the adjoint's slab thickness (0: adjoint_slab(P))
     int* adj_queue = nullptr;  // the adjoint's per-XCD unit counters
     // per-beam schedule (allocated on first use): sorted items, XCD runs,
     // their scratch, and the per-beam partial doses [n_beams][stride]
@@ -893,7 +894,7 @@ static int create_impl(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     ALLOC(G->tT, sizeof(float2) * (size_t)nbl * G->k_stride);
     ALLOC(G->order, sizeof(int) * max_bricks);
     ALLOC(G->cost, sizeof(int) * max_bricks);
-    ALLOC(G->adj_part, sizeof(float) * (size_t)adjoint_slabs(G->P) * nbl);
+    ALLOC(G->adj_part, sizeof(float) * (size_t)kAdjMaxSlabs * nbl);
     ALLOC(G->adj_queue, sizeof(int) * 8 * kAdjQueueInts);
     if (o.dc_enabled) {
         // one block: the 16-byte plane, then the 8-byte plane
@@ -1030,13 +1031,32 @@ int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stre
     return FSPB_OK;
 }
 
+static int adj_slab_of(const fspb_geometry* g) {
+    return g->adj_slab > 0 ? g->adj_slab : adjoint_slab(g->P);
+}
+
+int fspb_set_adjoint_slab(fspb_geometry* g, int planes) {
+    if (!g) return fail(FSPB_E_ARG, "set_adjoint_slab: NULL handle");
+    if (planes != 0 && (planes < adjoint_min_slab(g->P) || planes > g->P.nz))
+        return fail(FSPB_E_ARG, "set_adjoint_slab: %d planes outside [%d, %d] (or 0)", planes,
+                    adjoint_min_slab(g->P), g->P.nz);
+    g->adj_slab = planes;
+    return FSPB_OK;
+}
+
+int fspb_get_adjoint_slab(const fspb_geometry* g, int* planes) {
+    if (!g || !planes) return fail(FSPB_E_ARG, "get_adjoint_slab: NULL argument");
+    *planes = adj_slab_of(g);
+    return FSPB_OK;
+}
+
 int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void* stream) {
     if (!g || !voxel_weight || !grad) return fail(FSPB_E_ARG, "adjoint: NULL argument");
     if (g->siddon) return fail(FSPB_E_STATE, "adjoint: not available with exact depth tables");
     int rc = settle(g, (hipStream_t)stream);
     if (rc) return rc;
     launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad, g->adj_part,
-                   g->adj_queue, g->n_cu, (hipStream_t)stream);
+                   g->adj_queue, adj_slab_of(g), g->n_cu, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
@@ -1046,7 +1066,7 @@ int fspb_beamlet_pair_counts(fspb_geometry* g, int* counts, void* stream) {
     int rc = settle(g, (hipStream_t)stream);
     if (rc) return rc;
     launch_adjoint_count(g->args(), g->n_beamlets, counts, g->adj_part, g->adj_queue,
-                         g->n_cu, (hipStream_t)stream);
+                         adj_slab_of(g), g->n_cu, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }
@@ -1446,6 +1466,70 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     if (n_results) *n_results = n;
     if ((rc = fspb_set_schedule(g, best.per_beam, stream)) != FSPB_OK) return rc;
     return fspb_set_tile(g, best.shape, best.waves_per_block, stream);
+}
+
+int fspb_autotune_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad_scratch,
+                          int reps, void* stream, int* planes, float* ms, int max_results,
+                          int* n_results) {
+    if (!g || !voxel_weight || !grad_scratch || reps < 1)
+        return fail(FSPB_E_ARG, "autotune_adjoint: NULL argument or reps < 1");
+    if (g->siddon) return fail(FSPB_E_STATE, "autotune_adjoint: not available with exact depth tables");
+    hipStream_t s = (hipStream_t)stream;
+    if (int rc0 = settle(g, s)) return rc0;
+    // the default thickness, half and two and four times it, and the whole grid
+    const int d = adjoint_slab(g->P), lo = adjoint_min_slab(g->P), nz = g->P.nz;
+    std::vector<int> cand;
+    for (int c : {d / 2, d, 2 * d, 4 * d, nz}) {
+        c = std::min(std::max(c, std::max(lo, 1)), nz);
+        if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
+    std::sort(cand.begin(), cand.end());
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int keep = g->adj_slab;
+    int best = d, n = 0, rc = FSPB_OK;
+    float best_ms = 1e30f;
+    for (int c : cand) {
+        g->adj_slab = c;
+        std::vector<float> t_ms;
+        launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad_scratch,
+                       g->adj_part, g->adj_queue, c, g->n_cu, s);
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight,
+                           grad_scratch, g->adj_part, g->adj_queue, c, g->n_cu, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(FSPB_E_HIP, "autotune_adjoint: adjoint failed");
+                break;
+            }
+            float t = 0;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            t_ms.push_back(t);
+        }
+        if (rc) break;
+        std::sort(t_ms.begin(), t_ms.end());
+        const float med = t_ms[t_ms.size() / 2];
+        if (n < max_results) {
+            if (planes) planes[n] = c;
+            if (ms) ms[n] = med;
+        }
+        ++n;
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        g->adj_slab = keep;
+        return rc;
+    }
+    if (n_results) *n_results = n;
+    g->adj_slab = best;
+    return FSPB_OK;
 }
 
 int fspb_wait_ready(fspb_geometry* g, void* stream) {

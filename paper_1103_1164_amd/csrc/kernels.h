@@ -147,16 +147,20 @@ void launch_forward_batch(int dc, TileCfg cfg, const DoseArgs* plans, const int2
                           const float4* water, int water_n, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, long n, unsigned long long v, hipStream_t s);
 // The adjoint (and its pair count per beamlet) in units (beamlet, slab of
-// adjoint_slab(P) grid planes k): part holds adjoint_slabs(P) * n_beamlets
-// partial sums, queue 8 * kAdjQueueInts ints (the XCDs' unit counters, zeroed
-// by the launch); n_cu: the device's compute units.
+// `slab` grid planes k): part holds adjoint_slabs(P, slab) * n_beamlets
+// partial sums, at most kAdjMaxSlabs * n_beamlets (slab >= adjoint_min_slab),
+// queue 8 * kAdjQueueInts ints (the XCDs' unit counters, zeroed by the
+// launch); n_cu: the device's compute units.  adjoint_slab(P) is the default
+// thickness.
 constexpr int kAdjQueueInts = 16;
+constexpr int kAdjMaxSlabs = 64;
+int adjoint_min_slab(const PlanConst& P);
 int adjoint_slab(const PlanConst& P);
-int adjoint_slabs(const PlanConst& P);
+int adjoint_slabs(const PlanConst& P, int slab);
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
-                    float* part, int* queue, int n_cu, hipStream_t s);
+                    float* part, int* queue, int slab, int n_cu, hipStream_t s);
 void launch_adjoint_count(const DoseArgs& a, int n_beamlets, int* counts, float* part,
-                          int* queue, int n_cu, hipStream_t s);
+                          int* queue, int slab, int n_cu, hipStream_t s);
 void launch_sum_counts(const int* counts, long n, unsigned long long* partial, int n_partial,
                        unsigned long long* total, hipStream_t s);
 

@@ -358,6 +358,41 @@ def test_adjoint_long_rows_span_several_windows(oracle_mod):
     geo.close()
 
 
+def test_adjoint_slab_thickness(oracle_mod):
+    """The adjoint's unit thickness (grid planes per slab) changes only the
+    order of its partial sums: every thickness from one plane to the whole
+    grid matches the oracle, counts stay exact, a thickness is
+    deterministic, and the autotuner keeps one of those it timed."""
+    plan = _ragged_plans()[1]              # nz = 17
+    nz = plan.shape[0]
+    w = np.random.default_rng(6).uniform(0, 1, plan.n_vox).astype(np.float32)
+    orc = abi_oracle(plan)
+    g_o, amb = orc.adjoint(w)
+    cnt_o = orc.beamlet_pair_counts()
+    scale = np.abs(g_o).max()
+    geo = geometry(plan, 1)
+    wt = torch.as_tensor(w, device="cuda")
+    default = geo.get_adjoint_slab()
+    assert 1 <= default <= nz
+    for planes in (1, 2, 5, nz):
+        geo.set_adjoint_slab(planes)
+        assert geo.get_adjoint_slab() == planes
+        g1 = geo.adjoint(wt).clone()
+        assert torch.equal(geo.adjoint(wt), g1)
+        assert np.all(np.abs(g1.cpu().numpy() - g_o) <= REL_TOL * scale), planes
+        assert np.array_equal(geo.beamlet_pair_counts().cpu().numpy(), cnt_o), planes
+    geo.set_adjoint_slab(0)
+    assert geo.get_adjoint_slab() == default
+    for bad in (-1, nz + 1):
+        with pytest.raises(RuntimeError):
+            geo.set_adjoint_slab(bad)
+    res = geo.autotune_adjoint(wt, reps=2)
+    assert len(res) >= 2 and all(r["ms"] > 0 for r in res)
+    best = min(res, key=lambda r: r["ms"])
+    assert geo.get_adjoint_slab() == best["planes"]
+    geo.close()
+
+
 def test_autograd_function():
     from paper_1103_1164_amd import FspbDose
     plan = _ragged_plans()[0]
