@@ -60,9 +60,12 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 
 PEAK_HBM_GBS = 8000.0
 
 
-FORWARD_SOURCES = ("dose.hip", "pair.h", "kernels.h", "fspb_internal.h")
+FORWARD_SOURCES = ("dose.hip", "pair.h", "wave.h", "kernels.h", "fspb_internal.h")
+ADJOINT_SOURCES = ("adjoint.hip", "pair.h", "wave.h", "kernels.h", "fspb_internal.h")
 PMC_SUMMARY = ROOT / "profiles" / "dose_forward_c2_pmc.md"
 PMC_SUMMARY_C3 = ROOT / "profiles" / "dose_forward_c3_pmc.md"
+PMC_SUMMARY_ADJ = ROOT / "profiles" / "dose_adjoint_c2_pmc.md"
+PMC_SUMMARY_ADJ_C3 = ROOT / "profiles" / "dose_adjoint_c3_pmc.md"
 
 
 def _code_only(text: str) -> str:
@@ -74,21 +77,26 @@ def _code_only(text: str) -> str:
     return " ".join(text.split())
 
 
-def forward_source_hash() -> str:
-    """SHA-256 over the code of the forward kernel's sources (comments and
-    layout excluded): HBM counters taken on another version of the kernel do
-    not describe this one."""
+def source_hash(names=FORWARD_SOURCES) -> str:
+    """SHA-256 over the code of a kernel's sources (comments and layout
+    excluded): HBM counters taken on another version of the kernel do not
+    describe this one."""
     import hashlib
     h = hashlib.sha256()
-    for name in FORWARD_SOURCES:
+    for name in names:
         h.update(name.encode())
         h.update(_code_only((ROOT / "paper_1103_1164_amd" / "csrc" / name).read_text()).encode())
     return h.hexdigest()
 
 
-def pmc_record(tile, summary=None) -> dict:
+def forward_source_hash() -> str:
+    return source_hash(FORWARD_SOURCES)
+
+
+def pmc_record(tile=None, summary=None, sources=FORWARD_SOURCES, slab=None) -> dict:
     """The committed PMC summary's record, if it was taken on these sources
-    with this tile configuration; else an empty dict."""
+    with this tile configuration (forward) or slab thickness (adjoint); else
+    an empty dict."""
     summary = PMC_SUMMARY if summary is None else summary
     if not summary.exists():
         return {}
@@ -97,11 +105,28 @@ def pmc_record(tile, summary=None) -> dict:
         if line.startswith("    ") and ":" in line:
             k, v = line.strip().split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha256") != forward_source_hash():
+    if rec.get("source_sha256") != source_hash(sources):
         return {}
-    if rec.get("tile") != f"{tile[0]},{tile[1]}":
+    if tile is not None and rec.get("tile") != f"{tile[0]},{tile[1]}":
+        return {}
+    if slab is not None and rec.get("slab") != str(slab):
         return {}
     return rec
+
+
+def adjoint_roofline(pairs, ms, fpp, slab, summary):
+    """The adjoint's ALU roofline (the forward's arithmetic per pair) with
+    the HBM traffic of its committed PMC record, when that describes this
+    kernel and slab thickness."""
+    tf = pairs * fpp / (ms * 1e-3) / 1e12
+    pmc = pmc_record(summary=summary, sources=ADJOINT_SOURCES, slab=slab)
+    return {"bound": "alu", "kernel": "dose_adjoint<DC>", "achieved": round(tf, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+            "frac_nonpacked": round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "flops_per_pair": fpp, "pairs_per_launch": int(pairs), "launch_ms": round(ms, 4),
+            "slab_planes": slab,
+            "traffic": int(pmc["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in pmc else None,
+            "valu_busy": float(pmc["valu_busy_at_2.4GHz"]) if "valu_busy_at_2.4GHz" in pmc else None}
 
 
 def parse():
@@ -188,14 +213,17 @@ def main():
     pairs_all = geo.count_pairs(None)
     info = geo.info()
 
-    if a.forward_only:
-        for _ in range(a.forward_only):
-            geo.forward(flu, out=dose)
+    def copy_kernel():
         if a.copy_mib:
             # a kernel of known traffic (reads and writes copy_mib MiB once)
             src = torch.ones(a.copy_mib * (1 << 18), device=dev)
             dst = torch.empty_like(src)
             torch.mul(src, 1.0, out=dst)
+
+    if a.forward_only:
+        for _ in range(a.forward_only):
+            geo.forward(flu, out=dose)
+        copy_kernel()
         torch.cuda.synchronize()
         print(json.dumps({"forward_launches": a.forward_only, "pairs": pairs_fwd}))
         return
@@ -205,8 +233,10 @@ def main():
         g = torch.empty(plan.n_beamlets, device=dev)
         for _ in range(a.adjoint_only):
             geo.adjoint(w, out=g)
+        copy_kernel()
         torch.cuda.synchronize()
-        print(json.dumps({"adjoint_launches": a.adjoint_only, "pairs": pairs_all}))
+        print(json.dumps({"adjoint_launches": a.adjoint_only, "pairs": pairs_all,
+                          "slab_planes": geo.get_adjoint_slab()}))
         return
 
     # A stream of plans: each plan's geometry is created on its own stream and
@@ -292,6 +322,7 @@ def main():
     fpp = FLOPS_PER_PAIR_DC[drift_tables]
     achieved_tf = pairs_fwd * fpp / (fwd_ms * 1e-3) / 1e12
     pmc = pmc_record(geo_tile)
+    roofline_adj = adjoint_roofline(pairs_all, adj_ms, fpp, geo.get_adjoint_slab(), PMC_SUMMARY_ADJ)
     roofline = {
         "bound": "alu", "kernel": "dose_forward<DC>",
         "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -364,6 +395,7 @@ def main():
         "geometry_and_host_ms": round(geom_ms, 4),
         "adjoint_ms": round(adj_ms, 4),
         "adjoint_evals_per_s": pairs_all / (adj_ms * 1e-3),
+        "roofline_adjoint": roofline_adj,
         "h2d_ct_ms": round(h2d_ms, 4),
         "d2h_dose_ms": round(d2h_ms, 4),
         "gamma_plain_vs_dc": {k: (round(v, 5) if isinstance(v, float) else v)
@@ -605,7 +637,8 @@ def c3_case(time_loop, n=5):
         "adjoint_ms": round(adj_ms, 4), "adjoint_evals_per_s": pairs_all / (adj_ms * 1e-3),
         "roofline_forward": roof(pairs_fwd, fwd_ms, "dose_forward<DC>",
                                  int(pmc["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in pmc else None),
-        "roofline_adjoint": roof(pairs_all, adj_ms, "dose_adjoint<DC>"),
+        "roofline_adjoint": adjoint_roofline(pairs_all, adj_ms, fpp, geo.get_adjoint_slab(),
+                                             PMC_SUMMARY_ADJ_C3),
     }
     geo.close()
     return out

@@ -20,7 +20,7 @@ INCLUDE = ROOT / "include"
 OUT = PKG / "libfspb.so"
 BUILD = PKG / "_build"
 
-SOURCES = ["geometry.hip", "dose.hip", "mlp.hip", "gamma.hip", "fspb_api.hip"]
+SOURCES = ["geometry.hip", "dose.hip", "adjoint.hip", "mlp.hip", "gamma.hip", "fspb_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
