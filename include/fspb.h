@@ -533,9 +533,17 @@ void fspb_mlp_destroy(fspb_mlp* m);
 int fspb_surrogate_samples(fspb_geometry* g, const float* density, const int* rows, long long n,
                            uint16_t* x, float* t, int* valid, void* stream);
 
-/* Fused gather + inference for every (voxel, beam) row: prm (device, FP32
+/* Inference for every (voxel, beam) row: prm (device, FP32
  * [n_beams][n_vox][8]) gets (u1x, u1y, u2x, u2y) * log2(e), w1, w2, the
- * fallback flag (1 or 0) and 0.  Needs a density-corrected geometry. */
+ * fallback flag (1 or 0) and 0.  Needs a density-corrected geometry with
+ * n_vox < 2^30 and n_vox * n_beams < 2^32 (else FSPB_E_ARG).  A first pass
+ * writes the fallback rows (invalid, or |rho_hat - rho| at the voxel above
+ * the guard's het_max) and lists the others; the gather and the network
+ * then run on the listed rows only, reading the CT through 16-byte records
+ * of each voxel's 2x2 (x, y) neighbourhood built at the start of the call.
+ * The list and the records live in per-handle memory ((4 n_beams + 16)
+ * n_vox bytes, allocated on the first call): calls on one handle that
+ * overlap in time race.  Requires ny nz and nx below 2^24. */
 int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* density, float* prm,
                          void* stream);
 

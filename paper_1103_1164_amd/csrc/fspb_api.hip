@@ -241,6 +241,9 @@ struct fspb_geometry {
     int* order = nullptr;      // bricks in decreasing order of estimated work
     int* cost = nullptr;       // estimated work per brick (candidate beamlets)
     float* adj_part = nullptr; // the adjoint's per-(slab, beamlet) partial sums
+    unsigned* surr_live = nullptr;   // the surrogate's listed rows (allocated on first use)
+    unsigned* surr_count = nullptr;
+    float4* surr_quad = nullptr;     // the CT's 2x2 neighbourhoods, per call
     int adj_slab = 0;          // the adjoint's slab thickness (0: adjoint_slab(P))
     int* adj_queue = nullptr;  // the adjoint's per-XCD unit counters
     // per-beam schedule (allocated on first use): sorted items, XCD runs,
@@ -2099,6 +2102,13 @@ static int check_surrogate_geometry(const fspb_geometry* g, const char* what) {
     if (!g->dc_created)
         return fail(FSPB_E_STATE, "%s: the geometry was created without density correction", what);
     if (g->siddon) return fail(FSPB_E_STATE, "%s: not available with exact depth tables", what);
+    // row ids are 32-bit, the gathers address the CT with 32-bit byte offsets
+    // and index its rows with 24-bit multiplies
+    const long long nv = (long long)g->P.nx * g->P.ny * g->P.nz;
+    if (nv >= (1LL << 30) || nv * g->n_beams >= (1LL << 32) ||
+        (long long)g->P.ny * g->P.nz >= (1LL << 24) || g->P.nx >= (1 << 24))
+        return fail(FSPB_E_ARG, "%s: %lld voxels x %d beams exceed the surrogate's row range", what,
+                    nv, g->n_beams);
     return check_same_device(g->device, what);
 }
 
@@ -2124,8 +2134,17 @@ int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* densi
     if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
     if (!m || !density || !prm) return fail(FSPB_E_ARG, "surrogate_infer: NULL argument");
     if (m->device != g->device) return fail(FSPB_E_STATE, "surrogate_infer: handles on different devices");
+    if (!g->surr_live) {
+        const size_t rows = (size_t)g->P.nx * g->P.ny * g->P.nz * g->n_beams;
+        if ((rc = g->alloc((void**)&g->surr_live, sizeof(unsigned) * rows)) != FSPB_OK ||
+            (rc = g->alloc((void**)&g->surr_count, 256)) != FSPB_OK ||
+            (rc = g->alloc((void**)&g->surr_quad,
+                           sizeof(float4) * (size_t)g->P.nx * g->P.ny * g->P.nz)) != FSPB_OK)
+            return rc;
+    }
     launch_surrogate_infer(g->args(), density, g->rhohat, m->weights(), m->sc, m->gd,
-                           (float4*)prm, (hipStream_t)stream);
+                           (float4*)prm, g->surr_quad, g->surr_live, g->surr_count,
+                           (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return FSPB_OK;
 }

@@ -81,8 +81,13 @@ void launch_surrogate_samples(const DoseArgs& a, const float* rho, const int2* r
                               __bf16* X, float* T, int* valid, hipStream_t s);
 // Every (voxel, beam) row: prm[2 (b n_vox + v)] = (u1x, u1y, u2x, u2y) log2 e,
 // prm[2 (b n_vox + v) + 1] = (w1, w2, fallback flag, 0).
+// Two passes: classify every row (fallback records written, the others
+// listed in live[0 .. *n_live), live holding n_vox * n_beams entries), then
+// the gather and network over the list; quad (n_vox records) receives the
+// CT's 2x2 neighbourhoods the gathers read.
 void launch_surrogate_infer(const DoseArgs& a, const float* rho, const float* rhohat,
                             const MlpWeights& W, const SurrogateScale& sc,
-                            const SurrogateGuard& g, float4* prm, hipStream_t s);
+                            const SurrogateGuard& g, float4* prm, float4* quad, unsigned* live,
+                            unsigned* n_live, hipStream_t s);
 
 }  // namespace fspb

@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "pair.h"
+#include "wave.h"
 
 namespace fspb {
 
@@ -419,36 +420,119 @@ __device__ __forceinline__ RowGeo row_geometry(const DoseArgs& a, const float* _
     return r;
 }
 
+// Per-feature patch coefficients, staged in LDS by the kernels that gather
+// rows: feature f = 25 k + 5 b + a sits at (fraction back along the ray,
+// offset along e1, offset along e2) = (-(7 - k) / 7, 0.5 (a - 2), 0.5 (b - 2)).
+struct PatchCoef {
+    float4 c[kPatchN];
+    __device__ __forceinline__ void stage() {
+        for (int f = threadIdx.x; f < kPatchN; f += blockDim.x) {
+            const int k = f / 25, rem = f - 25 * k, bb = rem / 5, aa = rem - 5 * bb;
+            c[f] = make_float4(-(float)(kPatchPlanes - 1 - k) / (float)(kPatchPlanes - 1),
+                               kPatchPitch * (float)(aa - 2), kPatchPitch * (float)(bb - 2), 0.0f);
+        }
+    }
+};
+
+// Reciprocal voxel sizes of a plan (one division each, per kernel).
+struct InvSpacing {
+    float x, y, z;
+};
+__device__ __forceinline__ InvSpacing inv_spacing(const PlanConst& P) {
+    return InvSpacing{1.0f / P.dx, 1.0f / P.dy, 1.0f / P.dz};
+}
+
 // Trilinear density between voxel centres, indices clamped to the grid
-// (clamp-to-edge), at a point p relative to P0.
-__device__ __forceinline__ float density_at(const float* __restrict__ rho, const PlanConst& P,
-                                            float px, float py, float pz) {
-    const float gx = (px - P.qx0) / P.dx, gy = (py - P.qy0) / P.dy, gz = (pz - P.qz0) / P.dz;
+// (clamp-to-edge), at a point p relative to P0.  Corner offsets are 32-bit
+// (a plan's grid holds fewer than 2^30 voxels).
+__device__ __forceinline__ float density_at(const FSPB_GLOBAL float* __restrict__ rho,
+                                            const PlanConst& P, InvSpacing is, float px, float py,
+                                            float pz) {
+    const float gx = (px - P.qx0) * is.x, gy = (py - P.qy0) * is.y, gz = (pz - P.qz0) * is.z;
     const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
     const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
     const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-    const int x0 = min(max(ix, 0), P.nx - 1), x1 = min(max(ix + 1, 0), P.nx - 1);
     const int y0 = min(max(iy, 0), P.ny - 1), y1 = min(max(iy + 1, 0), P.ny - 1);
     const int z0 = min(max(iz, 0), P.nz - 1), z1 = min(max(iz + 1, 0), P.nz - 1);
-    const long sy = P.nx, sz = (long)P.nx * P.ny;
-    const float* p0 = rho + z0 * sz;
-    const float* p1 = rho + z1 * sz;
-    const float c00 = fmaf(fx, p0[y0 * sy + x1] - p0[y0 * sy + x0], p0[y0 * sy + x0]);
-    const float c10 = fmaf(fx, p0[y1 * sy + x1] - p0[y1 * sy + x0], p0[y1 * sy + x0]);
-    const float c01 = fmaf(fx, p1[y0 * sy + x1] - p1[y0 * sy + x0], p1[y0 * sy + x0]);
-    const float c11 = fmaf(fx, p1[y1 * sy + x1] - p1[y1 * sy + x0], p1[y1 * sy + x0]);
+    const unsigned r00 = (unsigned)((z0 * P.ny + y0) * P.nx), r10 = (unsigned)((z0 * P.ny + y1) * P.nx);
+    const unsigned r01 = (unsigned)((z1 * P.ny + y0) * P.nx), r11 = (unsigned)((z1 * P.ny + y1) * P.nx);
+    const int x0 = min(max(ix, 0), P.nx - 1), x1 = min(max(ix + 1, 0), P.nx - 1);
+    auto at = [&](unsigned r, int x) { return load_at(rho, 4u * (r + (unsigned)x)); };
+    const float a00 = at(r00, x0), b00 = at(r00, x1), a10 = at(r10, x0), b10 = at(r10, x1);
+    const float a01 = at(r01, x0), b01 = at(r01, x1), a11 = at(r11, x0), b11 = at(r11, x1);
+    const float c00 = fmaf(fx, b00 - a00, a00), c10 = fmaf(fx, b10 - a10, a10);
+    const float c01 = fmaf(fx, b01 - a01, a01), c11 = fmaf(fx, b11 - a11, a11);
     const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
     return fmaf(fz, c1 - c0, c0);
 }
+
+// The CT as 16-byte records, one per voxel (x, y): (rho(x, y), rho(x+1, y),
+// rho(x, y+1), rho(x+1, y+1)) in plane z, neighbours clamped to the grid.
+__global__ __launch_bounds__(256) void make_quads(const float* __restrict__ rho, int nx, int ny,
+                                                  int nz, float4* __restrict__ quad) {
+    const long n = (long)nx * ny * nz;
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny);
+        const long dx = x + 1 < nx ? 1 : 0, dy = y + 1 < ny ? nx : 0;
+        quad[v] = make_float4(rho[v], rho[v + dx], rho[v + dy], rho[v + dx + dy]);
+    }
+}
+
+// density_at from the quad records: two aligned 16-byte loads per sample
+// (planes z0 and z1) instead of eight 4-byte ones.  Same corner values and
+// the same arithmetic as density_at, so the same result bit for bit.
+__device__ __forceinline__ float density_at_quad(const FSPB_GLOBAL float4* __restrict__ quad,
+                                                 const PlanConst& P, InvSpacing is, float px,
+                                                 float py, float pz) {
+    const float gx = (px - P.qx0) * is.x, gy = (py - P.qy0) * is.y, gz = (pz - P.qz0) * is.z;
+    const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
+    const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
+    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+    const int x0 = min(max(ix, 0), P.nx - 1), y0 = min(max(iy, 0), P.ny - 1);
+    const int z0 = min(max(iz, 0), P.nz - 1), z1 = min(max(iz + 1, 0), P.nz - 1);
+    // 24-bit multiplies: ny nz and nx are below 2^24 (checked with the plan)
+    const unsigned o0 = __umul24(__umul24((unsigned)z0, (unsigned)P.ny) + (unsigned)y0, (unsigned)P.nx) + (unsigned)x0;
+    const unsigned o1 = __umul24(__umul24((unsigned)z1, (unsigned)P.ny) + (unsigned)y0, (unsigned)P.nx) + (unsigned)x0;
+    const float4 q0 = load_at(quad, 16u * o0), q1 = load_at(quad, 16u * o1);
+    // below the grid in x (or y) both corners along that axis are the edge
+    // voxel; above it the records already repeat the edge voxel
+    const bool xl = ix < 0, yl = iy < 0;
+    const float a0 = q0.x, b0 = xl ? q0.x : q0.y, c0 = yl ? q0.x : q0.z;
+    const float d0 = yl ? b0 : (xl ? q0.z : q0.w);
+    const float a1 = q1.x, b1 = xl ? q1.x : q1.y, c1 = yl ? q1.x : q1.z;
+    const float d1 = yl ? b1 : (xl ? q1.z : q1.w);
+    const float c00 = fmaf(fx, b0 - a0, a0), c10 = fmaf(fx, d0 - c0, c0);
+    const float c01 = fmaf(fx, b1 - a1, a1), c11 = fmaf(fx, d1 - c1, c1);
+    const float e0 = fmaf(fy, c10 - c00, c00), e1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, e1 - e0, e0);
+}
+
+// The two density sources of gather8: the CT itself, or its quad records
+// (identical values, so identical features).
+struct DensityPlain {
+    const FSPB_GLOBAL float* rho;
+    __device__ __forceinline__ float operator()(const PlanConst& P, InvSpacing is, float px, float py,
+                                                float pz) const {
+        return density_at(rho, P, is, px, py, pz);
+    }
+};
+struct DensityQuad {
+    const FSPB_GLOBAL float4* quad;
+    __device__ __forceinline__ float operator()(const PlanConst& P, InvSpacing is, float px, float py,
+                                                float pz) const {
+        return density_at_quad(quad, P, is, px, py, pz);
+    }
+};
 
 // Eight scaled input features of this lane's layer-1 A fragment for k-step
 // kt: lane l takes row l % 16 and features kt * 32 + 8 (l / 16) + j.  Also
 // folds the lane's share of the guard statistics (min / max patch density,
 // largest |rho - rho(voxel)| over the two planes next to the voxel); the
 // caller combines the four lanes of a row.
-__device__ __forceinline__ bf16x8 gather8(const float* __restrict__ rho, const PlanConst& P,
-                                          const RowGeo& r, int kt, int lane, float& rmin,
-                                          float& rmax, float& het) {
+template <class DS>
+__device__ __forceinline__ bf16x8 gather8(const DS& density, const PlanConst& P, InvSpacing is,
+                                          const PatchCoef& pc, const RowGeo& r, int kt, int lane,
+                                          float& rmin, float& rmax, float& het) {
     const int f0 = kt * 32 + 8 * (lane >> 4);
     bf16x8 xk;
 #pragma unroll
@@ -456,16 +540,15 @@ __device__ __forceinline__ bf16x8 gather8(const float* __restrict__ rho, const P
         const int f = f0 + j;
         float x = 0.0f;
         if (f < kPatchN) {
-            const int k = f / 25, rem = f - 25 * k, bb = rem / 5, aa = rem - 5 * bb;
-            const float back = -r.t * (float)(kPatchPlanes - 1 - k) / (float)(kPatchPlanes - 1);
-            const float la = kPatchPitch * (float)(aa - 2), lb = kPatchPitch * (float)(bb - 2);
-            const float px = r.qx + back * r.ux + la * r.e1x + lb * r.e2x;
-            const float py = r.qy + back * r.uy + la * r.e1y + lb * r.e2y;
-            const float pz = r.qz + back * r.uz + la * r.e1z + lb * r.e2z;
-            const float rv = density_at(rho, P, px, py, pz);
+            const float4 c = pc.c[f];
+            const float back = r.t * c.x;
+            const float px = fmaf(c.z, r.e2x, fmaf(c.y, r.e1x, fmaf(back, r.ux, r.qx)));
+            const float py = fmaf(c.z, r.e2y, fmaf(c.y, r.e1y, fmaf(back, r.uy, r.qy)));
+            const float pz = fmaf(c.z, r.e2z, fmaf(c.y, r.e1z, fmaf(back, r.uz, r.qz)));
+            const float rv = density(P, is, px, py, pz);
             rmin = fminf(rmin, rv);
             rmax = fmaxf(rmax, rv);
-            if (k >= kPatchPlanes - 2) het = fmaxf(het, fabsf(rv - r.rho_c));
+            if (f >= (kPatchPlanes - 2) * 25) het = fmaxf(het, fabsf(rv - r.rho_c));
             x = rv - 1.0f;
         } else if (f == kPatchN) {
             x = r.t * 0.1f - 1.0f;
@@ -495,9 +578,13 @@ __global__ __launch_bounds__(256) void surrogate_samples_kernel(DoseArgs a,
                                                                 long n, __bf16* __restrict__ X,
                                                                 float* __restrict__ T,
                                                                 int* __restrict__ valid) {
+    __shared__ PatchCoef pc;
+    pc.stage();
+    __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const long row = ((long)blockIdx.x * (blockDim.x >> 6) + wid) * 16 + (lane & 15);
     if (row >= n) return;
+    const InvSpacing is = inv_spacing(a.P);
     const int2 rv = rows[row];
     const long n_vox = (long)a.P.nx * a.P.ny * a.P.nz;
     RowGeo r;
@@ -510,7 +597,7 @@ __global__ __launch_bounds__(256) void surrogate_samples_kernel(DoseArgs a,
 #pragma unroll 1
     for (int kt = 0; kt < kK1 / 32; ++kt) {
         bf16x8 xk = {};
-        if (r.valid) xk = gather8(rho, a.P, r, kt, lane, rmin, rmax, het);
+        if (r.valid) xk = gather8(DensityPlain{as_global(rho)}, a.P, is, pc, r, kt, lane, rmin, rmax, het);
         *reinterpret_cast<bf16x8*>(X + row * kK1 + kt * 32 + fk) = xk;
     }
     if (lane < 16) {
@@ -526,23 +613,100 @@ __global__ __launch_bounds__(256) void surrogate_samples_kernel(DoseArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Fused gather + inference over every (voxel, beam) row.  A workgroup of 4
-// waves keeps the BF16 weights in LDS and walks groups of 4 tiles; a tile is
-// 16 consecutive voxels of one beam (one per lane row).  Each lane gathers
+// Inference over every (voxel, beam) row, in two passes.
+//
+// surrogate_classify_kernel: one thread per row (rows beam-major).  A row
+// that is invalid or fails the guard's cheapest test (|rho_hat - rho| at the
+// voxel) gets its fallback record at once; the others are appended to `live`
+// with one atomic per wave.  Their order in the list is arbitrary and nothing
+// depends on it: a row's result depends on that row alone (the matrix-core
+// products sum each output element in a fixed order).
+constexpr int kClassRows = 8;   // rows per thread per block of the classify pass
+
+__global__ __launch_bounds__(256) void surrogate_classify_kernel(DoseArgs a,
+                                                                 const float* __restrict__ rho,
+                                                                 const float* __restrict__ rhohat,
+                                                                 float het_max,
+                                                                 float4* __restrict__ prm,
+                                                                 unsigned* __restrict__ live,
+                                                                 unsigned* __restrict__ n_live) {
+    constexpr int kBlock = 256 * kClassRows;
+    __shared__ unsigned s_bits[kBlock / 32];
+    __shared__ int s_wsum[4];
+    __shared__ unsigned s_base;
+    const PlanConst& P = a.P;
+    const long n_vox = (long)P.nx * P.ny * P.nz;
+    const long n_rows = n_vox * P.n_beams;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // a block of 2,048 consecutive rows per round, classified with coalesced
+    // accesses (row q * 256 + tid); the keep bits go to an LDS bitmap, and
+    // each thread then lists eight consecutive rows, so the list keeps the
+    // rows' order (the gathers of a tile of 16 listed rows read neighbouring
+    // voxels' patches); one atomic reserves the block's slots
+    for (long blk = blockIdx.x; blk * kBlock < n_rows; blk += gridDim.x) {
+#pragma unroll
+        for (int q = 0; q < kClassRows; ++q) {
+            const long row = blk * kBlock + q * 256 + tid;
+            bool keep = false;
+            if (row < n_rows) {
+                const int b = (int)(row / n_vox);
+                const long v = row - (long)b * n_vox;
+                const RowGeo r = row_geometry(a, rho, v, b);
+                keep = r.valid && fabsf(rhohat[v] - r.rho_c) <= het_max;
+                if (!keep) {
+                    prm[2 * row] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    prm[2 * row + 1] = make_float4(0.f, 0.f, 1.f, 0.f);
+                }
+            }
+            const unsigned long long m = __ballot(keep);
+            if (lane == 0) {
+                s_bits[(q * 256 + wid * 64) / 32] = (unsigned)m;
+                s_bits[(q * 256 + wid * 64) / 32 + 1] = (unsigned)(m >> 32);
+            }
+        }
+        __syncthreads();
+        const unsigned mine = (s_bits[(tid * kClassRows) / 32] >> ((tid * kClassRows) % 32)) & 0xffu;
+        const int cnt = __popc(mine);
+        const int incl = wave_incl_scan_int(cnt, lane);
+        if (lane == 63) s_wsum[wid] = incl;
+        __syncthreads();
+        int off = incl - cnt, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (w < wid) off += s_wsum[w];
+            total += s_wsum[w];
+        }
+        if (tid == 0) s_base = total ? atomicAdd(n_live, (unsigned)total) : 0u;
+        __syncthreads();
+        const unsigned base = s_base;
+#pragma unroll
+        for (int q = 0; q < kClassRows; ++q)
+            if (mine & (1u << q)) live[base + off++] = (unsigned)(blk * kBlock + tid * kClassRows + q);
+        __syncthreads();   // s_bits, s_wsum and s_base are read before the next round writes them
+    }
+}
+
+__global__ void zero_u32(unsigned* __restrict__ p) { *p = 0u; }
+
+// surrogate_infer_kernel: the listed rows, 16 per wave (one per lane row).
+// A workgroup of 4 waves keeps the BF16 weights in LDS; each lane gathers
 // its own A fragments, so the inputs never touch memory.
 constexpr int kW1S = kK1 + 8;       // LDS row strides (elements), padded
 constexpr int kHS = kMlpHid + 8;
-constexpr int kInferWaves = 4;
+constexpr int kInferWaves = 8;
 
+// One activation buffer per wave, reused layer after layer (a layer's
+// inputs are all in registers before its outputs overwrite them): two
+// workgroups fit a CU's LDS.
 struct InferLds {
     alignas(16) __bf16 w1[kMlpHid * kW1S];
     alignas(16) __bf16 w2[kMlpHid * kHS];
     alignas(16) __bf16 w3[16 * kHS];
     float b1[kMlpHid], b2[kMlpHid], b3[16];
-    alignas(16) __bf16 h1[kInferWaves][16 * kHS];
-    alignas(16) __bf16 h2[kInferWaves][16 * kHS];
-    float y[kInferWaves][16 * 8];
+    alignas(16) __bf16 h[kInferWaves][16 * kHS];
+    PatchCoef pc;
 };
+static_assert(16 * 8 * sizeof(float) <= 16 * kHS * sizeof(__bf16), "the output rows fit the buffer");
 
 __device__ __forceinline__ void copy_rows16(__bf16* dst, int dst_stride, const __bf16* src,
                                             int src_stride, int rows, int cols) {
@@ -562,11 +726,15 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
+__global__ __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_eu(4)))
+void surrogate_infer_kernel(DoseArgs a,
                                                               const float* __restrict__ rho,
                                                               const float* __restrict__ rhohat,
                                                               MlpWeights W, SurrogateScale sc,
                                                               SurrogateGuard gd,
+                                                              const float4* __restrict__ quad,
+                                                              const unsigned* __restrict__ live,
+                                                              const unsigned* __restrict__ n_live_p,
                                                               float4* __restrict__ prm) {
     __shared__ InferLds L;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -579,43 +747,55 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
         L.b2[threadIdx.x] = W.b2[threadIdx.x];
     }
     if (threadIdx.x < 16) L.b3[threadIdx.x] = threadIdx.x < kMlpOut ? W.b3[threadIdx.x] : 0.0f;
+    L.pc.stage();
     __syncthreads();
 
     const PlanConst& P = a.P;
+    const InvSpacing is = inv_spacing(P);
     const long n_vox = (long)P.nx * P.ny * P.nz;
-    const long tiles_per_beam = (n_vox + 15) / 16;
-    const long n_tiles = tiles_per_beam * P.n_beams;
-    const long n_groups = (n_tiles + kInferWaves - 1) / kInferWaves;
-    __bf16* h1 = L.h1[wid];
-    __bf16* h2 = L.h2[wid];
-    float* yl = L.y[wid];
-    for (long g = blockIdx.x; g < n_groups; g += gridDim.x) {
-        const long tile = g * kInferWaves + wid;
-        const int b = (int)(tile / tiles_per_beam);
-        const long v = (tile - (long)b * tiles_per_beam) * 16 + fr;
-        const bool row_in = tile < n_tiles && v < n_vox;
+    const long n_live = (long)*n_live_p;
+    const DensityQuad dq{as_global(quad)};
+    __bf16* h = L.h[wid];
+    float* yl = reinterpret_cast<float*>(h);
+    // each XCD (workgroups are dealt round-robin to the 8 XCDs) walks one
+    // contiguous eighth of the listed tiles: the rows it has in flight are
+    // then neighbours, and the CT records their patches read stay in its L2
+    const long n_tiles = (n_live + 15) / 16;
+    const long per_xcd = (n_tiles + 7) / 8;
+    const int xcd = blockIdx.x & 7;
+    const long t_end = min((long)(xcd + 1) * per_xcd, n_tiles);
+    const long wg_per_xcd = gridDim.x / 8;
+    for (long tile = (long)xcd * per_xcd + (long)(blockIdx.x >> 3) * kInferWaves + wid; tile < t_end;
+         tile += wg_per_xcd * kInferWaves) {
+        const long li = tile * 16 + fr;
+        const bool row_in = li < n_live;
         RowGeo r;
         r.valid = false;
-        if (row_in) r = row_geometry(a, rho, v, b);
-        // The heterogeneity test runs first, on the cheapest data: the
-        // smoothed density at the voxel, then the two planes next to it
-        // (k-steps 4-6, kept as A fragments).  A wave whose rows all fall
-        // back skips the rest of the gather and the network.
+        long v = 0;
+        int b = 0;
+        if (row_in) {
+            const unsigned row = live[li];
+            b = (int)(row / (unsigned long)n_vox);
+            v = (long)row - (long)b * n_vox;
+            r = row_geometry(a, rho, v, b);
+        }
+        // the listed rows passed the cheap test; the two planes next to the
+        // voxel (k-steps 4-6, kept as A fragments) come next, and a wave
+        // whose rows all fall back then skips the rest of the gather and
+        // the network
         float rmin = FLT_MAX, rmax = -FLT_MAX, het = 0.0f;
         if (r.valid) het = fabsf(rhohat[v] - r.rho_c);
-        bool live = r.valid && het <= gd.het_max;
+        bool live_r = r.valid && het <= gd.het_max;
         constexpr int kNear = 4;            // first k-step that holds plane 6
         bf16x8 xn[kK1 / 32 - kNear];
-        if (__ballot(live) != 0) {
 #pragma unroll
-            for (int q = 0; q < kK1 / 32 - kNear; ++q) {
-                xn[q] = bf16x8{};
-                if (live) xn[q] = gather8(rho, P, r, kNear + q, lane, rmin, rmax, het);
-            }
-            row_stats_combine(rmin, rmax, het);
-            live = live && het <= gd.het_max;
+        for (int q = 0; q < kK1 / 32 - kNear; ++q) {
+            xn[q] = bf16x8{};
+            if (live_r) xn[q] = gather8(dq, P, is, L.pc, r, kNear + q, lane, rmin, rmax, het);
         }
-        const bool any = __ballot(live) != 0;
+        row_stats_combine(rmin, rmax, het);
+        live_r = live_r && het <= gd.het_max;
+        const bool any = __ballot(live_r) != 0;
         if (any) {
             // layer 1, the remaining inputs gathered one k-step (8 features a
             // lane) at a time
@@ -625,7 +805,7 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
 #pragma unroll 1
             for (int kt = 0; kt < kNear; ++kt) {
                 bf16x8 xk = {};
-                if (live) xk = gather8(rho, P, r, kt, lane, rmin, rmax, het);
+                if (live_r) xk = gather8(dq, P, is, L.pc, r, kt, lane, rmin, rmax, het);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[nt] = mfma(xk, ld8(L.w1 + (nt * 16 + fr) * kW1S + kt * 32 + fk), acc[nt]);
@@ -642,30 +822,41 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
                 const int col = nt * 16 + fr;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    h1[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[nt][j] + L.b1[col]);
+                    h[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[nt][j] + L.b1[col]);
             }
         }
         wave_sync();
         if (any) {
+            // layer 2: every fragment of h1 is read before h2 overwrites it
+            bf16x8 a2[2];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) a2[kt] = ld8(h + fr * kHS + kt * 32 + fk);
+            f32x4 acc[4];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt)
-                    acc = mfma(ld8(h1 + fr * kHS + kt * 32 + fk),
-                               ld8(L.w2 + (nt * 16 + fr) * kHS + kt * 32 + fk), acc);
+                    acc[nt] = mfma(a2[kt], ld8(L.w2 + (nt * 16 + fr) * kHS + kt * 32 + fk), acc[nt]);
+            }
+            wave_sync();
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
                 const int col = nt * 16 + fr;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    h2[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[j] + L.b2[col]);
+                    h[(4 * (lane >> 4) + j) * kHS + col] = (__bf16)gelu(acc[nt][j] + L.b2[col]);
             }
         }
         wave_sync();
         if (any) {
+            bf16x8 a3[2];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) a3[kt] = ld8(h + fr * kHS + kt * 32 + fk);
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
-                acc = mfma(ld8(h2 + fr * kHS + kt * 32 + fk), ld8(L.w3 + fr * kHS + kt * 32 + fk), acc);
+            for (int kt = 0; kt < 2; ++kt) acc = mfma(a3[kt], ld8(L.w3 + fr * kHS + kt * 32 + fk), acc);
+            wave_sync();
             if (fr < 8) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) yl[(4 * (lane >> 4) + j) * 8 + fr] = acc[j] + L.b3[fr];
@@ -674,8 +865,8 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
         wave_sync();
         if (lane < 16 && row_in) {
             float o[kMlpOut];
-            bool fb = !live;
-            if (live) {
+            bool fb = !live_r;
+            if (live_r) {
 #pragma unroll
                 for (int c = 0; c < kMlpOut; ++c) {
                     o[c] = fmaf(yl[lane * 8 + c], sc.stdev[c], sc.mean[c]);
@@ -692,10 +883,10 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(DoseArgs a,
             prm[2 * ((long)b * n_vox + v)] = ul;
             prm[2 * ((long)b * n_vox + v) + 1] = wv;
         }
-        // each wave reads and writes only its own h1, h2 and y (the weights
-        // are read-only here), so waves need not wait for one another: a
-        // wave's LDS accesses complete in order, and wave_sync keeps the
-        // compiler from moving them across the layer boundaries
+        // each wave reads and writes only its own activation buffer (the
+        // weights are read-only here), so waves need not wait for one
+        // another: a wave's LDS accesses complete in order, and wave_sync
+        // keeps the compiler from moving them across the layer boundaries
     }
 }
 
@@ -740,12 +931,21 @@ void launch_surrogate_samples(const DoseArgs& a, const float* rho, const int2* r
 
 void launch_surrogate_infer(const DoseArgs& a, const float* rho, const float* rhohat,
                             const MlpWeights& W, const SurrogateScale& sc,
-                            const SurrogateGuard& g, float4* prm, hipStream_t s) {
+                            const SurrogateGuard& g, float4* prm, float4* quad, unsigned* live,
+                            unsigned* n_live, hipStream_t s) {
     const long n_vox = (long)a.P.nx * a.P.ny * a.P.nz;
-    const long n_groups = ((n_vox + 15) / 16 * a.P.n_beams + kInferWaves - 1) / kInferWaves;
-    const unsigned grid = (unsigned)std::min<long>(n_groups, 2048);
+    const long n_rows = n_vox * a.P.n_beams;
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, s, n_live);
+    hipLaunchKernelGGL(make_quads, dim3((unsigned)std::min<long>((n_vox + 255) / 256, 16384)), dim3(256),
+                       0, s, rho, a.P.nx, a.P.ny, a.P.nz, quad);
+    const unsigned cgrid = (unsigned)std::min<long>((n_rows + 2047) / 2048, 4096);
+    hipLaunchKernelGGL(surrogate_classify_kernel, dim3(cgrid), dim3(256), 0, s, a, rho, rhohat,
+                       g.het_max, prm, live, n_live);
+    const long n_groups = ((n_rows + 15) / 16 + kInferWaves - 1) / kInferWaves;
+    const unsigned grid = (unsigned)(8 * std::min<long>((n_groups + 7) / 8, 256));   // a multiple of 8
     hipLaunchKernelGGL(surrogate_infer_kernel, dim3(grid), dim3(64 * kInferWaves), 0, s, a, rho,
-                       rhohat, W, sc, g, prm);
+                       rhohat, W, sc, g, (const float4*)quad, (const unsigned*)live,
+                       (const unsigned*)n_live, prm);
 }
 
 void launch_mlp_loss_sum(const float* parts, int n_parts, float* out, hipStream_t s) {
