@@ -156,6 +156,10 @@ def parse():
                     help="profiling aid: only launch the forward kernel this many times")
     ap.add_argument("--adjoint-only", type=int, default=0,
                     help="profiling aid: only launch the adjoint kernel this many times")
+    ap.add_argument("--surrogate-only", type=int, default=0,
+                    help="profiling aid: only run the surrogate's inference this many times "
+                         "(untrained network, the guard threshold het_max = 0.01 the calibration "
+                         "picks on these heads: the gathers and the network do the same work)")
     ap.add_argument("--profile-plan", choices=("c2", "c3", "paper_h5", "paper_l2"), default="c2",
                     help="profiling aid: the plan --forward-only / --adjoint-only launch on "
                          "(c2 with the benchmark's tile, the others with the library's default "
@@ -187,7 +191,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if a.profile_plan != "c2" and not (a.forward_only or a.adjoint_only):
+    if a.profile_plan != "c2" and not (a.forward_only or a.adjoint_only or a.surrogate_only):
         print("--profile-plan is a profiling aid: give --forward-only or --adjoint-only",
               file=sys.stderr)
         sys.exit(2)
@@ -226,6 +230,19 @@ def main():
         copy_kernel()
         torch.cuda.synchronize()
         print(json.dumps({"forward_launches": a.forward_only, "pairs": pairs_fwd}))
+        return
+    if a.surrogate_only:
+        from paper_1103_1164_amd import Mlp
+        mlp = Mlp.initial(0)
+        mlp.set_guard(het_max=0.01)
+        prm = geo.surrogate_infer(mlp)
+        for _ in range(a.surrogate_only):
+            geo.surrogate_infer(mlp, out=prm)
+        copy_kernel()
+        torch.cuda.synchronize()
+        print(json.dumps({"surrogate_launches": a.surrogate_only,
+                          "rows": int(prm.shape[0] * prm.shape[1]),
+                          "fallback_rows": int((prm[..., 6] != 0).sum())}))
         return
     if a.adjoint_only:
         w = torch.as_tensor(np.random.default_rng(5).uniform(0, 1, plan.n_vox).astype(np.float32),
