@@ -108,7 +108,11 @@ typedef struct {
     fspb_table1d fu1, fu2, fw1, fw2, b1, b2;
 } fspb_tables;
 
-/* Options.  Zero-initialised fields take the defaults in brackets. */
+/* Options.  Zero float fields take the defaults in brackets.  The integer
+ * fields are used as given, so a zero-initialised struct selects plain FSPB
+ * (dc_enabled = 0), the default tile and the brick-major schedule, while
+ * opts = NULL in fspb_create_geometry selects every default with the density
+ * correction on (dc_enabled = 1). */
 typedef struct {
     float roi_radius;    /* ROI cylinder radius [5 cm] (Algorithm A1 footnote) */
     float rho_surface;   /* body-surface density threshold [0.5] */
@@ -116,7 +120,8 @@ typedef struct {
     float rho_min;       /* commissioned density range [0.1] */
     float rho_max;       /*                            [2.0] */
     float sample_step;   /* ray sampling step [min(dx,dy,dz)/2] (Section 2.2) */
-    int dc_enabled;      /* 1: 3D density correction, 0: plain FSPB (A1 without step 11) */
+    int dc_enabled;      /* 1: 3D density correction, 0: plain FSPB (A1 without step 11);
+                            no bracketed default: 0 here means plain FSPB */
     int flags;           /* 0, or FSPB_FLAG_SIDDON */
     /* forward tile built at creation (see fspb_set_tile): tile_waves = 0
      * takes the default (brick shape 0, 8 waves per workgroup); otherwise
@@ -198,7 +203,8 @@ typedef struct {
  *   ct      host struct; ct->density device.
  *   beams   host array [n_beams].
  *   tables  host struct with host arrays (copied).
- *   opts    host struct or NULL for the defaults.
+ *   opts    host struct, or NULL for the defaults with the density
+ *           correction on (a zero-initialised struct turns it off).
  *   out     receives the handle (NULL on error).
  * Errors: FSPB_E_ARG for empty or inconsistent inputs (non-positive sizes,
  * source inside the grid box, depth tables on different grids, nonzero

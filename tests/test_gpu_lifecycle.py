@@ -115,3 +115,36 @@ def test_tile_given_at_creation_matches_set_tile(shape, waves):
     assert torch.equal(a.forward(f), b.forward(f))
     a.close()
     b.close()
+
+
+def test_zero_initialised_options_mean_plain_fspb():
+    """A zero-initialised fspb_options (every field 0) takes the bracketed
+    defaults for its float fields and dc_enabled = 0 (plain FSPB); NULL
+    options take the same defaults with the density correction on.  Both
+    match plans built with those defaults spelt out, bit for bit."""
+    from paper_1103_1164_amd import Geometry
+
+    class Zero:
+        roi_radius = rho_surface = smooth_sigma = rho_min = rho_max = sample_step = 0.0
+        dc_enabled = siddon = 0
+
+    plan = S.plan_small(n=(19, 17, 13), density=1.0, seed=2,
+                        beams=[S.Beam(gantry=0.7, nbx=3, nby=3, wx=0.5, wy=0.5)])
+    dens = torch.as_tensor(plan.density, device="cuda")
+    f = torch.as_tensor(plan.fluence, device="cuda")
+
+    def make(options):
+        return Geometry(dens, plan.spacing, plan.origin, plan.beams, plan.tables, options)
+
+    g_zero, g_null = make(Zero()), make(None)
+    assert g_zero.info()["dc_enabled"] == 0
+    assert g_null.info()["dc_enabled"] == 1
+    spelt = S.Options()                       # roi 5, surface 0.5, sigma 0.5, rho 0.1-2.0
+    assert (spelt.roi_radius, spelt.rho_surface, spelt.smooth_sigma,
+            spelt.rho_min, spelt.rho_max, spelt.sample_step) == (5.0, 0.5, 0.5, 0.1, 2.0, 0.0)
+    spelt.dc_enabled = 0
+    assert torch.equal(g_zero.forward(f), make(spelt).forward(f))
+    spelt.dc_enabled = 1
+    assert torch.equal(g_null.forward(f), make(spelt).forward(f))
+    for g in (g_zero, g_null):
+        g.close()

@@ -267,25 +267,36 @@ def test_c3_adjoint_sampled_and_fd(oracle_mod):
     # quadratic objective: central differences of the GPU forward against the
     # adjoint of w' = 2 w (D - D0).  D is linear in f (Eq. 1), so L is exactly
     # quadratic and the central difference has no truncation error at any
-    # step: a step of 0.05 (fluences are about 1) keeps the FP32 rounding of
-    # the doses small against D(f + h) - D(f - h).  The difference of L is
-    # summed in FP64 to avoid cancellation.
+    # step; what remains is the FP32 rounding of the two doses, which grows
+    # as 1/h.  Steps 0.05 and 1e-3 (fluences are about 1); the difference of
+    # L is summed in FP64 from the FP32 doses.  The bound adds to 2e-3 of the
+    # gradient the rounding term: 4 ulp of each voxel's dose in D(f + h) and
+    # D(f - h), weighted by |w (D+ + D- - 2 D0)| and summed in absolute value,
+    # over 2 h.
     f = torch.as_tensor(plan.fluence, device="cuda")
     D = geo.forward(f).reshape(-1)
     D0 = torch.as_tensor(u, device="cuda") * D.max()
     wq = (2.0 * wt * (D - D0)).contiguous()
     gq = geo.adjoint(wq).double()
-    h = 0.05
     rng = np.random.default_rng(5)
-    for i in rng.choice(nb, size=16, replace=False):
-        fp, fm = f.clone(), f.clone()
-        fp[i] += h
-        fm[i] -= h
-        hh = (fp[i].double() - fm[i].double()) / 2
-        Dp, Dm = geo.forward(fp).reshape(-1).double(), geo.forward(fm).reshape(-1).double()
-        dL = torch.sum(wt.double() * (Dp - Dm) * (Dp + Dm - 2 * D0.double()))
-        fd = float(dL / (2 * hh))
-        assert abs(fd - float(gq[i])) <= 2e-3 * max(abs(float(gq[i])), 1e-3 * float(gq.abs().max()))
+    pick_fd = rng.choice(nb, size=16, replace=False)
+    worst = {}
+    for h in (0.05, 1e-3):
+        for i in pick_fd:
+            fp, fm = f.clone(), f.clone()
+            fp[i] += h
+            fm[i] -= h
+            hh = (fp[i].double() - fm[i].double()) / 2
+            Dp, Dm = geo.forward(fp).reshape(-1).double(), geo.forward(fm).reshape(-1).double()
+            c = wt.double() * (Dp + Dm - 2 * D0.double())
+            dL = torch.sum(c * (Dp - Dm))
+            fd = float(dL / (2 * hh))
+            rounding = float(torch.sum(c.abs() * 4 * 2.0 ** -24 * (Dp.abs() + Dm.abs())) / (2 * hh))
+            g_i = float(gq[i])
+            tol = 2e-3 * max(abs(g_i), 1e-3 * float(gq.abs().max())) + rounding
+            assert abs(fd - g_i) <= tol, (h, int(i), fd, g_i, rounding)
+            worst[h] = max(worst.get(h, 0.0), abs(fd - g_i) / max(abs(g_i), 1e-30))
+    say(f"c3 finite differences: max relative deviation {worst}")
 
 
 def test_c2_adjoint_sampled(oracle_mod):
