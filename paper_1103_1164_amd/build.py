@@ -20,7 +20,8 @@ INCLUDE = ROOT / "include"
 OUT = PKG / "libfspb.so"
 BUILD = PKG / "_build"
 
-SOURCES = ["geometry.hip", "dose.hip", "adjoint.hip", "mlp.hip", "gamma.hip", "fspb_api.hip"]
+SOURCES = ["geometry.hip", "dose.hip", "adjoint.hip", "mlp.hip", "gamma.hip", "api_common.hip",
+           "fspb_api.hip", "api_batch.hip", "api_mlp.hip", "api_gamma.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,0 +1,89 @@
+// api_common.hip -- host side of libfspb shared by the entry points: error
+// reporting, argument checks of tables and the device checks.
+#include "api_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+
+namespace fspb {
+
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+int check_table(const fspb_table1d& t, const char* name) {
+    if (t.n < 1 || !t.v) return fail(FSPB_E_ARG, "table %s: needs n >= 1 and values", name);
+    if (!isfinite(t.start) || (t.n > 1 && !finite_pos(t.step)))
+        return fail(FSPB_E_ARG, "table %s: start must be finite and step > 0", name);
+    return FSPB_OK;
+}
+
+int check_device(int* dev) {
+    // the architecture of each device is looked up once (the property query
+    // is slow compared with creating a plan)
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> arch_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
+    }
+    HIP_TRY(hipGetDevice(dev));
+    const int v = (*dev >= 0 && *dev < kMaxDevices) ? arch_ok[*dev].load() : 0;
+    if (v == 1) return FSPB_OK;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (*dev >= 0 && *dev < kMaxDevices) arch_ok[*dev].store(ok ? 1 : -1);
+    if (!ok)
+        return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
+                    prop.gcnArchName);
+    return FSPB_OK;
+}
+
+int check_same_device(int dev, const char* what) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) return fail(FSPB_E_STATE, "%s: handle lives on device %d, current is %d", what, dev, cur);
+    return FSPB_OK;
+}
+
+const char* last_error_text() { return g_last_error.c_str(); }
+void clear_last_error() { g_last_error.clear(); }
+
+}  // namespace fspb
+
+extern "C" {
+
+const char* fspb_error_string(int code) {
+    switch (code) {
+        case FSPB_OK: return "success";
+        case FSPB_E_ARG: return "invalid argument";
+        case FSPB_E_HIP: return "HIP runtime error";
+        case FSPB_E_NOMEM: return "out of memory";
+        case FSPB_E_STATE: return "invalid state for this handle";
+        case FSPB_E_UNSUPPORTED: return "unsupported device";
+        default: return "unknown error";
+    }
+}
+
+const char* fspb_last_error(void) { return fspb::last_error_text(); }
+
+}  // extern "C"

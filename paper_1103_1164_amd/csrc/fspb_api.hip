@@ -1,54 +1,33 @@
-// fspb_api.hip -- host side of libfspb: the C ABI of include/fspb.h.
+// fspb_api.hip -- host side of libfspb: the geometry handle's entry points
+// of the C ABI in include/fspb.h (creation, forward, adjoint, pair counts,
+// inspection, tiling and schedules, density updates, release) and the
+// device-memory pool and table sets behind them.  The batch, surrogate and
+// gamma entry points are in api_batch.hip, api_mlp.hip and api_gamma.hip;
+// error reporting and the shared checks in api_common.hip.
 //
 // Responsibilities: argument validation (pure host, before any HIP call),
 // device buffers owned by the geometry handle, packing of the commissioned
 // tables into the layouts the kernels read, and kernel launches.  All of the
 // method's per-voxel and per-beamlet arithmetic runs in the kernels.
-#include "fspb.h"
-#include "gamma.h"
-#include "kernels.h"
-#include "mlp.h"
+#include "api_internal.h"
 
 #include <float.h>
 #include <math.h>
-#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <deque>
 #include <functional>
-#include <cmath>
 #include <map>
 #include <new>
-#include <mutex>
-#include <string>
-#include <vector>
 
-using namespace fspb;
+namespace fspb {
 
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(FSPB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
 
 // Device memory comes from a per-device caching pool: blocks freed by
 // fspb_destroy are kept (by size class) and handed to the next geometry, so a
@@ -108,6 +87,8 @@ void reap_locked(size_t limit) {
 int g_alloc_count = 0;
 std::string g_alloc_env;
 
+}  // namespace
+
 int pool_alloc(int dev, void** p, size_t bytes, size_t* cls_out) {
     *p = nullptr;
     const char* inj = getenv("FSPB_TEST_FAIL_ALLOC");
@@ -166,38 +147,11 @@ void pool_free(int dev, void* p, size_t cls) {
     pool().cached += cls;
 }
 
-bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
-
-int check_table(const fspb_table1d& t, const char* name) {
-    if (t.n < 1 || !t.v) return fail(FSPB_E_ARG, "table %s: needs n >= 1 and values", name);
-    if (!isfinite(t.start) || (t.n > 1 && !finite_pos(t.step)))
-        return fail(FSPB_E_ARG, "table %s: start must be finite and step > 0", name);
-    return FSPB_OK;
-}
-
-}  // namespace
-
-// Packed commissioned tables (water, A and density tables in the layouts the
-// kernels read), shared by every geometry built from bitwise-identical tables
-// on a device.  Sets stay while a geometry uses them; unused ones are kept
-// (up to kMaxIdleTableSets per process) for the next plan, and
-// fspb_release_cached_memory frees them.
-struct TableSet {
-    int device = 0;
-    std::vector<uint32_t> key;   // every table parameter and value, bitwise
-    float4* dtab = nullptr;
-    float4* atab = nullptr;
-    float* denstab = nullptr;
-    DensTabs dens{};
-    float w2c = 1.0f;            // b2 = w2c b1 at every sample when w2_one
-    int w2_one = 0;
-    int refs = 0;
-    unsigned long long last_use = 0;
-};
+std::mutex g_tables_mu;
 
 namespace {
+
 constexpr int kMaxIdleTableSets = 8;
-std::mutex g_tables_mu;
 unsigned long long g_tables_clock = 0;
 std::vector<TableSet*>& table_sets() {
     static auto* v = new std::vector<TableSet*>();   // never destroyed
@@ -209,121 +163,6 @@ void free_table_set(TableSet* t) {
     (void)hipFree(t->denstab);
     delete t;
 }
-}  // namespace
-
-struct fspb_geometry {
-    int device = 0;
-    PlanConst P{};
-    DensTabs dens{};
-    int n_beams = 0, n_beamlets = 0, k_stride = 0;
-    int dc_created = 0, dc_enabled = 0;
-    int smooth_r[3] = {0, 0, 0};
-    float sample_step = 0.0f;
-    size_t device_bytes = 0;
-    // device buffers
-    float* rhohat = nullptr;
-    float4* fac = nullptr;
-    BeamDesc* beams = nullptr;
-    BeamIn* beam_in = nullptr;
-    Frame64* frames = nullptr;
-    BeamletDesc* desc = nullptr;
-    TraceInfo* tinfo = nullptr;
-    float4* dtab = nullptr;
-    float4* atab = nullptr;
-    float* denstab = nullptr;
-    float2* tT = nullptr;
-    float4* tTW = nullptr;    // DC only: depth + first weight-drift table (16-byte entries)
-    float2* tW2 = nullptr;    // DC only: second weight-drift table (8-byte entries, same index)
-    float4* sid = nullptr;    // exact (Siddon) depth tables, when the plan asks for them
-    int siddon = 0, sid_stride = 0;
-    float* w3 = nullptr;
-    int* counts = nullptr;
-    int* order = nullptr;      // bricks in decreasing order of estimated work
-    int* cost = nullptr;       // estimated work per brick (candidate beamlets)
-    float* adj_part = nullptr; // the adjoint's per-(slab, beamlet) partial sums
-    unsigned* surr_live = nullptr;   // the surrogate's listed rows (allocated on first use)
-    unsigned* surr_count = nullptr;
-    float4* surr_quad = nullptr;     // the CT's 2x2 neighbourhoods, per call
-    int adj_slab = 0;          // the adjoint's slab thickness (0: adjoint_slab(P))
-    int* adj_queue = nullptr;  // the adjoint's per-XCD unit counters
-    // per-beam schedule (allocated on first use): sorted items, XCD runs,
-    // their scratch, and the per-beam partial doses [n_beams][stride]
-    SplitSched split{};
-    float* planes = nullptr;
-    float* tmp0 = nullptr;     // smoothing intermediates (alias the depth tables when they fit)
-    float* tmp1 = nullptr;
-    float* rho = nullptr;      // the handle's copy of the CT it was created from
-    // creation work is asynchronous: `ready` is recorded on `ready_stream`
-    // after it; first use on another stream (or from the host) waits for it
-    hipEvent_t ready = nullptr;
-    hipStream_t ready_stream = nullptr;
-    bool pending = false;
-    // the streams of the handle's queued work (release waits for each); more
-    // than kMaxHandleStreams, or work captured into a graph, make
-    // fspb_destroy wait for the whole device
-    std::vector<hipStream_t> streams;
-    bool many_streams = false;
-    TileCfg tile;
-    std::vector<int> h_cost;   // host copy of cost (fetched when a batch needs it)
-    bool h_cost_valid = false;
-    TraceGrid tg{};
-    TraceParams tp{};
-    int n_cu = 0;              // the device's compute units
-    unsigned long long* partial = nullptr;
-    unsigned long long* total = nullptr;
-    // host copies
-    std::vector<BeamletDesc> h_desc;
-    std::vector<Frame64> h_frames;
-    std::vector<TraceInfo> h_info;
-    int k_max = 0, n_hit = 0, n_amb = 0;
-    bool host_ready = false;               // host copies are fetched on first use
-    std::vector<std::pair<void*, size_t>> blocks;   // pool blocks owned by the handle
-
-    int alloc(void** p, size_t bytes) {
-        size_t cls = 0;
-        int rc = pool_alloc(device, p, bytes, &cls);
-        if (rc == FSPB_OK) {
-            blocks.push_back({*p, cls});
-            device_bytes += cls;
-        }
-        return rc;
-    }
-
-    DoseArgs args() const {
-        DoseArgs a;
-        a.P = P;
-        a.P.dc = dc_enabled;
-        a.beams = beams;
-        a.bl = desc;
-        a.fac = fac;
-        a.dtab = dtab;
-        a.atab = atab;
-        a.tT = tT;
-        a.tTW = tTW;
-        a.tW2 = tW2;
-        a.sid = sid;
-        return a;
-    }
-
-    TableSet* tabs = nullptr;      // shared commissioned tables (not owned)
-
-    void release() {
-        if (ready) (void)hipEventDestroy(ready);
-        ready = nullptr;
-        pending = false;
-        for (auto& b : blocks) pool_free(device, b.first, b.second);
-        blocks.clear();
-        if (tabs) {
-            std::lock_guard<std::mutex> lk(g_tables_mu);
-            --tabs->refs;
-            tabs = nullptr;
-        }
-    }
-
-    int fetch_host() const;
-};
-
-namespace {
 
 int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_tables* t,
              const fspb_options* o) {
@@ -408,34 +247,12 @@ int validate(const fspb_ct* ct, int n_beams, const fspb_beam* beams, const fspb_
     return FSPB_OK;
 }
 
-int check_device(int* dev) {
-    // the architecture of each device is looked up once (the property query
-    // is slow compared with creating a plan)
-    constexpr int kMaxDevices = 64;
-    static std::atomic<int> arch_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
-    int n = 0;
-    hipError_t e = hipGetDeviceCount(&n);
-    if (e != hipSuccess || n < 1) {
-        (void)hipGetLastError();
-        return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
-    }
-    HIP_TRY(hipGetDevice(dev));
-    const int v = (*dev >= 0 && *dev < kMaxDevices) ? arch_ok[*dev].load() : 0;
-    if (v == 1) return FSPB_OK;
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, *dev));
-    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (*dev >= 0 && *dev < kMaxDevices) arch_ok[*dev].store(ok ? 1 : -1);
-    if (!ok)
-        return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
-                    prop.gcnArchName);
-    return FSPB_OK;
-}
-
 }  // namespace
 
+}  // namespace fspb
+
 // Waits (on the host) for the handle's creation work.
-static int settle_host(fspb_geometry* g) {
+int settle_host(fspb_geometry* g) {
     if (!g->pending) return FSPB_OK;
     if (hipEventQuery(g->ready) != hipSuccess) HIP_TRY(hipEventSynchronize(g->ready));
     g->pending = false;
@@ -467,7 +284,7 @@ static bool note_stream(fspb_geometry* g, hipStream_t s) {
 // Orders work on stream s after the handle's creation work: on the creation
 // stream that order holds already; another stream waits for the ready event
 // on the device (or, while capturing a graph, on the host).
-static int settle(fspb_geometry* g, hipStream_t s) {
+int settle(fspb_geometry* g, hipStream_t s) {
     const bool cap = note_stream(g, s);
     if (!g->pending || s == g->ready_stream) return FSPB_OK;
     if (hipEventQuery(g->ready) == hipSuccess) {
@@ -501,21 +318,18 @@ int fspb_geometry::fetch_host() const {
     return FSPB_OK;
 }
 
-extern "C" {
-
-const char* fspb_error_string(int code) {
-    switch (code) {
-        case FSPB_OK: return "success";
-        case FSPB_E_ARG: return "invalid argument";
-        case FSPB_E_HIP: return "HIP runtime error";
-        case FSPB_E_NOMEM: return "out of memory";
-        case FSPB_E_STATE: return "invalid state for this handle";
-        case FSPB_E_UNSUPPORTED: return "unsupported device";
-        default: return "unknown error";
-    }
+int fetch_cost(fspb_geometry* G, hipStream_t s) {
+    if (G->h_cost_valid) return FSPB_OK;
+    const long nb = brick_count(G->P, G->tile.shape);
+    G->h_cost.assign(nb, 0);
+    HIP_TRY(hipMemcpyAsync(G->h_cost.data(), G->cost, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    G->h_cost_valid = true;
+    return FSPB_OK;
 }
 
-const char* fspb_last_error(void) { return g_last_error.c_str(); }
+extern "C" {
+
 
 // Brick schedule for the handle's tile shape: estimated work per brick
 // (candidate beamlets), longest first, built on the device (asynchronous).
@@ -549,16 +363,6 @@ static int build_order(fspb_geometry* G, hipStream_t s) {
     return FSPB_OK;
 }
 
-// Host copy of the brick costs for the batch scheduler (synchronises s).
-static int fetch_cost(fspb_geometry* G, hipStream_t s) {
-    if (G->h_cost_valid) return FSPB_OK;
-    const long nb = brick_count(G->P, G->tile.shape);
-    G->h_cost.assign(nb, 0);
-    HIP_TRY(hipMemcpyAsync(G->h_cost.data(), G->cost, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    G->h_cost_valid = true;
-    return FSPB_OK;
-}
 
 // Packs the commissioned tables into the kernels' layouts (once per
 // distinct set and device):
@@ -1010,7 +814,7 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         return rc;
     }
     *out = G;
-    g_last_error.clear();
+    clear_last_error();
     return FSPB_OK;
 }
 
@@ -1564,713 +1368,3 @@ int fspb_update_density(fspb_geometry* g, const float* density, void* stream) {
 
 }  // extern "C"
 
-// ---------------------------------------------------------------------------
-// Batches: many plans in one persistent launch.
-struct fspb_batch {
-    int device = 0;
-    int n_plans = 0, n_waves = 0;
-    int dc = kPlain;                 // correction mode shared by every plan
-    TileCfg tile;
-    std::vector<fspb_geometry*> plans;
-    std::vector<std::pair<void*, size_t>> blocks;
-    const float4* water = nullptr;   // the water table all plans share, else null
-    int water_n = 0;
-    DoseArgs* d_args = nullptr;
-    int2* d_items = nullptr;
-    int* d_begin = nullptr;
-    unsigned long long* ts_done = nullptr;
-    unsigned long long* ts_start = nullptr;
-    long n_items = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    double clock_khz = 100000.0;
-
-    int alloc(void** p, size_t bytes) {
-        size_t cls = 0;
-        int rc = pool_alloc(device, p, bytes, &cls);
-        if (rc == FSPB_OK) blocks.push_back({*p, cls});
-        return rc;
-    }
-    void release() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-        for (auto& b : blocks) pool_free(device, b.first, b.second);
-        blocks.clear();
-    }
-};
-
-static int batch_enqueue(fspb_batch* b, const float* const* fluence, float* const* dose,
-                         const float* const* density, hipStream_t s) {
-    for (int p = 0; p < b->n_plans; ++p)
-        if (!fluence[p] || !dose[p]) return fail(FSPB_E_ARG, "batch: NULL fluence or dose of plan %d", p);
-    if (density)
-        for (int p = 0; p < b->n_plans; ++p) {
-            int rc = fspb_update_density(b->plans[p], density[p], s);
-            if (rc) return rc;
-        }
-    BatchPtrs ptrs = {};
-    for (int p = 0; p < b->n_plans; ++p) {
-        ptrs.fluence[p] = fluence[p];
-        ptrs.dose[p] = dose[p];
-    }
-    launch_fill_u64(b->ts_done, (long)b->n_plans * b->n_waves, 0ULL, s);
-    HIP_TRY(hipGetLastError());
-    launch_forward_batch(b->dc, b->tile, b->d_args, b->d_items, b->d_begin, b->n_waves, ptrs,
-                         b->ts_done, b->ts_start, b->water, b->water_n, s);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-extern "C" {
-
-int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_per_block,
-                      int waves_per_cu, int policy, void* stream, fspb_batch** out) {
-    if (!out) return fail(FSPB_E_ARG, "batch_create: out is NULL");
-    *out = nullptr;
-    if (n < 1 || !geoms) return fail(FSPB_E_ARG, "batch_create: need n >= 1 geometries");
-    if (n > kMaxBatchPlans) return fail(FSPB_E_ARG, "batch_create: at most %d plans", kMaxBatchPlans);
-    if (shape < 0 || shape >= kNumShapes) return fail(FSPB_E_ARG, "batch_create: bad shape");
-    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
-        waves_per_block != kLdsWaves)
-        return fail(FSPB_E_ARG, "batch_create: waves_per_block must be 1, 2, 4 or 8");
-    if (waves_per_cu < 1 || waves_per_cu > 32)
-        return fail(FSPB_E_ARG, "batch_create: waves_per_cu must be 1..32");
-    if (policy != FSPB_SCHEDULE_THROUGHPUT && policy != FSPB_SCHEDULE_LATENCY)
-        return fail(FSPB_E_ARG, "batch_create: unknown schedule policy %d", policy);
-    for (int p = 0; p < n; ++p) {
-        if (!geoms[p]) return fail(FSPB_E_ARG, "batch_create: geometry %d is NULL", p);
-        if (int rc = settle_host(geoms[p])) return rc;   // the batch may run on any stream
-        if (geoms[p]->siddon)
-            return fail(FSPB_E_STATE, "batch_create: geometry %d uses exact depth tables", p);
-        if (geoms[p]->dc_enabled != geoms[0]->dc_enabled)
-            return fail(FSPB_E_ARG, "batch_create: plans must share the density-correction mode");
-    }
-    hipStream_t s = (hipStream_t)stream;
-    fspb_batch* B = new (std::nothrow) fspb_batch();
-    if (!B) return fail(FSPB_E_NOMEM, "host allocation failed");
-    B->device = geoms[0]->device;
-    B->n_plans = n;
-    B->dc = kPlain;
-    if (geoms[0]->dc_enabled) {
-        B->dc = kDcOneDrift;
-        for (int p = 0; p < n; ++p)
-            if (!geoms[p]->P.w2_one) B->dc = kDcTwoDrift;
-    }
-    B->tile.shape = shape;
-    B->tile.waves_per_block = waves_per_block;
-    B->plans.assign(geoms, geoms + n);
-    // one shared water table (plans built from the same commissioned tables
-    // share the device copy) can be staged in LDS by the persistent kernel
-    B->water = geoms[0]->dtab;
-    B->water_n = geoms[0]->P.dt_n;
-    for (int p = 1; p < n; ++p)
-        if (geoms[p]->dtab != B->water) B->water = nullptr;
-    auto bail = [&](int rc) {
-        (void)hipStreamSynchronize(s);
-        B->release();
-        delete B;
-        return rc;
-    };
-    int cus = 256;
-    {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, B->device) == hipSuccess) cus = prop.multiProcessorCount;
-        int khz = 0;
-        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, B->device) == hipSuccess && khz > 0)
-            B->clock_khz = khz;
-    }
-    B->n_waves = waves_per_cu * cus;
-    // items: every brick of every plan with its estimated work for the batch
-    // shape; longest-processing-time-first assignment to the waves
-    struct Item {
-        int plan, brick, cost;
-    };
-    std::vector<Item> items;
-    for (int p = 0; p < n; ++p) {
-        fspb_geometry* g = geoms[p];
-        if (g->tile.shape != shape) {
-            int rc = fspb_set_tile(g, shape, g->tile.waves_per_block, stream);
-            if (rc) return bail(rc);
-        }
-        const long nb = brick_count(g->P, shape);
-        int rc = fetch_cost(g, (hipStream_t)stream);
-        if (rc) return bail(rc);
-        for (long q = 0; q < nb; ++q) items.push_back({p, (int)q, g->h_cost[q] + 4});
-    }
-    if (policy == FSPB_SCHEDULE_THROUGHPUT) {
-        // one longest-first list over all plans: shortest makespan
-        std::stable_sort(items.begin(), items.end(),
-                         [](const Item& x, const Item& y) { return x.cost > y.cost; });
-    } else {
-        // plans in increasing order of total work, each plan's bricks
-        // longest-first: small plans complete early
-        std::vector<long long> tot(n, 0);
-        for (const Item& it : items) tot[it.plan] += it.cost;
-        std::vector<int> rank(n);
-        std::vector<int> ord(n);
-        for (int p = 0; p < n; ++p) ord[p] = p;
-        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return tot[x] < tot[y]; });
-        for (int r = 0; r < n; ++r) rank[ord[r]] = r;
-        std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) {
-            if (rank[x.plan] != rank[y.plan]) return rank[x.plan] < rank[y.plan];
-            return x.cost > y.cost;
-        });
-    }
-    std::vector<std::vector<int2>> per(B->n_waves);
-    std::vector<std::pair<long long, int>> heap;
-    heap.reserve(B->n_waves);
-    for (int w = 0; w < B->n_waves; ++w) heap.push_back({0LL, w});
-    auto cmp = [](const std::pair<long long, int>& a, const std::pair<long long, int>& b) {
-        return a.first > b.first || (a.first == b.first && a.second > b.second);
-    };
-    std::make_heap(heap.begin(), heap.end(), cmp);
-    for (const Item& it : items) {
-        std::pop_heap(heap.begin(), heap.end(), cmp);
-        auto& top = heap.back();
-        per[top.second].push_back(make_int2(it.plan, it.brick));
-        top.first += it.cost;
-        std::push_heap(heap.begin(), heap.end(), cmp);
-    }
-    std::vector<int2> flat;
-    std::vector<int> begin(B->n_waves + 1, 0);
-    for (int w = 0; w < B->n_waves; ++w) {
-        begin[w] = (int)flat.size();
-        flat.insert(flat.end(), per[w].begin(), per[w].end());
-    }
-    begin[B->n_waves] = (int)flat.size();
-    B->n_items = (long)flat.size();
-    std::vector<DoseArgs> args(n);
-    for (int p = 0; p < n; ++p) args[p] = geoms[p]->args();
-    int rc;
-    if ((rc = B->alloc((void**)&B->d_args, sizeof(DoseArgs) * n))) return bail(rc);
-    if ((rc = B->alloc((void**)&B->d_items, sizeof(int2) * std::max<size_t>(flat.size(), 1)))) return bail(rc);
-    if ((rc = B->alloc((void**)&B->d_begin, sizeof(int) * begin.size()))) return bail(rc);
-    if ((rc = B->alloc((void**)&B->ts_done, sizeof(unsigned long long) * (size_t)n * B->n_waves))) return bail(rc);
-    if ((rc = B->alloc((void**)&B->ts_start, sizeof(unsigned long long) * B->n_waves))) return bail(rc);
-    if (hipMemcpyAsync(B->d_args, args.data(), sizeof(DoseArgs) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(B->d_items, flat.data(), sizeof(int2) * flat.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(B->d_begin, begin.data(), sizeof(int) * begin.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return bail(fail(FSPB_E_HIP, "batch_create: copy failed"));
-    *out = B;
-    return FSPB_OK;
-}
-
-int fspb_batch_forward(fspb_batch* b, const float* const* fluence, float* const* dose, void* stream) {
-    if (!b || !fluence || !dose) return fail(FSPB_E_ARG, "batch_forward: NULL argument");
-    return batch_enqueue(b, fluence, dose, nullptr, (hipStream_t)stream);
-}
-
-int fspb_batch_capture(fspb_batch* b, const float* const* fluence, float* const* dose,
-                       const float* const* density, void* stream) {
-    if (!b || !fluence || !dose) return fail(FSPB_E_ARG, "batch_capture: NULL argument");
-    if (!stream) return fail(FSPB_E_ARG, "batch_capture: capture needs a non-null stream");
-    hipStream_t s = (hipStream_t)stream;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = batch_enqueue(b, fluence, dose, density, s);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
-    if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-    }
-    if (e != hipSuccess) return fail(FSPB_E_HIP, "batch_capture: %s", hipGetErrorString(e));
-    b->graph = graph;
-    HIP_TRY(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
-    return FSPB_OK;
-}
-
-int fspb_batch_replay(fspb_batch* b, void* stream) {
-    if (!b) return fail(FSPB_E_ARG, "batch_replay: NULL batch");
-    if (!b->exec) return fail(FSPB_E_STATE, "batch_replay: nothing captured");
-    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
-    return FSPB_OK;
-}
-
-int fspb_batch_latencies(const fspb_batch* b, double* plan_ms, double* total_ms, void* stream) {
-    if (!b) return fail(FSPB_E_ARG, "batch_latencies: NULL batch");
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    std::vector<unsigned long long> done((size_t)b->n_plans * b->n_waves), start(b->n_waves);
-    HIP_TRY(hipMemcpy(done.data(), b->ts_done, sizeof(unsigned long long) * done.size(), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(start.data(), b->ts_start, sizeof(unsigned long long) * start.size(), hipMemcpyDeviceToHost));
-    unsigned long long t0 = ~0ULL, tend = 0;
-    for (unsigned long long v : start) t0 = std::min(t0, v);
-    for (int p = 0; p < b->n_plans; ++p) {
-        unsigned long long m = 0;
-        for (int w = 0; w < b->n_waves; ++w) m = std::max(m, done[(size_t)p * b->n_waves + w]);
-        tend = std::max(tend, m);
-        if (plan_ms) plan_ms[p] = m > t0 ? (double)(m - t0) / b->clock_khz : 0.0;
-    }
-    if (total_ms) *total_ms = tend > t0 ? (double)(tend - t0) / b->clock_khz : 0.0;
-    return FSPB_OK;
-}
-
-int fspb_batch_info(const fspb_batch* b, int* n_waves, long long* n_items) {
-    if (!b) return fail(FSPB_E_ARG, "batch_info: NULL batch");
-    if (n_waves) *n_waves = b->n_waves;
-    if (n_items) *n_items = b->n_items;
-    return FSPB_OK;
-}
-
-void fspb_batch_destroy(fspb_batch* b) {
-    if (!b) return;
-    (void)hipDeviceSynchronize();
-    b->release();
-    delete b;
-}
-
-}  // extern "C"
-
-// ===========================================================================
-// Learned surrogate: network state and the surrogate entry points.
-struct fspb_mlp {
-    int device = 0;
-    float* master = nullptr;   // FP32 parameters (flat layout of fspb.h)
-    float* am = nullptr;       // Adam moments
-    float* av = nullptr;
-    __bf16* w1t = nullptr;     // BF16 copies in the layouts the kernels read
-    __bf16* w2t = nullptr;
-    __bf16* w2r = nullptr;
-    __bf16* w3t = nullptr;
-    __bf16* w3r = nullptr;
-    float* grad_parts = nullptr;   // per-workgroup gradients of one launch
-    float* loss_parts = nullptr;
-    int part_tiles = 0;
-    size_t grad_cls = 0, loss_cls = 0;
-    long long step = 0;
-    SurrogateScale sc{};
-    SurrogateGuard gd{};
-    std::vector<std::pair<void*, size_t>> blocks;
-
-    int alloc(void** p, size_t bytes) {
-        size_t cls = 0;
-        int rc = pool_alloc(device, p, bytes, &cls);
-        if (rc == FSPB_OK) blocks.push_back({*p, cls});
-        return rc;
-    }
-    MlpWeights weights() const {
-        MlpWeights W;
-        W.w1t = W.w1t_rw = w1t;
-        W.w2t = W.w2t_rw = w2t;
-        W.w2r = W.w2r_rw = w2r;
-        W.w3t = W.w3t_rw = w3t;
-        W.w3r = W.w3r_rw = w3r;
-        W.b1 = master + kOffB1;
-        W.b2 = master + kOffB2;
-        W.b3 = master + kOffB3;
-        return W;
-    }
-    // per-workgroup scratch for a launch over n rows (grown on demand; the
-    // old buffers are returned only after the device has finished with them)
-    int ensure_parts(long long n) {
-        const int tiles = mlp_tiles((long)n);
-        if (tiles <= part_tiles) return FSPB_OK;
-        HIP_TRY(hipDeviceSynchronize());
-        pool_free(device, grad_parts, grad_cls);
-        pool_free(device, loss_parts, loss_cls);
-        grad_parts = loss_parts = nullptr;
-        part_tiles = 0;
-        int rc = pool_alloc(device, (void**)&grad_parts, sizeof(float) * (size_t)tiles * kMlpParams,
-                            &grad_cls);
-        if (rc != FSPB_OK) return rc;
-        rc = pool_alloc(device, (void**)&loss_parts, sizeof(float) * (size_t)tiles, &loss_cls);
-        if (rc != FSPB_OK) {
-            pool_free(device, grad_parts, grad_cls);
-            grad_parts = nullptr;
-            return rc;
-        }
-        part_tiles = tiles;
-        return FSPB_OK;
-    }
-    void release() {
-        pool_free(device, grad_parts, grad_cls);
-        pool_free(device, loss_parts, loss_cls);
-        for (auto& b : blocks) pool_free(device, b.first, b.second);
-        blocks.clear();
-    }
-};
-
-namespace {
-
-int check_rows(long long n, bool allow_zero, const char* what) {
-    if (n < (allow_zero ? 0 : 1) || n > FSPB_MLP_MAX_ROWS)
-        return fail(FSPB_E_ARG, "%s: row count %lld outside [%d, %d]", what, n, allow_zero ? 0 : 1,
-                    FSPB_MLP_MAX_ROWS);
-    return FSPB_OK;
-}
-
-int check_same_device(int dev, const char* what) {
-    int cur = -1;
-    HIP_TRY(hipGetDevice(&cur));
-    if (cur != dev) return fail(FSPB_E_STATE, "%s: handle lives on device %d, current is %d", what, dev, cur);
-    return FSPB_OK;
-}
-
-int upload_state(fspb_mlp* m, const float* params, const float* am, const float* av) {
-    std::vector<float> zero(kMlpParams, 0.0f);
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(m->master, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m->am, am ? am : zero.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m->av, av ? av : zero.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
-    launch_mlp_sync(m->master, m->weights(), 0);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipDeviceSynchronize());
-    return FSPB_OK;
-}
-
-int check_finite(const float* v, int n, const char* what) {
-    for (int q = 0; q < n; ++q)
-        if (!isfinite(v[q])) return fail(FSPB_E_ARG, "%s: value %d is not finite", what, q);
-    return FSPB_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int fspb_mlp_create(const float* params, fspb_mlp** out) {
-    if (!out) return fail(FSPB_E_ARG, "mlp_create: NULL out");
-    *out = nullptr;
-    if (!params) return fail(FSPB_E_ARG, "mlp_create: NULL params");
-    int rc = check_finite(params, kMlpParams, "mlp_create: params");
-    if (rc != FSPB_OK) return rc;
-    int dev = 0;
-    if ((rc = check_device(&dev)) != FSPB_OK) return rc;
-    fspb_mlp* m = new (std::nothrow) fspb_mlp();
-    if (!m) return fail(FSPB_E_NOMEM, "mlp_create: host allocation failed");
-    m->device = dev;
-    for (int c = 0; c < kMlpOut; ++c) {
-        m->sc.mean[c] = 0.0f;
-        m->sc.stdev[c] = 1.0f;
-        m->gd.band_lo[c] = -FLT_MAX;
-        m->gd.band_hi[c] = FLT_MAX;
-    }
-    m->gd.rho_lo = -FLT_MAX;
-    m->gd.rho_hi = FLT_MAX;
-    m->gd.het_max = FLT_MAX;
-    const size_t fp = sizeof(float) * kMlpParams;
-    if ((rc = m->alloc((void**)&m->master, fp)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->am, fp)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->av, fp)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->w1t, sizeof(__bf16) * kW1tN)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->w2t, sizeof(__bf16) * kW2N)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->w2r, sizeof(__bf16) * kW2N)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->w3t, sizeof(__bf16) * kW3tN)) != FSPB_OK ||
-        (rc = m->alloc((void**)&m->w3r, sizeof(__bf16) * kW3rN)) != FSPB_OK ||
-        (rc = upload_state(m, params, nullptr, nullptr)) != FSPB_OK) {
-        m->release();
-        delete m;
-        return rc;
-    }
-    *out = m;
-    return FSPB_OK;
-}
-
-int fspb_mlp_set_scaling(fspb_mlp* m, const float* mean, const float* stdev) {
-    if (!m || !mean || !stdev) return fail(FSPB_E_ARG, "mlp_set_scaling: NULL argument");
-    for (int c = 0; c < kMlpOut; ++c)
-        if (!isfinite(mean[c]) || !finite_pos(stdev[c]))
-            return fail(FSPB_E_ARG, "mlp_set_scaling: output %d needs a finite mean and std > 0", c);
-    for (int c = 0; c < kMlpOut; ++c) {
-        m->sc.mean[c] = mean[c];
-        m->sc.stdev[c] = stdev[c];
-    }
-    return FSPB_OK;
-}
-
-int fspb_mlp_set_guard(fspb_mlp* m, const fspb_surrogate_guard* g) {
-    if (!m || !g) return fail(FSPB_E_ARG, "mlp_set_guard: NULL argument");
-    if (std::isnan(g->rho_lo) || std::isnan(g->rho_hi) || std::isnan(g->het_max))
-        return fail(FSPB_E_ARG, "mlp_set_guard: NaN bound");
-    for (int c = 0; c < kMlpOut; ++c)
-        if (std::isnan(g->band_lo[c]) || std::isnan(g->band_hi[c]))
-            return fail(FSPB_E_ARG, "mlp_set_guard: NaN band for output %d", c);
-    m->gd.rho_lo = g->rho_lo;
-    m->gd.rho_hi = g->rho_hi;
-    m->gd.het_max = g->het_max;
-    for (int c = 0; c < kMlpOut; ++c) {
-        m->gd.band_lo[c] = g->band_lo[c];
-        m->gd.band_hi[c] = g->band_hi[c];
-    }
-    return FSPB_OK;
-}
-
-int fspb_mlp_loss_grad(fspb_mlp* m, const uint16_t* x, const float* t, long long n, float* grad,
-                       float* loss, void* stream) {
-    if (!m || !x || !t) return fail(FSPB_E_ARG, "mlp_loss_grad: NULL argument");
-    int rc;
-    if ((rc = check_rows(n, false, "mlp_loss_grad")) != FSPB_OK) return rc;
-    if ((rc = check_same_device(m->device, "mlp_loss_grad")) != FSPB_OK) return rc;
-    if ((rc = m->ensure_parts(n)) != FSPB_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int tiles = mlp_tiles((long)n);
-    launch_mlp_train((const __bf16*)x, t, (long)n, m->weights(), m->grad_parts, m->loss_parts, s);
-    HIP_TRY(hipGetLastError());
-    if (grad) launch_mlp_grad_sum(m->grad_parts, tiles, grad, s);
-    if (loss) launch_mlp_loss_sum(m->loss_parts, tiles, loss, s);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-int fspb_mlp_train_step(fspb_mlp* m, const uint16_t* x, const float* t, long long n,
-                        const fspb_adam* opt, float* loss, void* stream) {
-    if (!m || !x || !t || !opt) return fail(FSPB_E_ARG, "mlp_train_step: NULL argument");
-    if (!finite_pos(opt->lr) || !(opt->beta1 >= 0.0f && opt->beta1 < 1.0f) ||
-        !(opt->beta2 >= 0.0f && opt->beta2 < 1.0f) || !finite_pos(opt->eps))
-        return fail(FSPB_E_ARG, "mlp_train_step: needs lr > 0, 0 <= beta < 1, eps > 0");
-    int rc;
-    if ((rc = check_rows(n, false, "mlp_train_step")) != FSPB_OK) return rc;
-    if ((rc = check_same_device(m->device, "mlp_train_step")) != FSPB_OK) return rc;
-    if ((rc = m->ensure_parts(n)) != FSPB_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int tiles = mlp_tiles((long)n);
-    const MlpWeights W = m->weights();
-    launch_mlp_train((const __bf16*)x, t, (long)n, W, m->grad_parts, m->loss_parts, s);
-    HIP_TRY(hipGetLastError());
-    if (loss) launch_mlp_loss_sum(m->loss_parts, tiles, loss, s);
-    const long long k = m->step + 1;
-    AdamParams ap;
-    ap.lr = opt->lr;
-    ap.beta1 = opt->beta1;
-    ap.beta2 = opt->beta2;
-    ap.eps = opt->eps;
-    ap.bc1 = (float)(1.0 - pow((double)opt->beta1, (double)k));
-    ap.bc2 = (float)(1.0 - pow((double)opt->beta2, (double)k));
-    launch_mlp_adam(m->grad_parts, tiles, W, m->master, m->am, m->av, ap, s);
-    HIP_TRY(hipGetLastError());
-    m->step = k;
-    return FSPB_OK;
-}
-
-int fspb_mlp_predict(fspb_mlp* m, const uint16_t* x, long long n, float* y, void* stream) {
-    if (!m) return fail(FSPB_E_ARG, "mlp_predict: NULL handle");
-    int rc;
-    if ((rc = check_rows(n, true, "mlp_predict")) != FSPB_OK) return rc;
-    if (n == 0) return FSPB_OK;
-    if (!x || !y) return fail(FSPB_E_ARG, "mlp_predict: NULL argument");
-    if ((rc = check_same_device(m->device, "mlp_predict")) != FSPB_OK) return rc;
-    launch_mlp_forward((const __bf16*)x, (long)n, m->weights(), y, (hipStream_t)stream);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-int fspb_mlp_get_state(const fspb_mlp* m, float* params, float* adam_m, float* adam_v,
-                       long long* step) {
-    if (!m) return fail(FSPB_E_ARG, "mlp_get_state: NULL handle");
-    HIP_TRY(hipDeviceSynchronize());
-    const size_t fp = sizeof(float) * kMlpParams;
-    if (params) HIP_TRY(hipMemcpy(params, m->master, fp, hipMemcpyDeviceToHost));
-    if (adam_m) HIP_TRY(hipMemcpy(adam_m, m->am, fp, hipMemcpyDeviceToHost));
-    if (adam_v) HIP_TRY(hipMemcpy(adam_v, m->av, fp, hipMemcpyDeviceToHost));
-    if (step) *step = m->step;
-    return FSPB_OK;
-}
-
-int fspb_mlp_set_state(fspb_mlp* m, const float* params, const float* adam_m,
-                       const float* adam_v, long long step) {
-    if (!m || !params) return fail(FSPB_E_ARG, "mlp_set_state: NULL argument");
-    if (step < 0) return fail(FSPB_E_ARG, "mlp_set_state: negative step");
-    int rc = check_finite(params, kMlpParams, "mlp_set_state: params");
-    if (rc == FSPB_OK && adam_m) rc = check_finite(adam_m, kMlpParams, "mlp_set_state: adam_m");
-    if (rc == FSPB_OK && adam_v) rc = check_finite(adam_v, kMlpParams, "mlp_set_state: adam_v");
-    if (rc != FSPB_OK) return rc;
-    if ((rc = check_same_device(m->device, "mlp_set_state")) != FSPB_OK) return rc;
-    if ((rc = upload_state(m, params, adam_m, adam_v)) != FSPB_OK) return rc;
-    m->step = step;
-    return FSPB_OK;
-}
-
-void fspb_mlp_destroy(fspb_mlp* m) {
-    if (!m) return;
-    (void)hipDeviceSynchronize();
-    m->release();
-    delete m;
-}
-
-static int check_surrogate_geometry(const fspb_geometry* g, const char* what) {
-    if (!g) return fail(FSPB_E_ARG, "%s: NULL geometry", what);
-    if (!g->dc_created)
-        return fail(FSPB_E_STATE, "%s: the geometry was created without density correction", what);
-    if (g->siddon) return fail(FSPB_E_STATE, "%s: not available with exact depth tables", what);
-    // row ids are 32-bit, the gathers address the CT with 32-bit byte offsets
-    // and index its rows with 24-bit multiplies
-    const long long nv = (long long)g->P.nx * g->P.ny * g->P.nz;
-    if (nv >= (1LL << 30) || nv * g->n_beams >= (1LL << 32) ||
-        (long long)g->P.ny * g->P.nz >= (1LL << 24) || g->P.nx >= (1 << 24))
-        return fail(FSPB_E_ARG, "%s: %lld voxels x %d beams exceed the surrogate's row range", what,
-                    nv, g->n_beams);
-    return check_same_device(g->device, what);
-}
-
-int fspb_surrogate_samples(fspb_geometry* g, const float* density, const int* rows, long long n,
-                           uint16_t* x, float* t, int* valid, void* stream) {
-    int rc;
-    if ((rc = check_surrogate_geometry(g, "surrogate_samples")) != FSPB_OK) return rc;
-    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
-    if (n < 0 || n > (1LL << 30)) return fail(FSPB_E_ARG, "surrogate_samples: bad row count %lld", n);
-    if (n == 0) return FSPB_OK;
-    if (!density || !rows || !x || !t || !valid)
-        return fail(FSPB_E_ARG, "surrogate_samples: NULL argument");
-    launch_surrogate_samples(g->args(), density, (const int2*)rows, (long)n, (__bf16*)x, t, valid,
-                             (hipStream_t)stream);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* density, float* prm,
-                         void* stream) {
-    int rc;
-    if ((rc = check_surrogate_geometry(g, "surrogate_infer")) != FSPB_OK) return rc;
-    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
-    if (!m || !density || !prm) return fail(FSPB_E_ARG, "surrogate_infer: NULL argument");
-    if (m->device != g->device) return fail(FSPB_E_STATE, "surrogate_infer: handles on different devices");
-    if (!g->surr_live) {
-        const size_t rows = (size_t)g->P.nx * g->P.ny * g->P.nz * g->n_beams;
-        if ((rc = g->alloc((void**)&g->surr_live, sizeof(unsigned) * rows)) != FSPB_OK ||
-            (rc = g->alloc((void**)&g->surr_count, 256)) != FSPB_OK ||
-            (rc = g->alloc((void**)&g->surr_quad,
-                           sizeof(float4) * (size_t)g->P.nx * g->P.ny * g->P.nz)) != FSPB_OK)
-            return rc;
-    }
-    launch_surrogate_infer(g->args(), density, g->rhohat, m->weights(), m->sc, m->gd,
-                           (float4*)prm, g->surr_quad, g->surr_live, g->surr_count,
-                           (hipStream_t)stream);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-int fspb_forward_surrogate(fspb_geometry* g, const float* fluence, const float* prm, float* dose,
-                           void* stream) {
-    int rc;
-    if ((rc = check_surrogate_geometry(g, "forward_surrogate")) != FSPB_OK) return rc;
-    if ((rc = settle(g, (hipStream_t)stream)) != FSPB_OK) return rc;
-    if (!fluence || !prm || !dose) return fail(FSPB_E_ARG, "forward_surrogate: NULL argument");
-    launch_forward_surrogate(g->args(), g->tile, g->order, fluence, (const float4*)prm, dose,
-                             (hipStream_t)stream);
-    HIP_TRY(hipGetLastError());
-    return FSPB_OK;
-}
-
-}  // extern "C"
-
-// ===========================================================================
-// Gamma index.
-extern "C" int fspb_gamma(const float* ref, const float* eval, int nx, int ny, int nz, float dx,
-                          float dy, float dz, const fspb_gamma_params* params, float* gamma,
-                          fspb_gamma_stats* stats, void* stream) {
-    if (!ref || !eval) return fail(FSPB_E_ARG, "gamma: NULL dose grid");
-    if (nx < 1 || ny < 1 || nz < 1) return fail(FSPB_E_ARG, "gamma: grid sizes must be >= 1");
-    const long long nv = (long long)nx * ny * nz;
-    if (nv > (1LL << 31) - 1) return fail(FSPB_E_ARG, "gamma: grid of %lld voxels exceeds 2^31-1", nv);
-    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
-        return fail(FSPB_E_ARG, "gamma: voxel spacing must be finite and > 0");
-    fspb_gamma_params p{};
-    if (params) p = *params;
-    if (p.dist == 0) p.dist = 0.3f;
-    if (p.dose_frac == 0) p.dose_frac = 0.03f;
-    if (p.gamma_cap == 0) p.gamma_cap = 5.0f;
-    if (p.iso_frac == 0) p.iso_frac = 0.5f;
-    if (!finite_pos(p.dist) || !finite_pos(p.dose_frac) || !finite_pos(p.gamma_cap) ||
-        !isfinite(p.dose_max) || !isfinite(p.iso_frac))
-        return fail(FSPB_E_ARG, "gamma: criteria must be finite and > 0");
-    // offsets of the search sphere, shortest first
-    const double R = (double)p.gamma_cap * p.dist;
-    const int mx = (int)floor(R / dx), my = (int)floor(R / dy), mz = (int)floor(R / dz);
-    struct Off {
-        int i, j, k;
-        double d2;
-    };
-    std::vector<Off> offs;
-    for (int k = -mz; k <= mz; ++k)
-        for (int j = -my; j <= my; ++j)
-            for (int i = -mx; i <= mx; ++i) {
-                const double d2 = (i * (double)dx) * (i * (double)dx) + (j * (double)dy) * (j * (double)dy) +
-                                  (k * (double)dz) * (k * (double)dz);
-                if (d2 <= R * R) offs.push_back({i, j, k, d2});
-            }
-    if ((int)offs.size() > kMaxGammaOffsets)
-        return fail(FSPB_E_ARG, "gamma: search sphere of %zu offsets exceeds %d (reduce the cap)",
-                    offs.size(), kMaxGammaOffsets);
-    std::stable_sort(offs.begin(), offs.end(), [](const Off& a, const Off& b) { return a.d2 < b.d2; });
-    std::vector<int4> hoff(offs.size());
-    const double inv_dd2 = 1.0 / ((double)p.dist * p.dist);
-    for (size_t q = 0; q < offs.size(); ++q) {
-        const float d2 = (float)(offs[q].d2 * inv_dd2);
-        int bits;
-        memcpy(&bits, &d2, 4);
-        hoff[q] = make_int4(offs[q].i, offs[q].j, offs[q].k, bits);
-    }
-    int dev = 0, rc = check_device(&dev);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int n_part = 512;
-    struct Scratch {
-        int dev;
-        std::vector<std::pair<void*, size_t>> b;
-        ~Scratch() {
-            for (auto& x : b) pool_free(dev, x.first, x.second);
-        }
-        int get(void** p, size_t bytes) {
-            size_t cls = 0;
-            int r = pool_alloc(dev, p, bytes, &cls);
-            if (r == FSPB_OK) b.push_back({*p, cls});
-            return r;
-        }
-    } S{dev, {}};
-    int4* doff = nullptr;
-    float* fpart = nullptr;
-    float* dmax = nullptr;
-    GammaPart* gpart = nullptr;
-    GammaPart* gout = nullptr;
-    float* g = gamma;
-    if ((rc = S.get((void**)&doff, sizeof(int4) * hoff.size())) ||
-        (rc = S.get((void**)&fpart, sizeof(float) * n_part)) ||
-        (rc = S.get((void**)&dmax, sizeof(float))) ||
-        (rc = S.get((void**)&gpart, sizeof(GammaPart) * n_part)) ||
-        (rc = S.get((void**)&gout, sizeof(GammaPart))) || (!g && (rc = S.get((void**)&g, sizeof(float) * nv))))
-        return rc;
-    HIP_TRY(hipMemcpyAsync(doff, hoff.data(), sizeof(int4) * hoff.size(), hipMemcpyHostToDevice, s));
-    float D = p.dose_max;
-    if (!(D > 0.0f)) {
-        launch_grid_max(ref, (long)nv, fpart, n_part, dmax, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&D, dmax, sizeof(float), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (!(D > 0.0f)) return fail(FSPB_E_ARG, "gamma: the reference dose has no positive value");
-    }
-    GammaArgs a;
-    a.nx = nx;
-    a.ny = ny;
-    a.nz = nz;
-    const double dD = (double)p.dose_frac * D;
-    a.inv_dD2 = (float)(1.0 / (dD * dD));
-    a.cap2 = p.gamma_cap * p.gamma_cap;
-    a.n_off = (int)hoff.size();
-    launch_gamma(ref, eval, doff, a, g, s);
-    HIP_TRY(hipGetLastError());
-    GammaPart h{};
-    if (stats) {
-        launch_gamma_stats(g, ref, (long)nv, p.iso_frac * D, gpart, n_part, gout, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&h, gout, sizeof(GammaPart), hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));   // scratch goes back to the pool after this
-    if (stats) {
-        stats->gamma_max = h.max;
-        stats->n_iso = h.n;
-        stats->gamma_avg_iso = h.n ? h.sum / (double)h.n : 0.0;
-        stats->pass_rate_iso = h.n ? (double)h.pass / (double)h.n : 0.0;
-        stats->dose_max = D;
-    }
-    return FSPB_OK;
-}

@@ -88,26 +88,30 @@ def test_oracle_under_address_and_ub_sanitizers(oracle_asan, tmp_path, k):
 
 @pytest.fixture(scope="module")
 def abi_asan(tmp_path_factory):
-    """libfspb with its C ABI source (fspb_api.hip) compiled with the
-    host-side sanitizers (device code as usual), the other objects as built,
-    and the driver linked against it."""
+    """libfspb with its C ABI sources (fspb_api.hip, api_*.hip) compiled with
+    the host-side sanitizers (device code as usual), the kernels' objects as
+    built, and the driver linked against it."""
     from paper_1103_1164_amd import build as B
     hipcc = B.hipcc()
     clang = Path(hipcc).resolve().parent.parent / "llvm" / "bin" / "clang"
     if not clang.exists():
         pytest.skip("clang of the ROCm toolchain not found")
-    others = [B.BUILD / (Path(s).stem + ".o") for s in B.SOURCES if s != "fspb_api.hip"]
+    api = [s for s in B.SOURCES if s == "fspb_api.hip" or s.startswith("api_")]
+    others = [B.BUILD / (Path(s).stem + ".o") for s in B.SOURCES if s not in api]
     if not all(o.exists() for o in others):
         B.build()
     d = tmp_path_factory.mktemp("abi_asan")
-    obj = d / "fspb_api_san.o"
     inc = ["-I", str(B.INCLUDE), "-I", str(B.CSRC)]
-    cmd = [hipcc, *B.HIPCC_FLAGS, "-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *inc, "-c", str(B.CSRC / "fspb_api.hip"), "-o", str(obj)]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-4000:]
+    objs = []
+    for src in api:
+        obj = d / (Path(src).stem + "_san.o")
+        cmd = [hipcc, *B.HIPCC_FLAGS, "-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *inc, "-c", str(B.CSRC / src), "-o", str(obj)]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-4000:]
+        objs.append(obj)
     lib = d / "libfspb_san.so"
-    r = subprocess.run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *map(str, others), str(obj),
-                        "-o", str(lib)], capture_output=True, text=True)
+    r = subprocess.run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *map(str, others),
+                        *map(str, objs), "-o", str(lib)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
     exe = d / "abi_driver"
     r = subprocess.run([str(clang), "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
