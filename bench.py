@@ -22,6 +22,7 @@ batch, the surrogate, the exact-path comparison and the commissioning fit.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -278,16 +279,24 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    # Python's cyclic garbage collector stays off in the timed loops: a
+    # full collection (tens of ms with torch loaded) would otherwise land in
+    # one plan's step; the garbage is collected before each loop
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for k in range(a.steps):
         step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     ms_step = (t1 - t0) * 1e3 / a.steps
     fwd_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
 
     # one plan at a time: geometry + forward, synchronised after each plan
     lat = []
+    gc.collect()
+    gc.disable()
     for _ in range(max(10, a.steps)):
         torch.cuda.synchronize()
         t_a = time.perf_counter()
@@ -296,6 +305,7 @@ def main():
         g.close()
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t_a) * 1e3)
+    gc.enable()
     ms_plan = float(np.median(lat))
 
     # ---- side measurements (outside the timed region) ---------------------

@@ -17,6 +17,8 @@
 #include "wave.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace fspb {
 
@@ -326,12 +328,26 @@ __global__ void fill_i32(int* __restrict__ p, int n, int v) {
 namespace {
 // Resident workgroups of one adjoint kernel on the whole device: the
 // persistent grid (a multiple of 8, so that every XCD gets the same number).
+// The occupancy query is made once per kernel and LDS size.
 template <class K>
 int persistent_grid(K kernel, int threads, size_t lds, int n_cu) {
+    static std::mutex mu;
+    static std::map<size_t, int> per_cu_of;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = per_cu_of.find(lds);
+        if (it != per_cu_of.end()) {
+            per_cu = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) !=
+                    hipSuccess || per_cu < 1) {
+                (void)hipGetLastError();
+                per_cu = 1;
+            }
+            per_cu_of[lds] = per_cu;
+        }
+    }
     return 8 * ((per_cu * std::max(n_cu, 8) + 7) / 8);
 }
 }  // namespace

@@ -34,11 +34,16 @@ int check_table(const fspb_table1d& t, const char* name) {
     return FSPB_OK;
 }
 
+namespace {
+// Per device, looked up once (the property query is slow compared with
+// creating a plan): whether it is a gfx950 (0 unknown, 1 yes, -1 no) and its
+// compute units.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_arch_ok[kMaxDevices];
+std::atomic<int> g_cu_count[kMaxDevices];
+}  // namespace
+
 int check_device(int* dev) {
-    // the architecture of each device is looked up once (the property query
-    // is slow compared with creating a plan)
-    constexpr int kMaxDevices = 64;
-    static std::atomic<int> arch_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || n < 1) {
@@ -46,16 +51,23 @@ int check_device(int* dev) {
         return fail(FSPB_E_UNSUPPORTED, "no HIP device available");
     }
     HIP_TRY(hipGetDevice(dev));
-    const int v = (*dev >= 0 && *dev < kMaxDevices) ? arch_ok[*dev].load() : 0;
+    if (*dev < 0 || *dev >= kMaxDevices)
+        return fail(FSPB_E_UNSUPPORTED, "device %d: at most %d devices", *dev, kMaxDevices);
+    const int v = g_arch_ok[*dev].load();
     if (v == 1) return FSPB_OK;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, *dev));
     const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (*dev >= 0 && *dev < kMaxDevices) arch_ok[*dev].store(ok ? 1 : -1);
+    g_cu_count[*dev].store(prop.multiProcessorCount);
+    g_arch_ok[*dev].store(ok ? 1 : -1);
     if (!ok)
         return fail(FSPB_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev,
                     prop.gcnArchName);
     return FSPB_OK;
+}
+
+int device_cu_count(int dev) {
+    return dev >= 0 && dev < kMaxDevices ? g_cu_count[dev].load() : 0;
 }
 
 int check_same_device(int dev, const char* what) {

@@ -37,6 +37,8 @@ bool finite_pos(float v);
 int check_table(const fspb_table1d& t, const char* name);
 // The current device, which must be a gfx950 (FSPB_E_UNSUPPORTED otherwise).
 int check_device(int* dev);
+// Compute units of a device that passed check_device (cached; 0 if unknown).
+int device_cu_count(int dev);
 // The current device is dev (FSPB_E_STATE otherwise).
 int check_same_device(int dev, const char* what);
 

@@ -802,10 +802,7 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
     fspb_geometry* G = new (std::nothrow) fspb_geometry();
     if (!G) return fail(FSPB_E_NOMEM, "host allocation failed");
     G->device = dev;
-    if (hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        delete G;
-        return fail(FSPB_E_HIP, "hipDeviceGetAttribute failed");
-    }
+    G->n_cu = device_cu_count(dev);
     rc = create_impl(ct, n_beams, beams, tables, opts, (hipStream_t)stream, G);
     if (rc) {
         (void)hipStreamSynchronize((hipStream_t)stream);
