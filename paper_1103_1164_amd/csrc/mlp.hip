@@ -618,9 +618,10 @@ __global__ __launch_bounds__(256) void surrogate_samples_kernel(DoseArgs a,
 // surrogate_classify_kernel: one thread per row (rows beam-major).  A row
 // that is invalid or fails the guard's cheapest test (|rho_hat - rho| at the
 // voxel) gets its fallback record at once; the others are appended to `live`
-// with one atomic per wave.  Their order in the list is arbitrary and nothing
-// depends on it: a row's result depends on that row alone (the matrix-core
-// products sum each output element in a fixed order).
+// with one atomic per block of 2,048 rows, in row order within the block.
+// The blocks' order in the list is arbitrary and nothing depends on it: a
+// row's result depends on that row alone (the matrix-core products sum each
+// output element in a fixed order).
 constexpr int kClassRows = 8;   // rows per thread per block of the classify pass
 
 __global__ __launch_bounds__(256) void surrogate_classify_kernel(DoseArgs a,
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(256) void surrogate_classify_kernel(DoseArgs a,
 __global__ void zero_u32(unsigned* __restrict__ p) { *p = 0u; }
 
 // surrogate_infer_kernel: the listed rows, 16 per wave (one per lane row).
-// A workgroup of 4 waves keeps the BF16 weights in LDS; each lane gathers
+// A workgroup of 8 waves keeps the BF16 weights in LDS; each lane gathers
 // its own A fragments, so the inputs never touch memory.
 constexpr int kW1S = kK1 + 8;       // LDS row strides (elements), padded
 constexpr int kHS = kMlpHid + 8;
