@@ -14,11 +14,10 @@
 // sums are added in slab order, so the gradient is deterministic.
 #include "kernels.h"
 #include "pair.h"
+#include "persistent.h"
 #include "wave.h"
 
 #include <algorithm>
-#include <map>
-#include <mutex>
 
 namespace fspb {
 
@@ -325,32 +324,6 @@ __global__ void fill_i32(int* __restrict__ p, int n, int v) {
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = v;
 }
 
-namespace {
-// Resident workgroups of one adjoint kernel on the whole device: the
-// persistent grid (a multiple of 8, so that every XCD gets the same number).
-// The occupancy query is made once per kernel and LDS size.
-template <class K>
-int persistent_grid(K kernel, int threads, size_t lds, int n_cu) {
-    static std::mutex mu;
-    static std::map<size_t, int> per_cu_of;
-    int per_cu = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = per_cu_of.find(lds);
-        if (it != per_cu_of.end()) {
-            per_cu = it->second;
-        } else {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) !=
-                    hipSuccess || per_cu < 1) {
-                (void)hipGetLastError();
-                per_cu = 1;
-            }
-            per_cu_of[lds] = per_cu;
-        }
-    }
-    return 8 * ((per_cu * std::max(n_cu, 8) + 7) / 8);
-}
-}  // namespace
 
 void launch_adjoint(const DoseArgs& a, bool dc, int n_beamlets, const float* w, float* grad,
                     float* part, int* queue, int slab, int n_cu, hipStream_t s) {

@@ -15,6 +15,7 @@
 // (The transpose is in adjoint.hip.)
 #include "kernels.h"
 #include "pair.h"
+#include "persistent.h"
 #include "wave.h"
 
 #include <float.h>
@@ -253,26 +254,17 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
 // of the sorted items; wave w of its m-th workgroup takes positions
 // (m wpb + w) ipw .. + ipw - 1 of that concatenation (consecutive items: the
 // same beam, neighbouring slabs).  For each, the item's beam alone is
-// evaluated for its brick and written to that beam's plane.
-template <int DC, int BX, int BY, int BZ, bool LW>
-__global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose_forward_split(
+// evaluated for its brick and written to that beam's plane.  The water
+// table is read from global memory (1, 2 or 4 waves per workgroup).
+template <int DC, int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void dose_forward_split(
     DoseArgs a, const int* __restrict__ order, const int* __restrict__ chunk, int ipw,
     const float* __restrict__ fluence, float* __restrict__ planes, long stride) {
-    extern __shared__ float4 s_water[];
     const int wpb = blockDim.x / kWave;
     const int x = blockIdx.x & 7, m = blockIdx.x >> 3;
     int total = 0;
     for (int k = 0; k < kSplitSegments; ++k) total += chunk[x + 8 * k + 1] - chunk[x + 8 * k];
-    if (m * wpb * ipw >= total) return;   // the whole workgroup: nothing to stage
-    if (LW) {
-        const int n = a.P.dt_n;
-        const FSPB_GLOBAL float4* __restrict__ g = as_global(a.dtab);
-        for (int q = threadIdx.x; q < 3 * n; q += blockDim.x) {
-            const int plane = q / n, j = q - plane * n;
-            s_water[3 * j + plane] = g[q];
-        }
-        __syncthreads();
-    }
+    if (m * wpb * ipw >= total) return;
     const int nb = bricks_total<BX, BY, BZ>(a.P);
     const int v0 = (m * wpb + (int)(threadIdx.x / kWave)) * ipw;
     const int v1 = min(v0 + ipw, total);
@@ -289,16 +281,66 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
         }
         const int item = uniform(order[pos]);
         const int b = item / nb, brick = item - b * nb;
-        float* plane = planes + (long)b * stride;
-        if (LW)
-            brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, plane, nullptr,
-                                              WaterLds{(const FSPB_LDS float4*)s_water}, nullptr, b,
-                                              b + 1);
-        else
-            brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, plane, nullptr,
-                                              WaterGlobal{as_global(a.dtab), a.P.dt_n}, nullptr, b,
-                                              b + 1);
+        brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, planes + (long)b * stride, nullptr,
+                                          WaterGlobal{as_global(a.dtab), a.P.dt_n}, nullptr, b,
+                                          b + 1);
     }
+}
+
+// The per-beam schedule with the water table in LDS: persistent workgroups
+// of kLdsWaves waves stage the table once.  Each wave then takes positions of
+// its XCD's concatenation of segments from the XCD's counter (zeroed before
+// the launch), one item at a time, asking for the next position while the
+// current item runs, until the XCD's run is done.  A wave's items are those
+// of the static schedule, in the same order along the list, and each is
+// evaluated by the same brick pass, so the planes are bitwise the same.
+template <int DC, int BX, int BY, int BZ>
+__global__ __launch_bounds__(kLdsWaves * kWave) __attribute__((amdgpu_waves_per_eu(6))) void dose_forward_split_q(
+    DoseArgs a, const int* __restrict__ order, const int* __restrict__ chunk,
+    const float* __restrict__ fluence, float* __restrict__ planes, long stride,
+    int* __restrict__ queue) {
+    extern __shared__ float4 s_water[];
+    const int x = blockIdx.x & 7;
+    int total = 0;
+    for (int k = 0; k < kSplitSegments; ++k) total += chunk[x + 8 * k + 1] - chunk[x + 8 * k];
+    if (total == 0) return;   // the whole workgroup: nothing to stage
+    {
+        const int n = a.P.dt_n;
+        const FSPB_GLOBAL float4* __restrict__ g = as_global(a.dtab);
+        for (int q = threadIdx.x; q < 3 * n; q += blockDim.x) {
+            const int plane = q / n, j = q - plane * n;
+            s_water[3 * j + plane] = g[q];
+        }
+        __syncthreads();
+    }
+    const int nb = bricks_total<BX, BY, BZ>(a.P);
+    const int lane = threadIdx.x & (kWave - 1);
+    int* const q = queue + x * kSplitQueueInts;
+    int got = 0;
+    if (lane == 0) got = atomicAdd(q, 1);
+    int v = __builtin_amdgcn_readlane(got, 0);
+    while (v < total) {
+        if (lane == 0) got = atomicAdd(q, 1);   // the next position, early
+        int j = v, pos = 0;
+        for (int k = 0; k < kSplitSegments; ++k) {
+            const int s0 = chunk[x + 8 * k], len = chunk[x + 8 * k + 1] - s0;
+            if (j < len) {
+                pos = s0 + j;
+                break;
+            }
+            j -= len;
+        }
+        const int item = uniform(order[pos]);
+        const int b = item / nb, brick = item - b * nb;
+        brick_pass<DC, kDose, BX, BY, BZ>(a, brick, fluence, planes + (long)b * stride, nullptr,
+                                          WaterLds{(const FSPB_LDS float4*)s_water}, nullptr, b,
+                                          b + 1);
+        v = __builtin_amdgcn_readlane(got, 0);
+    }
+}
+
+__global__ void zero_queue(int* __restrict__ p, int n) {
+    for (int q = threadIdx.x; q < n; q += blockDim.x) p[q] = 0;
 }
 
 // dose[v] = sum over beams of planes[b][v] (plane b at planes + b stride,
@@ -848,7 +890,8 @@ void launch_split_schedule(const DoseArgs& a, TileCfg cfg, const SplitSched& sc,
 
 template <int DC>
 static void launch_split_dc(const DoseArgs& a, TileCfg cfg, const SplitSched& sc,
-                            const float* fluence, float* planes, long stride, hipStream_t s) {
+                            const float* fluence, float* planes, long stride, int n_cu,
+                            hipStream_t s) {
     const size_t water_bytes = sizeof(float4) * 3 * (size_t)a.P.dt_n;
     const bool lds = cfg.waves_per_block == kLdsWaves;
     const bool lw = lds && water_bytes <= (size_t)kLdsWaterMax;
@@ -857,16 +900,19 @@ static void launch_split_dc(const DoseArgs& a, TileCfg cfg, const SplitSched& sc
     const int ipw = kSplitItemsPerWave;
     const long per_xcd = (split_run_cap(n) + (long)wpb * ipw - 1) / ((long)wpb * ipw);
     dim3 grid((unsigned)(8 * per_xcd)), block(kWave * wpb);
+    if (lw) hipLaunchKernelGGL(zero_queue, dim3(1), dim3(128), 0, s, sc.queue, 8 * kSplitQueueInts);
 #define FSPB_SHAPE(ID, X, Y, Z)                                                                   \
     case ID:                                                                                      \
-        if (lw)                                                                                   \
-            hipLaunchKernelGGL((dose_forward_split<DC, X, Y, Z, true>), grid, block, water_bytes, \
-                               s, a, (const int*)sc.order, (const int*)sc.chunk, ipw, fluence,    \
-                               planes, stride);                                                   \
-        else                                                                                      \
-            hipLaunchKernelGGL((dose_forward_split<DC, X, Y, Z, false>), grid, block, 0, s, a,    \
+        if (lw) {                                                                                 \
+            auto k = dose_forward_split_q<DC, X, Y, Z>;                                           \
+            hipLaunchKernelGGL(k, dim3(persistent_grid(k, kLdsWaves * kWave, water_bytes, n_cu)), \
+                               block, water_bytes, s, a, (const int*)sc.order,                    \
+                               (const int*)sc.chunk, fluence, planes, stride, sc.queue);          \
+        } else {                                                                                  \
+            hipLaunchKernelGGL((dose_forward_split<DC, X, Y, Z>), grid, block, 0, s, a,           \
                                (const int*)sc.order, (const int*)sc.chunk, ipw, fluence, planes,  \
                                stride);                                                           \
+        }                                                                                         \
         break;
     switch (cfg.shape) {
         FSPB_SHAPE(0, 4, 4, 4)
@@ -878,15 +924,16 @@ static void launch_split_dc(const DoseArgs& a, TileCfg cfg, const SplitSched& sc
 }
 
 void launch_forward_split(const DoseArgs& a, bool dc, TileCfg cfg, const SplitSched& sc,
-                          const float* fluence, float* planes, float* dose, hipStream_t s) {
+                          const float* fluence, float* planes, float* dose, int n_cu,
+                          hipStream_t s) {
     const long nv = (long)a.P.nx * a.P.ny * a.P.nz;
     const long stride = (nv + 63) / 64 * 64;
     if (dc && a.P.w2_one)
-        launch_split_dc<kDcOneDrift>(a, cfg, sc, fluence, planes, stride, s);
+        launch_split_dc<kDcOneDrift>(a, cfg, sc, fluence, planes, stride, n_cu, s);
     else if (dc)
-        launch_split_dc<kDcTwoDrift>(a, cfg, sc, fluence, planes, stride, s);
+        launch_split_dc<kDcTwoDrift>(a, cfg, sc, fluence, planes, stride, n_cu, s);
     else
-        launch_split_dc<kPlain>(a, cfg, sc, fluence, planes, stride, s);
+        launch_split_dc<kPlain>(a, cfg, sc, fluence, planes, stride, n_cu, s);
     const int blocks = (int)std::min<long>((nv / 4 + 255) / 256 + 1, 8192);
     hipLaunchKernelGGL(sum_planes, dim3(blocks), dim3(256), 0, s, (const float*)planes,
                        a.P.n_beams, nv, stride, dose);

@@ -352,6 +352,7 @@ static int build_order(fspb_geometry* G, hipStream_t s) {
                 (rc = G->alloc((void**)&G->split.cost, sizeof(int) * max_items)) != FSPB_OK ||
                 (rc = G->alloc((void**)&G->split.key, sizeof(int) * max_items)) != FSPB_OK ||
                 (rc = G->alloc((void**)&G->split.chunk, sizeof(int) * (8 * kSplitSegments + 1))) != FSPB_OK ||
+                (rc = G->alloc((void**)&G->split.queue, sizeof(int) * 8 * kSplitQueueInts)) != FSPB_OK ||
                 (rc = G->alloc((void**)&G->split.hist_n, sizeof(int) * 64 * kSplitKeys)) != FSPB_OK ||
                 (rc = G->alloc((void**)&G->split.hist_w, sizeof(unsigned int) * 64 * kSplitKeys)) != FSPB_OK ||
                 (rc = G->alloc((void**)&G->planes, sizeof(float) * stride * G->P.n_beams)) != FSPB_OK)
@@ -821,7 +822,7 @@ static void enqueue_forward(fspb_geometry* g, const float* fluence, float* dose,
         launch_forward_siddon(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
     else if (g->tile.per_beam)
         launch_forward_split(g->args(), g->dc_enabled != 0, g->tile, g->split, fluence, g->planes,
-                             dose, s);
+                             dose, g->n_cu, s);
     else
         launch_forward(g->args(), g->dc_enabled != 0, g->tile, g->order, fluence, dose, s);
 }

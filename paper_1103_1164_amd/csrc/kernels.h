@@ -112,12 +112,17 @@ void launch_order_bricks(const int* cost, long n, int* order, hipStream_t s);
 // beam's partial dose to planes[beam][voxel]; sum_planes adds the planes in
 // beam order, which is the order the brick-major forward adds its beams in,
 // so both give bitwise the same dose for one brick shape.
+// With 8-wave workgroups (the water table in LDS) the workgroups are
+// persistent instead: each wave takes its XCD's next position from the XCD's
+// counter, item after item, until the XCD's run is done.
 constexpr int kSplitKeys = 4096;
 constexpr int kSplitItemsPerWave = 1;   // consecutive items a wavefront takes
 constexpr int kSplitSegments = 2;       // segments per XCD
+constexpr int kSplitQueueInts = 16;     // ints per XCD counter (64 bytes apart)
 struct SplitSched {
     int* order;     // [n_items] sorted items
     int* chunk;     // [8 kSplitSegments + 1] segment boundaries in order[]
+    int* queue;     // [8 kSplitQueueInts] the XCDs' position counters
     int* cost;      // [n_items] scratch: estimated work per item
     int* key;       // [n_items] scratch: sort key per item
     int* hist_n;    // [slices][kSplitKeys] scratch: items per key and slice
@@ -130,7 +135,8 @@ long split_run_cap(long n_items);
 int split_sort_slices(long n_items);
 void launch_split_schedule(const DoseArgs& a, TileCfg cfg, const SplitSched& sc, hipStream_t s);
 void launch_forward_split(const DoseArgs& a, bool dc, TileCfg cfg, const SplitSched& sc,
-                          const float* fluence, float* planes, float* dose, hipStream_t s);
+                          const float* fluence, float* planes, float* dose, int n_cu,
+                          hipStream_t s);
 // Per-plan fluence and dose pointers of a batch, passed by value as a kernel
 // argument (so a captured graph keeps them).
 constexpr int kMaxBatchPlans = 64;

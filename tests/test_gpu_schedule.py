@@ -2,7 +2,9 @@
 its dose is bitwise that of the brick-major schedule, on small ragged plans
 (every shape and workgroup size) and on config 2; against the oracle through
 the per-beam path; and the schedule follows set_tile, update_density and a
-plan too large for LDS-staged water tables."""
+plan too large for LDS-staged water tables.  With 8-wave workgroups the
+per-beam kernel is persistent (per-XCD item counters); idle XCDs and
+repeated launches are covered too."""
 import numpy as np
 import pytest
 import torch
@@ -58,6 +60,27 @@ def test_per_beam_oracle_parity_and_update():
     geo.close()
 
 
+def test_per_beam_persistent_idle_xcds_and_repeats():
+    """The 8-wave per-beam kernel takes its items from per-XCD counters:
+    with a single brick and beam most XCDs get no item, and the counters are
+    cleared before every launch, so repeated forwards agree bitwise."""
+    rng = np.random.default_rng(3)
+    for n, beams in (((4, 4, 4), [S.Beam(gantry=0.9, nbx=2, nby=2)]),
+                     ((9, 7, 5), [S.Beam(gantry=0.3, nbx=3, nby=2), S.Beam(gantry=3.5, nbx=2, nby=2)])):
+        rho = rng.uniform(0.5, 1.5, size=(n[2], n[1], n[0])).astype(np.float32)
+        plan = S.plan_small(n=n, density=rho, seed=9, beams=beams, name="tiny")
+        geo = geometry(plan, 1)
+        f = torch.as_tensor(plan.fluence, device="cuda")
+        geo.set_tile(0, 8)
+        ref = geo.forward(f).clone()
+        geo.set_schedule(1)
+        for _ in range(3):
+            assert torch.equal(geo.forward(f), ref), n
+        d_o, amb, _ = abi_oracle(plan).dose()
+        assert_dose_parity(ref.cpu().numpy(), d_o, amb, what=f"tiny plan {n}")
+        geo.close()
+
+
 def test_per_beam_config2_bitwise():
     from bench import C2_TILE
     plan = S.plan_c2()
@@ -67,6 +90,7 @@ def test_per_beam_config2_bitwise():
     geo.set_schedule(1)
     got = geo.forward(f).clone()
     assert torch.equal(ref, got)
+    assert torch.equal(geo.forward(f), ref)          # again: the counters start from zero
     # the plain model too
     geo.set_dc(False)
     got_p = geo.forward(f).clone()
