@@ -613,6 +613,19 @@ const char* fspb_error_string(int code);
 /* Description of the last error on the calling thread ("" if none). */
 const char* fspb_last_error(void);
 
+/* Diagnostic messages on stderr, one line each, prefixed "[fspb] ":
+ *   0  none (the default)
+ *   1  every error an entry point returns, with its description
+ *   2  also plan-level events: geometry creation and release, tile and
+ *      schedule choices, autotuner results, batch and network creation,
+ *      device memory taken from or returned to the HIP runtime
+ *   3  also every kernel launch an entry point queues (name, stream)
+ * The initial level is read once from the environment variable
+ * FSPB_LOG_LEVEL (an integer; anything else means 0).  Sets the level for
+ * the whole process and returns the previous one; a level outside 0..3 is
+ * clamped. */
+int fspb_set_log_level(int level);
+
 #ifdef __cplusplus
 }
 #endif

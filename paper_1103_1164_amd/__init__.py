@@ -22,7 +22,8 @@ import torch
 from . import _lib
 from ._lib import FspbError, check, load
 
-__all__ = ["Geometry", "Batch", "Mlp", "FspbDose", "FspbError", "gamma_index", "load"]
+__all__ = ["Geometry", "Batch", "Mlp", "FspbDose", "FspbError", "gamma_index", "load",
+           "set_log_level"]
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -64,6 +65,12 @@ def _marshal_tables(tables):
         _table_cache.pop(next(iter(_table_cache)))
     _table_cache[key] = (tabs, keep)      # keep: the objects whose ids form the key stay alive
     return tabs
+
+
+def set_log_level(level: int) -> int:
+    """Library diagnostics on stderr (0 none, 1 errors, 2 plan-level events,
+    3 queued operations; see fspb_set_log_level); returns the previous level."""
+    return int(load().fspb_set_log_level(int(level)))
 
 
 def drift_tables(tables):

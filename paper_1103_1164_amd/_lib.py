@@ -171,6 +171,7 @@ SIGNATURES = {
     "fspb_release_cached_memory": (C.c_int, []),
     "fspb_error_string": (C.c_char_p, [C.c_int]),
     "fspb_last_error": (C.c_char_p, []),
+    "fspb_set_log_level": (C.c_int, [C.c_int]),
 }
 
 _lib = None

@@ -196,6 +196,9 @@ int fspb_batch_create(int n, fspb_geometry* const* geoms, int shape, int waves_p
         hipStreamSynchronize(s) != hipSuccess)
         return bail(fail(FSPB_E_HIP, "batch_create: copy failed"));
     *out = B;
+    log_msg(2, "batch %p: %d plans, %zu work items over %d waves, shape %d, %d waves per workgroup, "
+               "%s policy", (void*)B, n, flat.size(), B->n_waves, shape, waves_per_block,
+            policy == FSPB_SCHEDULE_LATENCY ? "latency" : "throughput");
     return FSPB_OK;
 }
 
@@ -235,6 +238,7 @@ int fspb_batch_replay(fspb_batch* b, void* stream) {
     if (!b) return fail(FSPB_E_ARG, "batch_replay: NULL batch");
     if (!b->exec) return fail(FSPB_E_STATE, "batch_replay: nothing captured");
     HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    log_msg(3, "batch_replay: batch %p, stream %p", (void*)b, stream);
     return FSPB_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -15,6 +16,36 @@ namespace {
 thread_local std::string g_last_error;
 }  // namespace
 
+namespace {
+// -1: not yet read from the environment
+std::atomic<int> g_log_level{-1};
+
+int clamp_level(long v) { return v < 0 ? 0 : v > 3 ? 3 : (int)v; }
+}  // namespace
+
+int log_level() {
+    int v = g_log_level.load(std::memory_order_relaxed);
+    if (v >= 0) return v;
+    const char* e = getenv("FSPB_LOG_LEVEL");
+    char* end = nullptr;
+    const long x = e ? strtol(e, &end, 10) : 0;
+    int fresh = (e && end != e && *end == '\0') ? clamp_level(x) : 0;
+    int expected = -1;
+    // another thread (or fspb_set_log_level) may have set it meanwhile
+    if (!g_log_level.compare_exchange_strong(expected, fresh)) fresh = expected;
+    return fresh;
+}
+
+void log_msg(int level, const char* fmt, ...) {
+    if (log_level() < level) return;
+    char buf[640];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[fspb] %s\n", buf);
+}
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -22,6 +53,7 @@ int fail(int code, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    log_msg(1, "error %d (%s): %s", code, fspb_error_string(code), buf);
     return code;
 }
 
@@ -97,5 +129,11 @@ const char* fspb_error_string(int code) {
 }
 
 const char* fspb_last_error(void) { return fspb::last_error_text(); }
+
+int fspb_set_log_level(int level) {
+    const int prev = fspb::log_level();
+    fspb::g_log_level.store(level < 0 ? 0 : level > 3 ? 3 : level);
+    return prev;
+}
 
 }  // extern "C"

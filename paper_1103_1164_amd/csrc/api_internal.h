@@ -17,6 +17,10 @@ namespace fspb {
 // Records a printf-style message for fspb_last_error (per thread) and
 // returns code.
 int fail(int code, const char* fmt, ...);
+// Diagnostic line on stderr when the log level (fspb_set_log_level,
+// FSPB_LOG_LEVEL) is at least `level`.
+int log_level();
+void log_msg(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_last_error();
 
 #define HIP_TRY(expr)                                                                   \

@@ -143,6 +143,7 @@ int fspb_mlp_create(const float* params, fspb_mlp** out) {
         return rc;
     }
     *out = m;
+    log_msg(2, "network %p created on device %d", (void*)m, m->device);
     return FSPB_OK;
 }
 
@@ -316,6 +317,7 @@ int fspb_surrogate_infer(fspb_geometry* g, const fspb_mlp* m, const float* densi
                            (float4*)prm, g->surr_quad, g->surr_live, g->surr_count,
                            (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    log_msg(3, "surrogate_infer: geometry %p, network %p, stream %p", (void*)g, (const void*)m, stream);
     return FSPB_OK;
 }
 

@@ -117,8 +117,10 @@ int pool_alloc(int dev, void** p, size_t bytes, size_t* cls_out) {
         }
     }
     hipError_t e = hipMalloc(p, cls);
+    if (e == hipSuccess) log_msg(2, "pool: %zu bytes from the HIP runtime on device %d", cls, dev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        log_msg(2, "pool: hipMalloc of %zu bytes failed; returning cached blocks of device %d", cls, dev);
         // give the cached blocks back to the runtime and try once more
         std::vector<void*> drop;
         {
@@ -812,6 +814,10 @@ int fspb_create_geometry(const fspb_ct* ct, int n_beams, const fspb_beam* beams,
         return rc;
     }
     *out = G;
+    log_msg(2, "geometry %p: %dx%dx%d voxels, %d beams, %d beamlets, %s, %s tables, tile %d/%d waves, "
+               "%s schedule, device %d", (void*)G, G->P.nx, G->P.ny, G->P.nz, n_beams, G->n_beamlets,
+            G->dc_enabled ? "DC" : "plain", G->siddon ? "exact" : "uniform", G->tile.shape,
+            G->tile.waves_per_block, G->tile.per_beam ? "per-beam" : "brick-major", dev);
     clear_last_error();
     return FSPB_OK;
 }
@@ -833,6 +839,7 @@ int fspb_forward(fspb_geometry* g, const float* fluence, float* dose, void* stre
     if (rc) return rc;
     enqueue_forward(g, fluence, dose, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    log_msg(3, "forward: geometry %p, stream %p", (void*)g, stream);
     return FSPB_OK;
 }
 
@@ -863,6 +870,7 @@ int fspb_adjoint(fspb_geometry* g, const float* voxel_weight, float* grad, void*
     launch_adjoint(g->args(), g->dc_enabled != 0, g->n_beamlets, voxel_weight, grad, g->adj_part,
                    g->adj_queue, adj_slab_of(g), g->n_cu, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    log_msg(3, "adjoint: geometry %p, stream %p, %d-plane slabs", (void*)g, stream, adj_slab_of(g));
     return FSPB_OK;
 }
 
@@ -1081,6 +1089,7 @@ int fspb_beamlet(const fspb_geometry* g, int i, fspb_beamlet_info* info, float* 
 
 void fspb_destroy(fspb_geometry* g) {
     if (!g) return;
+    log_msg(2, "geometry %p released", (void*)g);
     // with the queued work on a few known streams, the buffers return to the
     // pool once the work on each is done, without waiting here; at most
     // kMaxPendingReleases handles wait so
@@ -1147,6 +1156,7 @@ int fspb_release_cached_memory(void) {
         pool().cached = 0;
     }
     for (void* p : drop) HIP_TRY(hipFree(p));
+    log_msg(2, "pool: %zu cached blocks returned to the HIP runtime", drop.size());
     return FSPB_OK;
 }
 
@@ -1269,6 +1279,9 @@ int fspb_autotune(fspb_geometry* g, const float* fluence, float* dose_scratch, i
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (n_results) *n_results = n;
+    log_msg(2, "autotune: geometry %p, %d configurations timed, best %s schedule, shape %d, "
+               "%d waves per workgroup, %.4f ms", (void*)g, n,
+            best.per_beam ? "per-beam" : "brick-major", best.shape, best.waves_per_block, best_ms);
     if ((rc = fspb_set_schedule(g, best.per_beam, stream)) != FSPB_OK) return rc;
     return fspb_set_tile(g, best.shape, best.waves_per_block, stream);
 }
@@ -1333,6 +1346,8 @@ int fspb_autotune_adjoint(fspb_geometry* g, const float* voxel_weight, float* gr
         return rc;
     }
     if (n_results) *n_results = n;
+    log_msg(2, "autotune_adjoint: geometry %p, %d thicknesses timed, best %d planes, %.4f ms",
+            (void*)g, n, best, best_ms);
     g->adj_slab = best;
     return FSPB_OK;
 }

@@ -158,3 +158,35 @@ def test_drift_table_mode_on_the_host(lib):
     assert drift_tables(dataclasses.replace(t, b1=z)) == (2, 0.0)                 # b1 = 0, b2 != 0
     L = lib.load()
     assert L.fspb_drift_tables(None, None) == lib.FSPB_E_ARG
+
+
+def test_log_level_from_environment_and_setter(tmp_path):
+    """FSPB_LOG_LEVEL sets the initial level (errors at 1 go to stderr with
+    their code), fspb_set_log_level changes it and clamps, and the default
+    is silent.  Runs in child processes so that the level is read fresh."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes as C\n"
+        "from paper_1103_1164_amd import _lib, set_log_level\n"
+        "L = _lib.load()\n"
+        "print('initial', set_log_level(2))\n"
+        "print('now', set_log_level(9))\n"
+        "print('clamped', set_log_level(0))\n"
+        "set_log_level(1)\n"
+        "rc = L.fspb_create_geometry(None, 0, None, None, None, None, None)\n"
+        "print('rc', rc)\n")
+    env_base = {k: v for k, v in __import__('os').environ.items() if k != "FSPB_LOG_LEVEL"}
+    for env_level, want_initial in ((None, 0), ("1", 1), ("3", 3), ("7", 3), ("x", 0)):
+        env = dict(env_base)
+        if env_level is not None:
+            env["FSPB_LOG_LEVEL"] = env_level
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        lines = dict(l.split() for l in r.stdout.splitlines())
+        assert int(lines["initial"]) == want_initial, (env_level, r.stdout)
+        assert int(lines["now"]) == 2 and int(lines["clamped"]) == 3
+        assert int(lines["rc"]) == -1
+        errs = [l for l in r.stderr.splitlines() if l.startswith("[fspb] ")]
+        assert len(errs) == 1 and "error -1" in errs[0] and "out is NULL" in errs[0], r.stderr
