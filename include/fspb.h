@@ -348,11 +348,14 @@ int fspb_get_tile(const fspb_geometry* g, int* shape, int* waves_per_block);
  *                 owns (allocated on first use: 4 n_beams n_vox bytes); a
  *                 second pass adds the planes in beam order.  The items are
  *                 sorted by beam and by depth along the beam's central axis,
- *                 and the sorted list is cut into 8 runs of about equal
- *                 estimated work, one per XCD, so each XCD sweeps one beam's
- *                 slabs and the depth-table lines its bricks share stay in
- *                 its L2.  For a given brick shape the dose is bitwise that
- *                 of per_beam = 0.
+ *                 and the sorted list is cut into 16 segments of about equal
+ *                 estimated work, XCD x running segments x and x + 8, so each
+ *                 XCD sweeps one beam's slabs at a time and the depth-table
+ *                 lines its bricks share stay in its L2.  With 8 waves per
+ *                 workgroup (water table in LDS) the workgroups are
+ *                 persistent and take their XCD's items one at a time from a
+ *                 counter the handle owns.  For a given brick shape the dose
+ *                 is bitwise that of per_beam = 0.
  * Builds the schedule on the stream (calls on other streams then wait for it
  * on the device).  FSPB_E_STATE with exact depth tables (FSPB_FLAG_SIDDON).
  * fspb_autotune covers both schedules. */
