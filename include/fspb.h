@@ -622,7 +622,8 @@ const char* fspb_last_error(void);
  *   2  also plan-level events: geometry creation and release, tile and
  *      schedule choices, autotuner results, batch and network creation,
  *      device memory taken from or returned to the HIP runtime
- *   3  also every kernel launch an entry point queues (name, stream)
+ *   3  also each forward, adjoint, surrogate inference and batch replay
+ *      queued (handle, stream)
  * The initial level is read once from the environment variable
  * FSPB_LOG_LEVEL (an integer; anything else means 0).  Sets the level for
  * the whole process and returns the previous one; a level outside 0..3 is

@@ -69,7 +69,8 @@ def _marshal_tables(tables):
 
 def set_log_level(level: int) -> int:
     """Library diagnostics on stderr (0 none, 1 errors, 2 plan-level events,
-    3 queued operations; see fspb_set_log_level); returns the previous level."""
+    3 the forwards, adjoints, inferences and replays queued; see
+    fspb_set_log_level); returns the previous level."""
     return int(load().fspb_set_log_level(int(level)))
 
 
