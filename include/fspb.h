@@ -545,7 +545,8 @@ int fspb_surrogate_samples(fspb_geometry* g, const float* density, const int* ro
 /* Inference for every (voxel, beam) row: prm (device, FP32
  * [n_beams][n_vox][8]) gets (u1x, u1y, u2x, u2y) * log2(e), w1, w2, the
  * fallback flag (1 or 0) and 0.  Needs a density-corrected geometry with
- * n_vox < 2^30 and n_vox * n_beams < 2^32 (else FSPB_E_ARG).  A first pass
+ * n_vox < 2^28 (the CT's 16-byte records below are addressed with 32-bit
+ * byte offsets) and n_vox * n_beams < 2^32 (else FSPB_E_ARG).  A first pass
  * writes the fallback rows (invalid, or |rho_hat - rho| at the voxel above
  * the guard's het_max) and lists the others; the gather and the network
  * then run on the listed rows only, reading the CT through 16-byte records

@@ -273,10 +273,11 @@ static int check_surrogate_geometry(const fspb_geometry* g, const char* what) {
     if (!g->dc_created)
         return fail(FSPB_E_STATE, "%s: the geometry was created without density correction", what);
     if (g->siddon) return fail(FSPB_E_STATE, "%s: not available with exact depth tables", what);
-    // row ids are 32-bit, the gathers address the CT with 32-bit byte offsets
-    // and index its rows with 24-bit multiplies
+    // row ids are 32-bit; the gathers address the CT's 16-byte records (and
+    // the CT) with 32-bit byte offsets, and index its rows with 24-bit
+    // multiplies
     const long long nv = (long long)g->P.nx * g->P.ny * g->P.nz;
-    if (nv >= (1LL << 30) || nv * g->n_beams >= (1LL << 32) ||
+    if (nv >= (1LL << 28) || nv * g->n_beams >= (1LL << 32) ||
         (long long)g->P.ny * g->P.nz >= (1LL << 24) || g->P.nx >= (1 << 24))
         return fail(FSPB_E_ARG, "%s: %lld voxels x %d beams exceed the surrogate's row range", what,
                     nv, g->n_beams);

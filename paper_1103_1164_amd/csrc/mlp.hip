@@ -444,7 +444,7 @@ __device__ __forceinline__ InvSpacing inv_spacing(const PlanConst& P) {
 
 // Trilinear density between voxel centres, indices clamped to the grid
 // (clamp-to-edge), at a point p relative to P0.  Corner offsets are 32-bit
-// (a plan's grid holds fewer than 2^30 voxels).
+// (the surrogate takes plans of fewer than 2^28 voxels, checked with the plan).
 __device__ __forceinline__ float density_at(const FSPB_GLOBAL float* __restrict__ rho,
                                             const PlanConst& P, InvSpacing is, float px, float py,
                                             float pz) {
@@ -490,7 +490,8 @@ __device__ __forceinline__ float density_at_quad(const FSPB_GLOBAL float4* __res
     const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
     const int x0 = min(max(ix, 0), P.nx - 1), y0 = min(max(iy, 0), P.ny - 1);
     const int z0 = min(max(iz, 0), P.nz - 1), z1 = min(max(iz + 1, 0), P.nz - 1);
-    // 24-bit multiplies: ny nz and nx are below 2^24 (checked with the plan)
+    // 24-bit multiplies: ny nz and nx are below 2^24, and the byte offsets
+    // 16 o fit 32 bits: fewer than 2^28 voxels (both checked with the plan)
     const unsigned o0 = __umul24(__umul24((unsigned)z0, (unsigned)P.ny) + (unsigned)y0, (unsigned)P.nx) + (unsigned)x0;
     const unsigned o1 = __umul24(__umul24((unsigned)z1, (unsigned)P.ny) + (unsigned)y0, (unsigned)P.nx) + (unsigned)x0;
     const float4 q0 = load_at(quad, 16u * o0), q1 = load_at(quad, 16u * o1);
