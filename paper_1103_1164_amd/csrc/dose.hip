@@ -3,8 +3,8 @@
 //
 // Forward: voxel-major.  A wavefront owns a 64-voxel brick (4x4x4 by default,
 // one voxel per lane); with 8-wave workgroups the commissioned water table is
-// first staged in LDS.  For each beam it projects its voxels onto the isocentre plane and
-// reduces the projections across the wave to a rectangle of beamlets whose
+// first staged in LDS.  For each beam it bounds the projection of the box of
+// its voxel centres onto the isocentre plane by a rectangle of beamlets whose
 // 5 cm ROI cylinder can reach the brick.  The rectangle is filtered 64
 // beamlets at a time (one per lane) against the brick's bounding sphere and
 // the survivors are compacted; the wave then walks them with wave-uniform
@@ -18,7 +18,6 @@
 #include "persistent.h"
 #include "wave.h"
 
-#include <float.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -110,28 +109,48 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
             s_w = prm[2 * ((long)b * n_vox + v) + 1];
             own = s_w.z == 0.0f;
         }
-        // rectangle of beamlets in the isocentre plane that can reach the brick
-        float vx = qx - B.src[0], vy = qy - B.src[1], vz = qz - B.src[2];
-        float z = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
-        float X = fmaf(vx, B.ex[0], fmaf(vy, B.ex[1], vz * B.ex[2]));
-        float Y = fmaf(vx, B.ey[0], fmaf(vy, B.ey[1], vz * B.ey[2]));
-        float s = B.sad / z;
-        float pa = X * s, pb = Y * s;
-        float amin = wave_min(valid ? pa : FLT_MAX), amax = wave_max(valid ? pa : -FLT_MAX);
-        float bmin = wave_min(valid ? pb : FLT_MAX), bmax = wave_max(valid ? pb : -FLT_MAX);
-        float zmin = wave_min(valid ? z : FLT_MAX);
-        // A voxel inside beamlet (n,m)'s ROI lies within R / cos(theta) of its
-        // axis in the plane normal to the central axis; scaled to the
-        // isocentre plane that is at most pad_scale / z.
-        float pad = B.pad_scale / zmin * 1.0001f + 1e-3f;
-        float fm0 = fmaxf((amin - pad - B.a0) / B.wx, -1.0f);
-        float fm1 = fminf((amax + pad - B.a0) / B.wx, (float)B.nbx);
-        float fn0 = fmaxf((bmin - pad - B.b0) / B.wy, -1.0f);
-        float fn1 = fminf((bmax + pad - B.b0) / B.wy, (float)B.nby);
-        const int m_lo = uniform(max((int)ceilf(fm0), 0));
-        const int m_hi = uniform(min((int)floorf(fm1), B.nbx - 1));
-        const int n_lo = uniform(max((int)ceilf(fn0), 0));
-        const int n_hi = uniform(min((int)floorf(fn1), B.nby - 1));
+        // Rectangle of beamlets whose ROI can reach the brick, from the box of
+        // its voxel centres.  In the beam's frame (offsets X, Y along ex, ey
+        // and Z along the central axis, measured from the source) the box
+        // spans centre +- (hX, hY, hZ), and a point projects onto the
+        // isocentre plane at SAD (X, Y) / Z.  While Z > 0 over the box, X / Z
+        // is largest at the largest X together with the smallest Z if that X
+        // is >= 0 (else the largest Z), and smallest likewise: the bounds
+        // hold for every voxel, with no reduction across the wave.  A voxel
+        // inside beamlet (n,m)'s ROI lies within R / cos(theta) of its axis
+        // in the plane normal to the central axis: scaled to the isocentre
+        // plane, at most pad_scale / Z.  A box that reaches Z <= 0 (a source
+        // next to the grid) takes the whole field.
+        const float vx = cqx - B.src[0], vy = cqy - B.src[1], vz = cqz - B.src[2];
+        const float Zc = fmaf(vx, B.cax[0], fmaf(vy, B.cax[1], vz * B.cax[2]));
+        const float Xc = fmaf(vx, B.ex[0], fmaf(vy, B.ex[1], vz * B.ex[2]));
+        const float Yc = fmaf(vx, B.ey[0], fmaf(vy, B.ey[1], vz * B.ey[2]));
+        const float hZ = fmaf(hx, fabsf(B.cax[0]), fmaf(hy, fabsf(B.cax[1]), hz * fabsf(B.cax[2])));
+        const float hX = fmaf(hx, fabsf(B.ex[0]), fmaf(hy, fabsf(B.ex[1]), hz * fabsf(B.ex[2])));
+        const float hY = fmaf(hx, fabsf(B.ey[0]), fmaf(hy, fabsf(B.ey[1]), hz * fabsf(B.ey[2])));
+        const float zlo = Zc - hZ;
+        int m_lo = 0, m_hi = B.nbx - 1, n_lo = 0, n_hi = B.nby - 1;
+        if (zlo > 0.0f) {
+            const float rlo = fast_rcp(zlo), rhi = fast_rcp(Zc + hZ);
+            const float slo = B.sad * rlo, shi = B.sad * rhi;
+            const float X1 = Xc + hX, X0 = Xc - hX, Y1 = Yc + hY, Y0 = Yc - hY;
+            const float amax = X1 * (X1 >= 0.0f ? slo : shi), amin = X0 * (X0 <= 0.0f ? slo : shi);
+            const float bmax = Y1 * (Y1 >= 0.0f ? slo : shi), bmin = Y0 * (Y0 <= 0.0f ? slo : shi);
+            const float pad = fmaf(B.pad_scale * rlo, 1.0001f, 1e-3f);
+            const float iwx = fast_rcp(B.wx), iwy = fast_rcp(B.wy);
+            const float fm0 = fmaxf((amin - pad - B.a0) * iwx, -1.0f);
+            const float fm1 = fminf((amax + pad - B.a0) * iwx, (float)B.nbx);
+            const float fn0 = fmaxf((bmin - pad - B.b0) * iwy, -1.0f);
+            const float fn1 = fminf((bmax + pad - B.b0) * iwy, (float)B.nby);
+            m_lo = max((int)ceilf(fm0), 0);
+            m_hi = min((int)floorf(fm1), B.nbx - 1);
+            n_lo = max((int)ceilf(fn0), 0);
+            n_hi = min((int)floorf(fn1), B.nby - 1);
+        }
+        m_lo = uniform(m_lo);
+        m_hi = uniform(m_hi);
+        n_lo = uniform(n_lo);
+        n_hi = uniform(n_hi);
         const int first = uniform(B.first), nbl_x = uniform(B.nbx);
         const int nm = m_hi - m_lo + 1;
         const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
