@@ -46,7 +46,7 @@ __device__ __forceinline__ int bricks_total(const PlanConst& P) {
     return bricks_x<BX, BY, BZ>(P) * bricks_y<BX, BY, BZ>(P) * ((P.nz + BZ - 1) / BZ);
 }
 
-template <int DC, int MODE, int BX, int BY, int BZ, class WT>
+template <int DC, int MODE, int BX, int BY, int BZ, bool PIPE = false, class WT>
 __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                                            const float* fluence_, float* dose_, int* out_int_,
                                            const WT& water, const float4* prm_ = nullptr,
@@ -183,6 +183,50 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
             const int dst = pass ? rank : ncand + (lane - rank);
             const int pk_ib = __builtin_amdgcn_ds_permute(dst << 2, ib);
             const int pk_f = __builtin_amdgcn_ds_permute(dst << 2, __float_as_int(fi));
+            if constexpr (PIPE && MODE == kDose && DC != kDcTwoDrift) {
+                // Software pipeline over the candidates (PIPE).  A pair's depth
+                // record (t_eq and W1 at its sample, from a table larger than
+                // an XCD's L2) and the A record indexed by that t_eq are two
+                // dependent loads; waiting on both in turn per candidate left
+                // the SIMDs idle.  So the depth record of candidate e+1 is
+                // read while candidate e is evaluated: its depth comes from
+                // its descriptor, fetched (scalar loads) two candidates
+                // ahead, and the record is read on every lane before the pair
+                // test, at an index kept inside the beamlet's rows
+                // (depth_record).  It is issued after candidate e's A load,
+                // so that the wait for the A record (loads complete in
+                // order) does not wait for it too.  The arithmetic is
+                // pair_dose's, so the dose is bitwise the same.  The
+                // brick-major and batch kernels with the water table in LDS
+                // take it.  With the water table in global memory its three
+                // loads follow the prefetch and so wait for it; the per-beam
+                // kernels, whose items each walk a short candidate list,
+                // measured slower with it; both keep the loop below.
+                BeamletDesc dA = bl[__builtin_amdgcn_readlane(pk_ib, 0)];
+                BeamletDesc dB = bl[__builtin_amdgcn_readlane(pk_ib, min(1, ncand - 1))];
+                float t_cur = pair_depth(dA, qx, qy, qz);
+                float4 rec = depth_record<DC>(t_cur, dA, P, tT, tTW);
+                for (int e = 0; e < ncand; ++e) {
+                    const BeamletDesc d = dA;
+                    const float fe = __int_as_float(__builtin_amdgcn_readlane(pk_f, e));
+                    float xp, yp;
+                    const bool act = pair_test_given_depth(d, P, qx, qy, qz, t_cur, xp, yp) & valid;
+                    // the record is consumed on every lane, so that no load into
+                    // its registers is pending when the next one is issued
+                    float f, teq, W1, fa, kmag, cd;
+                    float4 ae;
+                    pair_depth_lerp<DC>(t_cur, rec, P, f, teq);
+                    if (act) pair_first_half<DC>(t_cur, rec, f, teq, d, P, atab, W1, fa, ae, kmag, cd);
+                    t_cur = pair_depth(dB, qx, qy, qz);
+                    rec = depth_record<DC>(t_cur, dB, P, tT, tTW);
+                    dA = dB;
+                    dB = bl[__builtin_amdgcn_readlane(pk_ib, min(e + 2, ncand - 1))];
+                    if (act)
+                        accb = fmaf(fe, pair_second_half<DC>(xp, yp, kmag, cd, d, fac, P, water, W1, fa, ae),
+                                    accb);
+                }
+                continue;
+            }
             // software pipeline: the next candidate's descriptor is fetched
             // (scalar loads) while the current one is evaluated; the fluences
             // travel in a vector register (a scalar load per candidate would
@@ -261,8 +305,8 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
     if (slot >= bricks_total<BX, BY, BZ>(a.P)) return;
     const int brick = order ? order[slot] : slot;
     if (LW)
-        brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int,
-                                         WaterLds{(const FSPB_LDS float4*)s_water}, prm);
+        brick_pass<DC, MODE, BX, BY, BZ, true>(a, brick, fluence, dose, out_int,
+                                               WaterLds{(const FSPB_LDS float4*)s_water}, prm);
     else
         brick_pass<DC, MODE, BX, BY, BZ>(a, brick, fluence, dose, out_int,
                                          WaterGlobal{as_global(a.dtab), a.P.dt_n}, prm);
@@ -419,8 +463,8 @@ __global__ __launch_bounds__(LW ? kLdsWaves * kWave : 256, LW ? 8 : 1) void dose
     for (int it = it0; it < it1; ++it) {
         const int p = uniform(items[it].x), brick = uniform(items[it].y);
         if (LW)
-            brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p],
-                                              nullptr, WaterLds{(const FSPB_LDS float4*)s_water});
+            brick_pass<DC, kDose, BX, BY, BZ, true>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p],
+                                                    nullptr, WaterLds{(const FSPB_LDS float4*)s_water});
         else
             brick_pass<DC, kDose, BX, BY, BZ>(plans[p], brick, ptrs.fluence[p], ptrs.dose[p],
                                               nullptr,

@@ -157,12 +157,22 @@ __device__ __forceinline__ void voxel_q(const PlanConst& P, int i, int j, int k,
 // Depth below the entrance and lateral offsets of a voxel for one beamlet,
 // and the pair test of Algorithm A1 step 8 (inside the ROI cylinder, t >= 0).
 template <class BD>
-__device__ __forceinline__ bool pair_coords(const BD& d, const PlanConst& P, float qx, float qy,
-                                            float qz, float& t, float& xp, float& yp) {
-    t = fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
+__device__ __forceinline__ float pair_depth(const BD& d, float qx, float qy, float qz) {
+    return fmaf(qx, d.d[0], fmaf(qy, d.d[1], fmaf(qz, d.d[2], d.c_t)));
+}
+template <class BD>
+__device__ __forceinline__ bool pair_test_given_depth(const BD& d, const PlanConst& P, float qx,
+                                                      float qy, float qz, float t, float& xp,
+                                                      float& yp) {
     xp = fmaf(qx, d.ex[0], fmaf(qy, d.ex[1], fmaf(qz, d.ex[2], d.c_x)));
     yp = fmaf(qx, d.ey[0], fmaf(qy, d.ey[1], fmaf(qz, d.ey[2], d.c_y)));
     return (t >= 0.0f) & (fmaf(xp, xp, yp * yp) <= P.R2);
+}
+template <class BD>
+__device__ __forceinline__ bool pair_coords(const BD& d, const PlanConst& P, float qx, float qy,
+                                            float qz, float& t, float& xp, float& yp) {
+    t = pair_depth(d, qx, qy, qz);
+    return pair_test_given_depth(d, P, qx, qy, qz, t, xp, yp);
 }
 
 // SAD / |r_a| for a voxel at depth t below the beamlet's entrance.
@@ -171,9 +181,43 @@ __device__ __forceinline__ float magnification(float t, const BD& b) {
     return b.sad * fast_rcp(t + b.s_entry);
 }
 
+// The arithmetic of Eqs. 2-4 for one pair once its table records are read:
+// water parameters (u0, us, wv lerped by fd) at geometric depth t, weight
+// drifts W1, W2 at that depth (Section 2.2; W1 alone when DC == kDcOneDrift,
+// none for plain FSPB), the A record ae lerped by fa, magnified lateral
+// offsets (x, y) and inverse square isq.
+// fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
+template <int DC, class BD>
+__device__ __forceinline__ float pair_from_records(float x, float y, float isq, const BD& b,
+                                                   float4 fac, const PlanConst& P, float fd,
+                                                   float4 u0, float4 us, float4 wv, float W1,
+                                                   float W2, float fa, float4 ae) {
+    float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
+    float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
+    float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
+
+    if (DC) {
+        // Section 2.1: u1 by local density, u2 and weights by smoothed
+        // density, weights drift with the passing history W_c(t).
+        u1x *= fac.x;
+        u1y *= fac.x;
+        u2x *= fac.y;
+        u2y *= fac.y;
+        w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
+        w2 = fmaxf(fac.w * (DC == kDcOneDrift ? fmaf(P.w2c, W1, w2) : w2 + W2), 0.0f);
+    }
+
+    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
+
+    // Eq. 3 with the Eq. 4 profiles
+    float p1, p2;
+    profile_products(x, y, b.nx2, b.ny2, u1x, u1y, u2x, u2y, p1, p2);
+    float F = fmaf(w1, p1, w2 * p2);
+    return F * A * isq;
+}
+
 // Unit-fluence dose D_i(r) (Eq. 2) of beamlet b at a voxel with depth t >= 0
 // below the beamlet's entrance and lateral offsets (xp, yp) from its axis.
-// fac = (f_u1(rho), f_u2(rho_hat), f_w1(rho_hat), f_w2(rho_hat)) of the voxel.
 // k = SAD / |r_a| (see magnification()) is computed by the caller.
 template <int DC, class BD, class WT>
 __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k, const BD& b,
@@ -222,29 +266,71 @@ __device__ __forceinline__ float pair_dose(float t, float xp, float yp, float k,
     const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
     const float fa = fract(ca);
     const float4 ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
+    return pair_from_records<DC>(x, y, isq, b, fac, P, fd, u0, us, wv, W1, W2, fa, ae);
+}
 
-    float u1x = fmaf(fd, us.x, u0.x), u1y = fmaf(fd, us.y, u0.y);
-    float u2x = fmaf(fd, us.z, u0.z), u2y = fmaf(fd, us.w, u0.w);
-    float w1 = fmaf(fd, wv.z, wv.x), w2 = fmaf(fd, wv.w, wv.y);
+// The beamlet's depth record at depth t (Section 2.2's uniform samples):
+// (t_eq, its slope, W1, its slope) of sample j = floor(t / step), or
+// (t_eq, slope, 0, 0) for plain FSPB.  For t >= 0 (a pair) j is the sample
+// pair_dose reads; any other t gives an index inside the beamlet's own rows
+// (the sample clamped to [0, j_last]), so the record can be fetched before
+// the pair test has run.
+template <int DC, class BD>
+__device__ __forceinline__ float4 depth_record(float t, const BD& b, const PlanConst& P,
+                                               const FSPB_GLOBAL float2* __restrict__ tT,
+                                               const FSPB_GLOBAL float4* __restrict__ tTW) {
+    const int j = min((int)fmaxf(t * P.inv_d, 0.0f), b.j_last);
+    const unsigned ot = (unsigned)(b.tab_off + j);
+    if (DC) return load_at(tTW, 16u * ot);
+    const float2 te = load_at(tT, 8u * ot);
+    return make_float4(te.x, te.y, 0.0f, 0.0f);
+}
 
-    if (DC) {
-        // Section 2.1: u1 by local density, u2 and weights by smoothed
-        // density, weights drift with the passing history W_c(t).
-        u1x *= fac.x;
-        u1y *= fac.x;
-        u2x *= fac.y;
-        u2y *= fac.y;
-        w1 = fmaxf(fac.z * (w1 + W1), 0.0f);
-        w2 = fmaxf(fac.w * (DC == kDcOneDrift ? fmaf(P.w2c, W1, w2) : w2 + W2), 0.0f);
-    }
-
-    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
-
-    // Eq. 3 with the Eq. 4 profiles
-    float p1, p2;
-    profile_products(x, y, b.nx2, b.ny2, u1x, u1y, u2x, u2y, p1, p2);
-    float F = fmaf(w1, p1, w2 * p2);
-    return F * A * isq;
+// pair_dose for DC != kDcTwoDrift in parts around other work, given the
+// pair's depth record rec (see depth_record) fetched ahead of time.
+// pair_depth_lerp lerps t_eq from the record at depth t; it may run on
+// every lane, as the record is in bounds for any t.  pair_first_half then
+// lerps W1, issues the A-table load, the one load that waits on the record,
+// and forms the magnification k and the water-table coordinate cd, so that
+// t is not needed afterwards.  pair_second_half reads the water parameters and
+// completes the pair.  Together they compute what pair_dose computes,
+// operation for operation.
+template <int DC>
+__device__ __forceinline__ void pair_depth_lerp(float t, float4 rec, const PlanConst& P,
+                                                float& f, float& teq) {
+    static_assert(DC != kDcTwoDrift, "the second drift table has a record of its own");
+    f = fract(t * P.inv_d);
+    teq = fmaf(f, rec.y, rec.x);
+    // formed here, on every lane: the wait for the record then precedes any
+    // branch on the pair test, so no path leaves its load pending
+    asm volatile("" : "+v"(teq));
+}
+template <int DC, class BD>
+__device__ __forceinline__ void pair_first_half(float t, float4 rec, float f, float teq,
+                                                const BD& b, const PlanConst& P,
+                                                const FSPB_GLOBAL float4* __restrict__ atab,
+                                                float& W1, float& fa, float4& ae, float& k,
+                                                float& cd) {
+    W1 = DC ? fmaf(f, rec.w, rec.z) : 0.0f;
+    // formed here, not where it is used: the record's registers are then
+    // free for the next record, with no copies
+    asm volatile("" : "+v"(W1));
+    const float ca = clampf(fmaf(teq, P.at_inv, P.at_off), 0.0f, (float)(P.at_n - 1));
+    fa = fract(ca);
+    ae = load_at(atab, 16u * ((unsigned)ca + (unsigned)b.a_off));
+    k = magnification(t, b);
+    cd = clampf(fmaf(t, P.dt_inv, P.dt_off), 0.0f, (float)(P.dt_n - 1));
+}
+template <int DC, class BD, class WT>
+__device__ __forceinline__ float pair_second_half(float xp, float yp, float k, float cd,
+                                                  const BD& b, float4 fac, const PlanConst& P,
+                                                  const WT& water, float W1, float fa, float4 ae) {
+    float x = xp * k, y = yp * k;
+    float isq = k * k;
+    const float fd = fract(cd);
+    float4 u0, us, wv;
+    water.get((unsigned)cd, u0, us, wv);
+    return pair_from_records<DC>(x, y, isq, b, fac, P, fd, u0, us, wv, W1, 0.0f, fa, ae);
 }
 
 // pair_dose with the exact (Siddon) depth tables: the radiological depth and
