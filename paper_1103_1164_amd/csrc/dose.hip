@@ -183,7 +183,7 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
             const int dst = pass ? rank : ncand + (lane - rank);
             const int pk_ib = __builtin_amdgcn_ds_permute(dst << 2, ib);
             const int pk_f = __builtin_amdgcn_ds_permute(dst << 2, __float_as_int(fi));
-            if constexpr (PIPE && MODE == kDose && DC != kDcTwoDrift) {
+            if constexpr (PIPE && (MODE == kDose || MODE == kSurr) && DC != kDcTwoDrift) {
                 // Software pipeline over the candidates (PIPE).  A pair's depth
                 // record (t_eq and W1 at its sample, from a table larger than
                 // an XCD's L2) and the A record indexed by that t_eq are two
@@ -196,9 +196,9 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                 // (depth_record).  It is issued after candidate e's A load,
                 // so that the wait for the A record (loads complete in
                 // order) does not wait for it too.  The arithmetic is
-                // pair_dose's, so the dose is bitwise the same.  The
-                // brick-major and batch kernels with the water table in LDS
-                // take it.  With the water table in global memory its three
+                // pair_dose's (pair_dose_given's for the surrogate's own
+                // rows), so the dose is bitwise the same.  The brick-major
+                // and batch kernels with the water table in LDS take it.  With the water table in global memory its three
                 // loads follow the prefetch and so wait for it; the per-beam
                 // kernels, whose items each walk a short candidate list,
                 // measured slower with it; both keep the loop below.
@@ -221,7 +221,11 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
                     rec = depth_record<DC>(t_cur, dB, P, tT, tTW);
                     dA = dB;
                     dB = bl[__builtin_amdgcn_readlane(pk_ib, min(e + 2, ncand - 1))];
-                    if (act)
+                    // the surrogate's rows: the network's parameters where the
+                    // row is its own, else the corrected pair (as below)
+                    if (MODE == kSurr && (act & own))
+                        accb = fmaf(fe, pair_given_from_A(xp, yp, kmag, d, s_ul, s_w, fa, ae), accb);
+                    else if (act)
                         accb = fmaf(fe, pair_second_half<DC>(xp, yp, kmag, cd, d, fac, P, water, W1, fa, ae),
                                     accb);
                 }

@@ -388,7 +388,11 @@ __device__ __forceinline__ RowGeo row_geometry(const DoseArgs& a, const float* _
     const PlanConst& P = a.P;
     RowGeo r;
     r.v = v;
-    const int i = (int)(v % P.nx), j = (int)((v / P.nx) % P.ny), k = (int)(v / ((long)P.nx * P.ny));
+    // 32-bit index arithmetic: the surrogate's plans hold fewer than 2^28
+    // voxels (checked when a surrogate call is made)
+    const unsigned nx = (unsigned)P.nx, ny = (unsigned)P.ny;
+    const unsigned vv = (unsigned)v, row_yz = vv / nx;
+    const int i = (int)(vv - row_yz * nx), j = (int)(row_yz % ny), k = (int)(row_yz / ny);
     voxel_q(P, i, j, k, r.qx, r.qy, r.qz);
     const BeamDesc& B = a.beams[b];
     const float vx = r.qx - B.src[0], vy = r.qy - B.src[1], vz = r.qz - B.src[2];
@@ -651,8 +655,9 @@ __global__ __launch_bounds__(256) void surrogate_classify_kernel(DoseArgs a,
             const long row = blk * kBlock + q * 256 + tid;
             bool keep = false;
             if (row < n_rows) {
-                const int b = (int)(row / n_vox);
-                const long v = row - (long)b * n_vox;
+                // rows < 2^32 (checked when a surrogate call is made)
+                const unsigned b = (unsigned)row / (unsigned)n_vox;
+                const long v = (long)((unsigned)row - b * (unsigned)n_vox);
                 const RowGeo r = row_geometry(a, rho, v, b);
                 keep = r.valid && fabsf(rhohat[v] - r.rho_c) <= het_max;
                 if (!keep) {
@@ -777,8 +782,8 @@ void surrogate_infer_kernel(DoseArgs a,
         int b = 0;
         if (row_in) {
             const unsigned row = live[li];
-            b = (int)(row / (unsigned long)n_vox);
-            v = (long)row - (long)b * n_vox;
+            b = (int)(row / (unsigned)n_vox);
+            v = (long)(row - (unsigned)b * (unsigned)n_vox);
             r = row_geometry(a, rho, v, b);
         }
         // the listed rows passed the cheap test; the two planes next to the

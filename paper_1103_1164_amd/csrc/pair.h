@@ -441,4 +441,19 @@ __device__ __forceinline__ float pair_dose_given(float t, float xp, float yp, fl
     return F * A * isq;
 }
 
+// pair_dose_given's arithmetic once the A record ae (lerped by fa) is read:
+// the second part of the pipelined loop for a row the network serves (see
+// pair_first_half), operation for operation.
+template <class BD>
+__device__ __forceinline__ float pair_given_from_A(float xp, float yp, float k, const BD& b,
+                                                   float4 ul, float4 wv, float fa, float4 ae) {
+    float x = xp * k, y = yp * k;
+    float isq = k * k;
+    const float A = fmaf(fa, fmaf(b.th_frac, ae.w, ae.z), fmaf(b.th_frac, ae.y, ae.x));
+    float p1, p2;
+    profile_products(x, y, b.nx2, b.ny2, ul.x, ul.y, ul.z, ul.w, p1, p2);
+    float F = fmaf(wv.x, p1, wv.y * p2);
+    return F * A * isq;
+}
+
 }  // namespace fspb
