@@ -472,12 +472,17 @@ __device__ __forceinline__ float density_at(const FSPB_GLOBAL float* __restrict_
 
 // The CT as 16-byte records, one per voxel (x, y): (rho(x, y), rho(x+1, y),
 // rho(x, y+1), rho(x+1, y+1)) in plane z, neighbours clamped to the grid.
+// Also clears the inference's list length, which the classify pass after it
+// counts up.  32-bit indices: the surrogate's plans hold fewer than 2^28
+// voxels (checked when a surrogate call is made).
 __global__ __launch_bounds__(256) void make_quads(const float* __restrict__ rho, int nx, int ny,
-                                                  int nz, float4* __restrict__ quad) {
-    const long n = (long)nx * ny * nz;
-    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
-        const int x = (int)(v % nx), y = (int)((v / nx) % ny);
-        const long dx = x + 1 < nx ? 1 : 0, dy = y + 1 < ny ? nx : 0;
+                                                  int nz, float4* __restrict__ quad,
+                                                  unsigned* __restrict__ n_live) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_live = 0u;
+    const unsigned n = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    for (unsigned v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned row = v / (unsigned)nx, x = v - row * (unsigned)nx, y = row % (unsigned)ny;
+        const unsigned dx = x + 1 < (unsigned)nx ? 1u : 0u, dy = y + 1 < (unsigned)ny ? (unsigned)nx : 0u;
         quad[v] = make_float4(rho[v], rho[v + dx], rho[v + dy], rho[v + dx + dy]);
     }
 }
@@ -692,8 +697,6 @@ __global__ __launch_bounds__(256) void surrogate_classify_kernel(DoseArgs a,
         __syncthreads();   // s_bits, s_wsum and s_base are read before the next round writes them
     }
 }
-
-__global__ void zero_u32(unsigned* __restrict__ p) { *p = 0u; }
 
 // surrogate_infer_kernel: the listed rows, 16 per wave (one per lane row).
 // A workgroup of 8 waves keeps the BF16 weights in LDS; each lane gathers
@@ -942,9 +945,8 @@ void launch_surrogate_infer(const DoseArgs& a, const float* rho, const float* rh
                             unsigned* n_live, hipStream_t s) {
     const long n_vox = (long)a.P.nx * a.P.ny * a.P.nz;
     const long n_rows = n_vox * a.P.n_beams;
-    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, s, n_live);
     hipLaunchKernelGGL(make_quads, dim3((unsigned)std::min<long>((n_vox + 255) / 256, 16384)), dim3(256),
-                       0, s, rho, a.P.nx, a.P.ny, a.P.nz, quad);
+                       0, s, rho, a.P.nx, a.P.ny, a.P.nz, quad, n_live);
     const unsigned cgrid = (unsigned)std::min<long>((n_rows + 2047) / 2048, 4096);
     hipLaunchKernelGGL(surrogate_classify_kernel, dim3(cgrid), dim3(256), 0, s, a, rho, rhohat,
                        g.het_max, prm, live, n_live);

@@ -1,4 +1,4 @@
-// wave.h -- wavefront-level reductions, scans and the uniform-value helper
+// wave.h -- wavefront-level scans, lane sums and the uniform-value helper
 // shared by the dose and adjoint kernels (wave64, gfx950).
 #pragma once
 
@@ -6,18 +6,6 @@
 
 namespace fspb {
 
-__device__ __forceinline__ float wave_min(float x) {
-    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, kWave));
-    return x;
-}
-__device__ __forceinline__ float wave_max(float x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));
-    return x;
-}
-__device__ __forceinline__ float wave_sum(float x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
-}
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ __forceinline__ int wave_incl_scan_int(int x, int lane) {
