@@ -101,14 +101,6 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
     if (b_hi < 0) b_hi = P.n_beams;
     for (int b = b_lo; b < b_hi; ++b) {
         const FSPB_CONST BeamDesc& B = beams[b];
-        // surrogate row of this voxel and beam
-        float4 s_ul = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s_w = s_ul;
-        bool own = false;
-        if (MODE == kSurr && valid) {
-            s_ul = prm[2 * ((long)b * n_vox + v)];
-            s_w = prm[2 * ((long)b * n_vox + v) + 1];
-            own = s_w.z == 0.0f;
-        }
         // Rectangle of beamlets whose ROI can reach the brick, from the box of
         // its voxel centres.  In the beam's frame (offsets X, Y along ex, ey
         // and Z along the central axis, measured from the source) the box
@@ -154,6 +146,15 @@ __device__ __forceinline__ void brick_pass(const DoseArgs& a, const int brick,
         const int first = uniform(B.first), nbl_x = uniform(B.nbx);
         const int nm = m_hi - m_lo + 1;
         const int total = (nm > 0 && n_hi >= n_lo) ? nm * (n_hi - n_lo + 1) : 0;
+        // surrogate row of this voxel and beam, read only when some beamlet
+        // of the beam can reach the brick
+        float4 s_ul = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s_w = s_ul;
+        bool own = false;
+        if (MODE == kSurr && valid && total > 0) {
+            s_ul = prm[2 * ((long)b * n_vox + v)];
+            s_w = prm[2 * ((long)b * n_vox + v) + 1];
+            own = s_w.z == 0.0f;
+        }
         float accb = 0.0f;
         for (int base = 0; base < total; base += kWave) {
             // 64 candidates at once: one per lane, tested against the brick's
