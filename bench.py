@@ -742,9 +742,11 @@ def surrogate_c5(plan, geo, flu, pairs_fwd, n_plans, time_loop):
     rep = SU.evaluate(mlp, plan, geo, flu)
     prm = geo.surrogate_infer(mlp)
     dose = geo.forward_surrogate(flu, prm)
-    # each time the median of three loops of 10 launches: the first loop after
-    # the host-side calibration runs measurably slower for all three kernels
+    # each time the median of three loops of 10 launches after one untimed
+    # loop: the first loop after the host-side calibration runs measurably
+    # slower for all three kernels
     def steady(fn):
+        time_loop(fn, 10)
         return sorted(time_loop(fn, 10) for _ in range(3))[1]
     infer_ms = steady(lambda: geo.surrogate_infer(mlp, out=prm))
     fs_ms = steady(lambda: geo.forward_surrogate(flu, prm, out=dose))
